@@ -1,0 +1,61 @@
+"""Radial kernels and their Fourier transforms (oracle, FP64).  Test infrastructure only.
+
+* Gaussian: the paper lists exp(-c r^2) (Tab. "Global functions", section 2.2); the
+  workloads use the shape form exp(-r^2 / (2 s^2)), i.e. c = 1/(2 s^2).
+* Multiquadric: sqrt(r^2 + c^2) (same table).
+* Fourier transform convention: eq. (5), Phi_hat(w) = int Phi(x) exp(-i w.x) dx, inverse
+  with (2 pi)^-d (eq. 6).  Under this convention the Gaussian transforms to
+  (2 pi s^2)^(d/2) exp(-s^2 |w|^2 / 2).  (The paper's Fourier-transform table prints the
+  unitary (2 pi)^(-d/2) convention; eq. 5 is taken as the definition.)
+* The quadrature coefficient of eq. (28)/(29) is C(xi) = (2 pi)^-d Phi_hat(xi).
+
+Pins: ``tests/test_oracle_rbf.py`` checks the transform by numerical integration
+(scipy.integrate.quad) and the kernels at closed-form points; the multiquadric
+evaluator and its second derivative reproduce the left column of the paper's
+Table "RMS errors" (tests/golden/tab_rms_left.txt).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAUSSIAN = "gaussian"
+MULTIQUADRIC = "multiquadric"
+
+
+def phi_of_r2(kernel: str, r2, shape: float):
+    """Phi as a function of the squared distance r^2 (eq. 7: Phi(x - x_j) = phi(|x - x_j|))."""
+    r2 = np.asarray(r2, dtype=np.float64)
+    if kernel == GAUSSIAN:
+        return np.exp(-r2 / (2.0 * shape * shape))
+    if kernel == MULTIQUADRIC:
+        return np.sqrt(r2 + shape * shape)
+    raise ValueError(kernel)
+
+
+def phi0(kernel: str, shape: float) -> float:
+    """Phi(0): the diagonal entry of the RBF matrix (eq. 54, A^diagonal)."""
+    return 1.0 if kernel == GAUSSIAN else float(shape)
+
+
+def gaussian_ft(xi, s: float, d: int):
+    """Phi_hat(xi) of exp(-|x|^2/(2 s^2)) in the convention of eq. (5); xi has shape (..., d)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    k2 = (xi * xi).sum(-1)
+    return (2.0 * math.pi * s * s) ** (d / 2.0) * np.exp(-0.5 * s * s * k2)
+
+
+def gaussian_c1(xi, s: float):
+    """One-dimensional factor of C(xi) = (2 pi)^-d Phi_hat(xi) for the Gaussian.
+
+    The Gaussian transform is a product over coordinates, so C(xi) = prod_k c1(xi_k) with
+    c1(t) = (2 pi)^-1 * sqrt(2 pi) s exp(-s^2 t^2 / 2) = s / sqrt(2 pi) * exp(-s^2 t^2 / 2).
+    """
+    xi = np.asarray(xi, dtype=np.float64)
+    return s / math.sqrt(2.0 * math.pi) * np.exp(-0.5 * s * s * xi * xi)
+
+
+def gaussian_C(xi, s: float, d: int):
+    """C(xi) = (2 pi)^-d Phi_hat(xi) (eq. 28/29) for the Gaussian."""
+    return (2.0 * math.pi) ** (-d) * gaussian_ft(xi, s, d)
