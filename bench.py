@@ -1,0 +1,185 @@
+"""Benchmark: band-limited FMM matrix-vector product throughput (points/s) on one MI355X.
+
+Workload (default): 3-D, N = 2^20 points, half uniform in [0,1]^3 and half from 32
+Gaussian blobs (standard deviation 0.01), stored as float32; Gaussian kernel
+exp(-r^2/(2 * 0.03^2)); lambda ~ N(0,1).  The headline path computes in FP64 with
+tolerance 1e-6 (relative 2-norm error against the exact sum); the FP32 path (tol 1e-4)
+is reported beside it.  A step is one full product (permute, near field, aggregation,
+upward sum, coarse and leaf translation, disaggregation) with inputs resident in HBM.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VEC_TFLOPS = 78.6
+FP32_VEC_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def phase_model(info, dtype_bytes, n):
+    """Algorithmic work of one launch of each phase (documented in the design doc)."""
+    P = info["half_nodes"]
+    d = info["d"]
+    nl = info["nleaves"]
+    nc = info["ncells"]
+    cb = 2 * dtype_bytes
+    pairs = info["near_pairs"]
+    return {
+        # (kind, amount): flops for ALU-bound phases, bytes for memory-bound ones
+        "p2p": ("alu", pairs * (3 * d + 3)),
+        "p2m": ("alu", 8.0 * n * P),
+        "l2p": ("alu", 8.0 * n * P),
+        "m2m": ("hbm", (nl + nc) * P * cb),
+        "m2l_coarse": ("hbm", 2.0 * d * nc * P * cb),
+        "m2l_leaf": ("hbm", (info["nnear"] + 2.0 * nl) * P * cb),
+        "permute": ("hbm", n * (2 * dtype_bytes + 4)),
+    }
+
+
+def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max):
+    dev = torch.device("cuda:0")
+    x = torch.as_tensor(w.points, dtype=dtype, device=dev)
+    lam = torch.as_tensor(w.lam, dtype=dtype, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = FmmPlan(x, kernel=w.kernel, shape=w.shape, tol=tol, n_max=n_max)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    log(f"[bench] plan {dtype} tol={tol}: {plan_ms:.1f} ms, nodes={info['nodes']} leaves={info['nleaves']} "
+        f"lc={info['coarse_level']} r={info['coarse_radius']} near_pairs={info['near_pairs']}")
+    u = torch.empty_like(lam)
+    for _ in range(warmup):
+        plan.matvec(lam, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.matvec(lam, u)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    log(f"[bench] timed {steps} steps: {total * 1e3 / steps:.3f} ms/step")
+    # per-phase durations with HIP events on the plan's stream (separate pass)
+    plan.set_profiling(True)
+    for _ in range(steps):
+        plan.matvec(lam, u)
+    torch.cuda.synchronize()
+    ph = plan.phase_times()
+    plan.set_profiling(False)
+    calls = max(ph.pop("calls"), 1)
+    phase_ms = {k: v / calls for k, v in ph.items()}
+    out = u.double().cpu().numpy()
+    plan.close()
+    del x, lam, u
+    torch.cuda.empty_cache()
+    return {"ms_per_step": total * 1e3 / steps, "plan_ms": plan_ms, "info": info, "phase_ms": phase_ms,
+            "u": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--n-max", type=int, default=128)
+    ap.add_argument("--cpu-targets", type=int, default=2048)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1606_07652_amd import FmmPlan
+    from workloads import c2
+
+    w = c2("gaussian", n=args.n)
+    n = w.points.shape[0]
+    log(f"[bench] workload {w.name}: n={n}")
+    main_run = run_path(torch, FmmPlan, w, torch.float64, 1e-6, args.steps, args.warmup, args.n_max)
+    f32_run = None if args.no_fp32 else run_path(torch, FmmPlan, w, torch.float32, 1e-4, args.steps,
+                                                  args.warmup, args.n_max)
+
+    # dominant kernel of the headline path and its roofline
+    info = main_run["info"]
+    model = phase_model(info, 8, n)
+    ph = main_run["phase_ms"]
+    dom = max((k for k in ph if k in model), key=lambda k: ph[k])
+    kind, amount = model[dom]
+    secs = ph[dom] * 1e-3
+    if kind == "hbm":
+        roof = {"bound": "hbm", "achieved": amount / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": amount / secs / 1e12, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+
+    result = {
+        "metric": "RBF-FMM matvec points/s @ rel-L2<=1e-6",
+        "value": n / (main_run["ms_per_step"] * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3d_mixed_uniform_blobs_gaussian_s0.03", "n": n, "kernel": "gaussian",
+                   "shape": w.shape, "tol": 1e-6, "n_max": args.n_max, "nodes": info["nodes"],
+                   "leaves": info["nleaves"], "coarse_level": info["coarse_level"],
+                   "coarse_radius": info["coarse_radius"]},
+        "plan_ms": main_run["plan_ms"],
+        "phase_ms": main_run["phase_ms"],
+        "roofline": roof,
+    }
+    if f32_run is not None:
+        result["fp32_path"] = {"value": n / (f32_run["ms_per_step"] * 1e-3), "unit": "points/s", "tol": 1e-4,
+                               "ms_per_step": f32_run["ms_per_step"], "nodes": f32_run["info"]["nodes"],
+                               "phase_ms": f32_run["phase_ms"]}
+
+    if not args.no_cpu:
+        # cpu_baseline leg: the oracle's direct sum on a bounded sample of targets; the same
+        # sample gives the sampled rel-L2 of both GPU paths.
+        from oracle import direct
+        rng = np.random.default_rng(123)
+        idx = np.sort(rng.choice(n, args.cpu_targets, replace=False))
+        xs = w.points.astype(np.float64)
+        ls = w.lam.astype(np.float64)
+        log(f"[bench] cpu oracle on {args.cpu_targets} targets x {n} sources ...")
+        t0 = time.perf_counter()
+        ref = direct.direct_sum(xs, ls, "gaussian", w.shape, targets=xs[idx])
+        tcpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": args.cpu_targets / tcpu, "unit": "points/s", "cores": direct.threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{args.cpu_targets} seeded targets x all {n} sources, FP64 direct sum "
+                                            f"({tcpu:.1f} s; points/s = targets / time)"}
+        result["rel_l2_sampled"] = direct.rel_l2(main_run["u"][idx], ref)
+        if f32_run is not None:
+            result["fp32_path"]["rel_l2_sampled"] = direct.rel_l2(f32_run["u"][idx], ref)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

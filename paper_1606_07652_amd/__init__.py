@@ -1,0 +1,16 @@
+"""MI355X (gfx950) band-limited FMM for radial basis functions.
+
+The compute path is the HIP library ``lib/librbffmm.so`` (sources in ``csrc/``, C ABI in
+``include/rbf_fmm.h``); this package only marshals arguments.  Importing it does not
+load the library; the first plan does, and fails loudly if the library is missing.
+"""
+from ._lib import RbfError, load  # noqa: F401
+
+__all__ = ["FmmPlan", "RbfError", "load"]
+
+
+def __getattr__(name):
+    if name == "FmmPlan":
+        from .fmm import FmmPlan
+        return FmmPlan
+    raise AttributeError(name)

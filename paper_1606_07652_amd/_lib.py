@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/rbf_fmm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "librbffmm.so")
+
+RBF_OK, RBF_ENOCONV, RBF_EINVAL, RBF_EUNSUPPORTED, RBF_ENOMEM, RBF_EHIP, RBF_ESTATE = 0, 1, -1, -2, -3, -4, -5
+RBF_F32, RBF_F64 = 0, 1
+RBF_GAUSSIAN, RBF_MULTIQUADRIC = 0, 1
+RBF_PC_NONE, RBF_PC_BLOCK_JACOBI, RBF_PC_LEARNED = 0, 1, 2
+RBF_NPHASES = 7
+PHASES = ["permute", "p2p", "p2m", "m2m", "m2l_coarse", "m2l_leaf", "l2p"]
+
+
+class RbfOpts(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int), ("max_level", ctypes.c_int), ("min_level", ctypes.c_int),
+                ("coarse_level", ctypes.c_int), ("coarse_radius", ctypes.c_int), ("nodes", ctypes.c_int),
+                ("band", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+
+
+class RbfSolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("precond", ctypes.c_int),
+                ("zero_init", ctypes.c_int), ("fallback", ctypes.c_int), ("time_limit_s", ctypes.c_double),
+                ("reserved", ctypes.c_int * 8)]
+
+
+class RbfSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("fallback_used", ctypes.c_int), ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("history", ctypes.c_double * 256), ("nhistory", ctypes.c_int)]
+
+
+class RbfPlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int), ("dtype", ctypes.c_int), ("kernel", ctypes.c_int),
+                ("nleaves", ctypes.c_int), ("nlevels", ctypes.c_int), ("coarse_level", ctypes.c_int),
+                ("coarse_radius", ctypes.c_int), ("nodes", ctypes.c_int), ("bits", ctypes.c_int),
+                ("half_nodes", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nnear", ctypes.c_int64),
+                ("near_pairs", ctypes.c_int64), ("shape", ctypes.c_double), ("tol", ctypes.c_double),
+                ("band", ctypes.c_double), ("period", ctypes.c_double), ("rcut", ctypes.c_double),
+                ("rfar", ctypes.c_double), ("ext", ctypes.c_double), ("lo", ctypes.c_double * 5),
+                ("device_bytes", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "rbf_fmm_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.POINTER(RbfOpts), ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_fmm_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_direct_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_interp_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                        ctypes.POINTER(RbfSolveOpts), ctypes.POINTER(RbfSolveInfo)]),
+    "rbf_fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rbf_last_error": (ctypes.c_char_p, []),
+    "rbf_fmm_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfPlanInfo)]),
+    "rbf_fmm_tree_export": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 6),
+    "rbf_fmm_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "rbf_fmm_phase_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+class RbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def load():
+    """Load the in-tree library; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_1606_07652_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(code: int, allow=(RBF_OK,)) -> int:
+    if code not in allow:
+        raise RbfError(code, load().rbf_last_error().decode(errors="replace"))
+    return code

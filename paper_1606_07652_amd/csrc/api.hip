@@ -1,0 +1,262 @@
+// C ABI entry points: planning (parameter rule, tree, tables), products, info, timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace rbf {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int Arena::alloc(void **p, size_t nbytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, nbytes ? nbytes : 16);
+    if (e != hipSuccess) {
+        set_error("hipMalloc(%zu bytes) failed: %s", nbytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EHIP;
+    }
+    ptrs.push_back(q);
+    bytes += (int64_t)nbytes;
+    *p = q;
+    return RBF_OK;
+}
+
+void Arena::release() {
+    for (void *q : ptrs) (void)hipFree(q);
+    ptrs.clear();
+    bytes = 0;
+}
+
+int compute_bbox(rbf_plan *p, const void *points);
+
+namespace {
+
+// Band limit of the Gaussian: s sigma = t with erfc(t / sqrt 2) = tol / 4 (the largest
+// deviation of the band-limited Gaussian from the Gaussian is erfc(s sigma / sqrt 2), at r = 0).
+double band_t(double tol) {
+    double lo = 0.0, hi = 40.0, target = tol / 4.0;
+    for (int i = 0; i < 200; ++i) {
+        double mid = 0.5 * (lo + hi);
+        if (std::erfc(mid / std::sqrt(2.0)) > target) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
+int choose_params(rbf_plan *p, const rbf_opts *o) {
+    const double s = p->shape, tol = p->tol;
+    const int d = p->d;
+    p->sigma = (o && o->band > 0) ? o->band : band_t(tol) / s;
+    p->rcut = s * std::sqrt(2.0 * std::log(4.0 / tol) + 1.0);
+    const double margin = s * std::sqrt(2.0 * std::log(4.0 / tol));
+    int lmax = 0;
+    if (p->n > p->n_max) lmax = (int)std::floor(std::log((double)p->n / p->n_max) / std::log(std::pow(2.0, d)));
+    lmax = std::max(0, std::min(lmax, 18 / d));
+    int best_l = 0, best_r = 0;
+    double best_far = p->ext;
+    for (int l = 1; l <= lmax; ++l) {
+        double w = p->ext / std::ldexp(1.0, l);
+        int r = 1 + (int)std::floor(p->rcut / w);
+        double far = (r + 1) * w;
+        if (far >= p->ext) continue;
+        if (far < best_far) { best_l = l; best_r = r; best_far = far; }
+    }
+    if (o && o->coarse_level >= 0) {
+        best_l = o->coarse_level;
+        if (best_l > 18 / d) { set_error("coarse_level %d too deep for d=%d", best_l, d); return RBF_EINVAL; }
+        double w = p->ext / std::ldexp(1.0, best_l);
+        best_r = (o->coarse_radius >= 0) ? o->coarse_radius : (best_l == 0 ? 0 : 1 + (int)std::floor(p->rcut / w));
+        best_far = (best_l == 0) ? p->ext : std::min((best_r + 1) * w, p->ext);
+    }
+    p->lc = best_l;
+    p->r = best_r;
+    p->rfar = best_far;
+    double L = best_far + margin;
+    int mn = (int)std::ceil(p->sigma * L / M_PI) + 1;
+    if (mn % 2) ++mn;
+    mn = std::max(mn, 4);
+    if (o && o->nodes > 0) {
+        if (o->nodes % 2 || o->nodes < 4) { set_error("nodes must be even and >= 4 (got %d)", o->nodes); return RBF_EINVAL; }
+        mn = o->nodes;
+    }
+    const int hmax = (d == 5) ? 12 : 32;
+    if (mn / 2 > hmax) {
+        set_error("tolerance %g needs %d quadrature nodes per dimension; at most %d are supported for d=%d",
+                  tol, mn, 2 * hmax, d);
+        return RBF_EUNSUPPORTED;
+    }
+    p->mn = mn;
+    p->H = mn / 2;
+    p->R = 1;
+    for (int k = 0; k < d - 1; ++k) p->R *= mn;
+    p->P = p->R * p->H;
+    p->L = 2.0 * M_PI / (2.0 * p->sigma / (mn - 1));
+    p->min_level = std::max(p->lc, (o && o->min_level > 0) ? o->min_level : 0);
+    return RBF_OK;
+}
+
+int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
+              const rbf_opts *opts, void *stream, rbf_plan **out) {
+    if (!points || !out) { set_error("rbf_fmm_plan: null pointer argument"); return RBF_EINVAL; }
+    if (n < 1 || n > (int64_t)0x3fffffff) { set_error("rbf_fmm_plan: n=%lld out of range", (long long)n); return RBF_EINVAL; }
+    if (d < 1 || d > kMaxDim) { set_error("rbf_fmm_plan: d=%d out of range [1,5]", d); return RBF_EINVAL; }
+    if (d != 2 && d != 3 && d != 5) { set_error("rbf_fmm_plan: d=%d is not compiled (2, 3, 5 are)", d); return RBF_EUNSUPPORTED; }
+    if (dtype != RBF_F32 && dtype != RBF_F64) { set_error("rbf_fmm_plan: bad dtype %d", dtype); return RBF_EINVAL; }
+    if (kernel != RBF_GAUSSIAN && kernel != RBF_MULTIQUADRIC) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
+    if (!(shape > 0) || !std::isfinite(shape)) { set_error("rbf_fmm_plan: shape must be positive"); return RBF_EINVAL; }
+    if (!(tol > 0 && tol < 1)) { set_error("rbf_fmm_plan: tol must lie in (0, 1)"); return RBF_EINVAL; }
+    if (kernel == RBF_MULTIQUADRIC) {
+        set_error("rbf_fmm_plan: the multiquadric far field is not available in this build");
+        return RBF_EUNSUPPORTED;
+    }
+    rbf_plan *p = new (std::nothrow) rbf_plan();
+    if (!p) { set_error("rbf_fmm_plan: out of host memory"); return RBF_ENOMEM; }
+    p->n = n; p->d = d; p->dtype = dtype; p->kernel = kernel; p->shape = shape; p->tol = tol;
+    p->stream = (hipStream_t)stream;
+    p->n_max = (opts && opts->n_max > 0) ? opts->n_max : 128;
+    p->max_level = (opts && opts->max_level > 0) ? opts->max_level : 64;
+    int rc = compute_bbox(p, points);
+    if (rc == RBF_OK) rc = choose_params(p, opts);
+    if (rc == RBF_OK) rc = build_tree(p, points);
+    const size_t tsz = dtype == RBF_F32 ? 4 : 8, csz = 2 * tsz;
+    if (rc == RBF_OK) {
+        double need = (double)csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) + 2.0 * tsz * n;
+        if (need > 200e9) {
+            set_error("rbf_fmm_plan: expansions need %.1f GB (nodes=%d, leaves=%d); raise tol or n_max", need / 1e9,
+                      p->mn, p->nleaves);
+            rc = RBF_ENOMEM;
+        }
+    }
+    Arena &ar = p->arena;
+    if (rc == RBF_OK) rc = ar.alloc(&p->lam_s, tsz * n);
+    if (rc == RBF_OK) rc = ar.alloc(&p->u_s, tsz * n);
+    if (rc == RBF_OK) rc = ar.alloc(&p->W, csz * p->P * p->nleaves);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->P * p->nleaves);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Wc, csz * p->P * p->ncells);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Lc, csz * p->P * p->ncells);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Tmp, csz * p->P * p->ncells);
+    if (rc == RBF_OK) rc = ar.alloc((void **)&p->xi, sizeof(double) * p->mn);
+    if (rc == RBF_OK) rc = ar.alloc((void **)&p->wc1, sizeof(double) * p->mn);
+    if (rc == RBF_OK) {
+        // tensor trapezoid nodes on [-sigma, sigma] and w_k C1(xi_k) for the Gaussian:
+        // C(xi) = (2 pi)^-d Phi_hat(xi) = prod_k s/sqrt(2 pi) exp(-s^2 xi_k^2 / 2).
+        std::vector<double> xi(p->mn), wc(p->mn);
+        const double h = 2.0 * p->sigma / (p->mn - 1);
+        for (int m = 0; m < p->mn; ++m) {
+            xi[m] = -p->sigma + h * m;
+            double w = (m == 0 || m == p->mn - 1) ? 0.5 * h : h;
+            wc[m] = w * shape / std::sqrt(2.0 * M_PI) * std::exp(-0.5 * shape * shape * xi[m] * xi[m]);
+        }
+        hipError_t e1 = hipMemcpy(p->xi, xi.data(), sizeof(double) * p->mn, hipMemcpyHostToDevice);
+        hipError_t e2 = hipMemcpy(p->wc1, wc.data(), sizeof(double) * p->mn, hipMemcpyHostToDevice);
+        if (e1 != hipSuccess || e2 != hipSuccess) { set_error("rbf_fmm_plan: table upload failed"); rc = RBF_EHIP; }
+    }
+    if (rc == RBF_OK) {
+        for (int k = 0; k < 2 * RBF_NPHASES && rc == RBF_OK; ++k)
+            if (hipEventCreate(&p->ev[k]) != hipSuccess) { set_error("hipEventCreate failed"); rc = RBF_EHIP; }
+    }
+    if (rc != RBF_OK) {
+        for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
+        p->arena.release();
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return RBF_OK;
+}
+
+}  // namespace
+}  // namespace rbf
+
+using namespace rbf;
+
+extern "C" {
+
+const char *rbf_last_error(void) { return g_err; }
+
+int rbf_fmm_plan(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
+                 const rbf_opts *opts, void *stream, rbf_plan **out) {
+    g_err[0] = 0;
+    return plan_impl(points, n, d, dtype, kernel, shape, tol, opts, stream, out);
+}
+
+int rbf_fmm_matvec(rbf_plan *plan, const void *lambda, void *u) {
+    if (!plan || !lambda || !u) { set_error("rbf_fmm_matvec: null argument"); return RBF_EINVAL; }
+    if (lambda == u) { set_error("rbf_fmm_matvec: lambda and u must not alias"); return RBF_EINVAL; }
+    return launch_matvec(plan, lambda, u);
+}
+
+int rbf_direct_matvec(rbf_plan *plan, const void *lambda, void *u) {
+    if (!plan || !lambda || !u) { set_error("rbf_direct_matvec: null argument"); return RBF_EINVAL; }
+    if (lambda == u) { set_error("rbf_direct_matvec: lambda and u must not alias"); return RBF_EINVAL; }
+    return launch_direct(plan, lambda, u);
+}
+
+int rbf_fmm_destroy(rbf_plan *plan) {
+    if (!plan) return RBF_OK;
+    (void)hipStreamSynchronize(plan->stream);
+    for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (plan->ev[k]) (void)hipEventDestroy(plan->ev[k]);
+    plan->solver_arena.release();
+    plan->arena.release();
+    delete plan;
+    return RBF_OK;
+}
+
+int rbf_fmm_plan_info(const rbf_plan *p, rbf_plan_info *info) {
+    if (!p || !info) { set_error("rbf_fmm_plan_info: null argument"); return RBF_EINVAL; }
+    std::memset(info, 0, sizeof(*info));
+    info->n = p->n; info->d = p->d; info->dtype = p->dtype; info->kernel = p->kernel;
+    info->nleaves = p->nleaves; info->nlevels = p->nlevels; info->coarse_level = p->lc;
+    info->coarse_radius = p->r; info->nodes = p->mn; info->bits = p->B;
+    info->half_nodes = p->P; info->ncells = p->ncells; info->nnear = p->nnear;
+    info->near_pairs = p->near_pairs;
+    info->shape = p->shape; info->tol = p->tol; info->band = p->sigma; info->period = p->L;
+    info->rcut = p->rcut; info->rfar = p->rfar; info->ext = p->ext;
+    for (int k = 0; k < kMaxDim; ++k) info->lo[k] = p->lo[k];
+    info->device_bytes = p->arena.bytes + p->solver_arena.bytes;
+    return RBF_OK;
+}
+
+int rbf_fmm_tree_export(const rbf_plan *p, int64_t *perm, int32_t *leaf_begin, int32_t *leaf_level,
+                        uint64_t *leaf_prefix, int32_t *near_ptr, int32_t *near_idx) {
+    if (!p) { set_error("rbf_fmm_tree_export: null plan"); return RBF_EINVAL; }
+    RBF_HIP(hipStreamSynchronize(p->stream));
+    if (perm) {
+        std::vector<int> tmp(p->n);
+        RBF_HIP(hipMemcpy(tmp.data(), p->perm, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < p->n; ++i) perm[i] = tmp[i];
+    }
+    if (leaf_begin) RBF_HIP(hipMemcpy(leaf_begin, p->leaf_begin, sizeof(int) * (p->nleaves + 1), hipMemcpyDeviceToHost));
+    if (leaf_level) RBF_HIP(hipMemcpy(leaf_level, p->leaf_level, sizeof(int) * p->nleaves, hipMemcpyDeviceToHost));
+    if (leaf_prefix) RBF_HIP(hipMemcpy(leaf_prefix, p->leaf_prefix, sizeof(uint64_t) * p->nleaves, hipMemcpyDeviceToHost));
+    if (near_ptr) RBF_HIP(hipMemcpy(near_ptr, p->near_ptr, sizeof(int) * (p->nleaves + 1), hipMemcpyDeviceToHost));
+    if (near_idx && p->nnear) RBF_HIP(hipMemcpy(near_idx, p->near_idx, sizeof(int) * p->nnear, hipMemcpyDeviceToHost));
+    return RBF_OK;
+}
+
+int rbf_fmm_set_profiling(rbf_plan *p, int on) {
+    if (!p) { set_error("rbf_fmm_set_profiling: null plan"); return RBF_EINVAL; }
+    p->profiling = on ? 1 : 0;
+    for (int k = 0; k < RBF_NPHASES; ++k) p->phase_ms[k] = 0;
+    p->prof_calls = 0;
+    return RBF_OK;
+}
+
+int rbf_fmm_phase_times(const rbf_plan *p, double *ms, int64_t *calls) {
+    if (!p || !ms) { set_error("rbf_fmm_phase_times: null argument"); return RBF_EINVAL; }
+    for (int k = 0; k < RBF_NPHASES; ++k) ms[k] = p->phase_ms[k];
+    if (calls) *calls = p->prof_calls;
+    return RBF_OK;
+}
+
+}  // extern "C"

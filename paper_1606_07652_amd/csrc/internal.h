@@ -1,0 +1,122 @@
+// Internal declarations shared by the translation units of librbffmm.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "rbf_fmm.h"
+
+namespace rbf {
+
+void set_error(const char *fmt, ...);
+
+#define RBF_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e__ = (call);                                                        \
+        if (e__ != hipSuccess) {                                                        \
+            ::rbf::set_error("%s: %s (%s:%d)", #call, hipGetErrorString(e__), __FILE__, \
+                             __LINE__);                                                 \
+            return RBF_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+#define RBF_TRY(expr)                  \
+    do {                               \
+        int rc__ = (expr);             \
+        if (rc__ != RBF_OK) return rc__; \
+    } while (0)
+
+constexpr int kMaxDim = 5;
+constexpr int kWave = 64;
+
+// Device-wide exclusive prefix sum of n int32 values; out may alias in.  If total is
+// non-null the sum of all inputs is written to *total (host) -- this synchronises.
+int exclusive_scan_i32(const int *in, int *out, int n, int *total, hipStream_t s);
+
+// Ordered set of device allocations owned by a plan.
+struct Arena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    int alloc(void **p, size_t nbytes);
+    void release();
+};
+
+// Spread consecutive workgroups over the 8 XCDs in contiguous chunks: dispatch
+// round-robins workgroup ids over XCDs, so id % 8 names the XCD; giving each XCD a
+// contiguous range of work keeps neighbouring boxes (which share sources) in one L2.
+__device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
+    const int nx = 8;
+    int per = nblocks / nx, rem = nblocks % nx;
+    int x = bid % nx, k = bid / nx;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+template <class T> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+
+}  // namespace rbf
+
+struct rbf_plan {
+    int64_t n = 0;
+    int d = 0, dtype = 0, kernel = 0;
+    double shape = 0, tol = 0;
+    hipStream_t stream = nullptr;
+
+    // tree and quadrature parameters
+    int n_max = 0, max_level = 0, min_level = 0, lc = 0, r = 0, mn = 0, H = 0, B = 0;
+    int64_t R = 0, P = 0;   // rows (nodes^(d-1)) and half-grid length R*H per expansion
+    double sigma = 0, L = 0, rcut = 0, rfar = 0, ext = 0;
+    double lo[rbf::kMaxDim] = {0, 0, 0, 0, 0};
+    int nleaves = 0, nlevels = 0;
+    int64_t ncells = 0, nnear = 0, near_pairs = 0, nranges = 0;
+
+    // device arrays (owned by arena)
+    rbf::Arena arena;
+    uint64_t *keys = nullptr;        // sorted Morton keys [n]
+    int *perm = nullptr;             // input index of sorted point i [n]
+    void *xs = nullptr;              // sorted coordinates, SoA [d][n]
+    int *leaf_begin = nullptr;       // [nleaves + 1]
+    int *leaf_level = nullptr;       // [nleaves]
+    uint64_t *leaf_prefix = nullptr; // [nleaves]
+    int *leaf_cell = nullptr;        // coarse cell (Morton index at lc) [nleaves]
+    int *near_ptr = nullptr;         // [nleaves + 1]
+    int *near_idx = nullptr;         // [nnear]
+    int *src_ptr = nullptr;          // merged source point ranges of the near field [nleaves + 1]
+    int2 *src_rng = nullptr;         // [nranges] (begin, end)
+    int *cell_leaf_begin = nullptr;  // [ncells + 1]
+    double *xi = nullptr;            // quadrature nodes [mn]
+    double *wc1 = nullptr;           // w_k C1(xi_k) per dimension (separable kernels) [mn]
+    void *lam_s = nullptr;           // sorted coefficients [n]
+    void *u_s = nullptr;             // sorted near-field result [n]
+    void *W = nullptr;               // leaf expansions [nleaves][P] complex
+    void *Lx = nullptr;              // leaf local expansions [nleaves][P] complex
+    void *Wc = nullptr;              // coarse expansions [ncells][P]
+    void *Lc = nullptr;              // coarse local expansions [ncells][P]
+    void *Tmp = nullptr;             // stencil pass buffer [ncells][P]
+
+    // profiling
+    int profiling = 0;
+    hipEvent_t ev[2 * RBF_NPHASES] = {};
+    double phase_ms[RBF_NPHASES] = {0};
+    int64_t prof_calls = 0;
+
+    // solver workspace (allocated on first solve)
+    rbf::Arena solver_arena;
+    int solver_m = 0;
+    double *V = nullptr;             // Arnoldi basis [(m+1)][n] FP64
+    double *Z = nullptr;             // preconditioned basis [m][n] FP64 (flexible GMRES)
+    double *sv = nullptr;            // small device vectors (dots, norms)
+    void *tvec = nullptr;            // plan-dtype vectors for products [3][n]
+
+    // learned preconditioner (optional)
+    void *pc = nullptr;
+};
+
+namespace rbf {
+int build_tree(rbf_plan *p, const void *points);
+int build_near_lists(rbf_plan *p);
+int launch_matvec(rbf_plan *p, const void *lambda, void *u);
+int launch_direct(rbf_plan *p, const void *lambda, void *u);
+}  // namespace rbf

@@ -1,0 +1,315 @@
+// Restarted (flexible) GMRES for A lambda = f with the fast product (section 1 names
+// GMRES as the Krylov method the fast product serves; the paper gives no details).
+//
+// Arnoldi vectors live on the device in FP64.  Orthogonalisation is classical
+// Gram-Schmidt applied twice (CGS2: two block projections, each a multi-dot and a
+// multi-axpy), which is mathematically the modified Gram-Schmidt of the CPU reference
+// and differs from it only in rounding.  Reductions use a fixed blocking, so a solve is
+// deterministic.  The (m+1) x m Hessenberg system, its Givens rotations and the
+// restart logic run on the host; each inner step moves j+2 doubles to the host.
+// Convergence is judged on the true residual ||f - A lambda|| / ||f||, recomputed with
+// a fresh product at every restart.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace rbf {
+int pc_apply(rbf_plan *p, const double *v, double *z);   // learned / block preconditioners (pc.hip)
+int pc_ready(rbf_plan *p, int kind);
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kDotBlocks = 512;
+
+template <class A, class B>
+__global__ void k_cvt(const A *__restrict__ in, B *__restrict__ out, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) out[i] = (B)in[i];
+}
+
+__global__ void k_sub(const double *__restrict__ f, const double *__restrict__ ax, double *__restrict__ r, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) r[i] = f[i] - ax[i];
+}
+
+__global__ void k_scale(const double *__restrict__ src, double a, double *__restrict__ dst, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) dst[i] = a * src[i];
+}
+
+__device__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// part[b * k + v] = sum over block b's slice of V[v] . w
+__global__ void __launch_bounds__(kThreads) k_multidot(const double *__restrict__ V, int64_t n, int k,
+                                                       const double *__restrict__ w, double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    for (int v = 0; v < k; ++v) {
+        const double *vv = V + (int64_t)v * n;
+        double s = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) s += vv[i] * w[i];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) part[blockIdx.x * k + v] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_parts(const double *__restrict__ part, int nb, int k,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) s += part[b * k + v];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[v] = s;
+}
+
+// w -= sum_v h[v] V[v]   (sign = -1)   or   x += sum_v h[v] V[v]   (sign = +1)
+__global__ void k_multiaxpy(double *__restrict__ w, const double *__restrict__ V, int64_t n, int k,
+                            const double *__restrict__ h, double sign) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int v = 0; v < k; ++v) s += h[v] * V[(int64_t)v * n + i];
+    w[i] += sign * s;
+}
+
+__global__ void k_isfinite(const double *__restrict__ v, int64_t n, int *flag) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n && !isfinite(v[i])) *flag = 1;
+}
+
+struct Solver {
+    rbf_plan *p;
+    int64_t n;
+    unsigned nb;
+    double *part = nullptr, *hdev = nullptr, *xd = nullptr, *fd = nullptr, *rd = nullptr, *wd = nullptr;
+    int *flag = nullptr;
+
+    int product(const double *x64, double *y64) {
+        // y = A x through the plan's dtype
+        hipStream_t s = p->stream;
+        if (p->dtype == RBF_F64) {
+            RBF_TRY(launch_matvec(p, x64, y64));
+            return RBF_OK;
+        }
+        float *tin = (float *)p->tvec, *tout = tin + n;
+        k_cvt<double, float><<<nb, kThreads, 0, s>>>(x64, tin, n);
+        RBF_HIP(hipGetLastError());
+        RBF_TRY(launch_matvec(p, tin, tout));
+        k_cvt<float, double><<<nb, kThreads, 0, s>>>(tout, y64, n);
+        RBF_HIP(hipGetLastError());
+        return RBF_OK;
+    }
+
+    int dots(const double *V, int k, const double *w, double *host_out) {
+        hipStream_t s = p->stream;
+        k_multidot<<<kDotBlocks, kThreads, 0, s>>>(V, n, k, w, part);
+        RBF_HIP(hipGetLastError());
+        k_reduce_parts<<<k, kThreads, 0, s>>>(part, kDotBlocks, k, hdev);
+        RBF_HIP(hipGetLastError());
+        if (host_out) {
+            RBF_HIP(hipMemcpyAsync(host_out, hdev, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+            RBF_HIP(hipStreamSynchronize(s));
+        }
+        return RBF_OK;
+    }
+
+    int norm(const double *w, double *out) {
+        double v = 0;
+        RBF_TRY(dots(w, 1, w, &v));
+        *out = std::sqrt(v);
+        return RBF_OK;
+    }
+};
+
+int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_solve_opts *o,
+               rbf_solve_info *info) {
+    auto t_start = std::chrono::steady_clock::now();
+    const int64_t n = p->n;
+    const int m = (o && o->restart > 0) ? o->restart : 50;
+    const int maxit = (o && o->max_iters > 0) ? o->max_iters : 1000;
+    int pck = o ? o->precond : RBF_PC_NONE;
+    const bool fallback = o ? (o->fallback != 0) : true;
+    const double tlim = (o && o->time_limit_s > 0) ? o->time_limit_s : 0.0;
+    if (pck != RBF_PC_NONE) {
+        int rc = pc_ready(p, pck);
+        if (rc != RBF_OK) return rc;
+    }
+    hipStream_t s = p->stream;
+    if (p->solver_m < m) {
+        p->solver_arena.release();
+        Arena &ar = p->solver_arena;
+        RBF_TRY(ar.alloc((void **)&p->V, sizeof(double) * (size_t)(m + 1) * n));
+        RBF_TRY(ar.alloc((void **)&p->Z, sizeof(double) * (size_t)m * n));
+        RBF_TRY(ar.alloc((void **)&p->sv, sizeof(double) * ((size_t)kDotBlocks * (m + 2) + 4 * (m + 2) + 8)));
+        RBF_TRY(ar.alloc(&p->tvec, sizeof(double) * (size_t)7 * n));
+        p->solver_m = m;
+    }
+    Solver S;
+    S.p = p;
+    S.n = n;
+    S.nb = (unsigned)((n + kThreads - 1) / kThreads);
+    S.part = p->sv;
+    S.hdev = p->sv + (size_t)kDotBlocks * (m + 2);
+    S.flag = (int *)(S.hdev + 2 * (m + 2));
+    double *base = (double *)p->tvec;
+    S.xd = base + 2 * n;  // tvec[0..2n) holds the float in/out pair for F32 plans
+    S.fd = base + 3 * n;
+    S.rd = base + 4 * n;
+    S.wd = base + 5 * n;
+    const unsigned nb = S.nb;
+    // x0 and f in FP64
+    if (p->dtype == RBF_F64) {
+        RBF_HIP(hipMemcpyAsync(S.fd, f, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (o && o->zero_init) RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
+        else RBF_HIP(hipMemcpyAsync(S.xd, lambda, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+        k_cvt<float, double><<<nb, kThreads, 0, s>>>((const float *)f, S.fd, n);
+        if (o && o->zero_init) RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
+        else k_cvt<float, double><<<nb, kThreads, 0, s>>>((const float *)lambda, S.xd, n);
+        RBF_HIP(hipGetLastError());
+    }
+    double bnorm = 0;
+    RBF_TRY(S.norm(S.fd, &bnorm));
+    rbf_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(m + 2), hh2(m + 2);
+    int its = 0, restarts = 0;
+    bool use_pc = pck != RBF_PC_NONE;
+    double best = INFINITY;
+    double last_cycle_res = INFINITY;
+    if (bnorm == 0.0) {
+        RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
+    }
+    while (bnorm > 0.0) {
+        RBF_TRY(S.product(S.xd, S.wd));
+        k_sub<<<nb, kThreads, 0, s>>>(S.fd, S.wd, S.rd, n);
+        RBF_HIP(hipGetLastError());
+        double beta = 0;
+        RBF_TRY(S.norm(S.rd, &beta));
+        double rel = beta / bnorm;
+        if (inf.nhistory < 256) inf.history[inf.nhistory++] = rel;
+        best = std::min(best, rel);
+        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (!(rel > rtol) || its >= maxit || (tlim > 0 && el >= tlim) || !std::isfinite(rel)) break;
+        if (use_pc && fallback && restarts > 0 && rel > 0.999 * last_cycle_res) {
+            use_pc = false;   // preconditioned cycle did not reduce the true residual
+            inf.fallback_used = 1;
+        }
+        last_cycle_res = rel;
+        k_scale<<<nb, kThreads, 0, s>>>(S.rd, 1.0 / beta, p->V, n);
+        RBF_HIP(hipGetLastError());
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool pc_failed = false;
+        for (int j = 0; j < m; ++j) {
+            double *vj = p->V + (size_t)j * n;
+            double *zj = use_pc ? p->Z + (size_t)j * n : vj;
+            if (use_pc) {
+                RBF_TRY(pc_apply(p, vj, zj));
+                int hf = 0;
+                RBF_HIP(hipMemsetAsync(S.flag, 0, sizeof(int), s));
+                k_isfinite<<<nb, kThreads, 0, s>>>(zj, n, S.flag);
+                RBF_HIP(hipMemcpyAsync(&hf, S.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+                RBF_HIP(hipStreamSynchronize(s));
+                if (hf) { pc_failed = true; break; }
+            }
+            RBF_TRY(S.product(zj, S.wd));
+            // CGS2
+            RBF_TRY(S.dots(p->V, j + 1, S.wd, hh.data()));
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, n, j + 1, S.hdev, -1.0);
+            RBF_HIP(hipGetLastError());
+            RBF_TRY(S.dots(p->V, j + 1, S.wd, hh2.data()));
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, n, j + 1, S.hdev, -1.0);
+            RBF_HIP(hipGetLastError());
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh2[i];
+            double hn = 0;
+            RBF_TRY(S.norm(S.wd, &hn));
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            double a = H[(size_t)j * m + j], den = std::hypot(a, hn);
+            if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; } else { cs[j] = a / den; sn[j] = hn / den; }
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++its;
+            k = j + 1;
+            if (!std::isfinite(hn)) { pc_failed = use_pc; k = j; break; }
+            if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || its >= maxit) break;
+            k_scale<<<nb, kThreads, 0, s>>>(S.wd, 1.0 / hn, p->V + (size_t)(j + 1) * n, n);
+            RBF_HIP(hipGetLastError());
+        }
+        if (pc_failed) {
+            if (!fallback) { set_error("rbf_interp_solve: preconditioner produced non-finite values"); return RBF_EINVAL; }
+            use_pc = false;
+            inf.fallback_used = 1;
+            ++restarts;
+            continue;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        if (k > 0) {
+            RBF_HIP(hipMemcpyAsync(S.hdev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.xd, use_pc ? p->Z : p->V, n, k, S.hdev, 1.0);
+            RBF_HIP(hipGetLastError());
+            RBF_HIP(hipStreamSynchronize(s));
+        }
+        ++restarts;
+    }
+    // write the solution in the plan's dtype
+    if (p->dtype == RBF_F64) RBF_HIP(hipMemcpyAsync(lambda, S.xd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else {
+        k_cvt<double, float><<<nb, kThreads, 0, s>>>(S.xd, (float *)lambda, n);
+        RBF_HIP(hipGetLastError());
+    }
+    RBF_HIP(hipStreamSynchronize(s));
+    inf.iters = its;
+    inf.restarts = restarts;
+    inf.true_res = (inf.nhistory > 0) ? inf.history[inf.nhistory - 1] : 0.0;
+    if (bnorm == 0.0) inf.true_res = 0.0;
+    inf.converged = inf.true_res <= rtol;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (info) *info = inf;
+    return inf.converged ? RBF_OK : RBF_ENOCONV;
+}
+
+}  // namespace
+}  // namespace rbf
+
+extern "C" int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, double rtol, const rbf_solve_opts *opts,
+                                rbf_solve_info *info) {
+    using namespace rbf;
+    if (!plan || !f || !lambda) { set_error("rbf_interp_solve: null argument"); return RBF_EINVAL; }
+    if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve: rtol must lie in (0, 1)"); return RBF_EINVAL; }
+    if (opts && (opts->restart < 0 || opts->restart > 1000)) { set_error("rbf_interp_solve: restart out of range"); return RBF_EINVAL; }
+    if (opts && (opts->precond < RBF_PC_NONE || opts->precond > RBF_PC_LEARNED)) {
+        set_error("rbf_interp_solve: unknown preconditioner %d", opts->precond);
+        return RBF_EINVAL;
+    }
+    return solve_impl(plan, f, lambda, rtol, opts, info);
+}

@@ -1,0 +1,137 @@
+"""Python binding of librbffmm: plans, products, solves.
+
+Torch provides device memory and the stream; every step of the computation runs in the
+HIP library (include/rbf_fmm.h).  Nothing here computes a result.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_KERNELS = {"gaussian": L.RBF_GAUSSIAN, "multiquadric": L.RBF_MULTIQUADRIC}
+_PCS = {"none": L.RBF_PC_NONE, "block_jacobi": L.RBF_PC_BLOCK_JACOBI, "learned": L.RBF_PC_LEARNED}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.RBF_F32
+    if t.dtype == torch.float64:
+        return L.RBF_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the HIP device")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class FmmPlan:
+    """Plan for u = A lambda with A_ij = Phi(x_i - x_j) on a fixed point set."""
+
+    def __init__(self, points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05,
+                 tol: float = 1e-6, n_max: int = 0, max_level: int = 0, min_level: int = 0,
+                 coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0, band: float = 0.0,
+                 stream: Optional[torch.cuda.Stream] = None):
+        lib = L.load()
+        if points.dim() != 2:
+            raise ValueError("points must be (n, d)")
+        self.n, self.d = points.shape
+        self.dtype = points.dtype
+        self.device = points.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
+        opts = L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band)
+        h = ctypes.c_void_p()
+        L.check(lib.rbf_fmm_plan(_ptr(points), self.n, self.d, _dtype_code(points), _KERNELS[kernel],
+                                 float(shape), float(tol), ctypes.byref(opts),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.kernel, self.shape, self.tol = kernel, shape, tol
+
+    # -- products --------------------------------------------------------------------
+    def _check_vec(self, v: torch.Tensor):
+        if v.shape != (self.n,) or v.dtype != self.dtype or v.device != self.device:
+            raise ValueError(f"expected a ({self.n},) {self.dtype} vector on {self.device}")
+
+    def matvec(self, lam: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_vec(lam)
+        if out is None:
+            out = torch.empty_like(lam)
+        self._check_vec(out)
+        L.check(L.load().rbf_fmm_matvec(self._h, _ptr(lam), _ptr(out)))
+        return out
+
+    def direct(self, lam: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_vec(lam)
+        if out is None:
+            out = torch.empty_like(lam)
+        self._check_vec(out)
+        L.check(L.load().rbf_direct_matvec(self._h, _ptr(lam), _ptr(out)))
+        return out
+
+    def solve(self, f: torch.Tensor, lam: Optional[torch.Tensor] = None, rtol: float = 1e-8,
+              restart: int = 50, max_iters: int = 1000, precond: str = "none", fallback: bool = True,
+              time_limit_s: float = 0.0):
+        self._check_vec(f)
+        zero = lam is None
+        if lam is None:
+            lam = torch.zeros_like(f)
+        self._check_vec(lam)
+        o = L.RbfSolveOpts(restart, max_iters, _PCS[precond], 1 if zero else 0, 1 if fallback else 0,
+                           float(time_limit_s))
+        info = L.RbfSolveInfo()
+        code = L.load().rbf_interp_solve(self._h, _ptr(f), _ptr(lam), float(rtol), ctypes.byref(o),
+                                         ctypes.byref(info))
+        L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
+        return lam, {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
+                     "fallback_used": bool(info.fallback_used), "true_res": info.true_res,
+                     "seconds": info.seconds, "history": list(info.history[:info.nhistory])}
+
+    # -- introspection ---------------------------------------------------------------
+    def info(self) -> dict:
+        inf = L.RbfPlanInfo()
+        L.check(L.load().rbf_fmm_plan_info(self._h, ctypes.byref(inf)))
+        out = {name: getattr(inf, name) for name, _ in L.RbfPlanInfo._fields_}
+        out["lo"] = list(inf.lo)[: self.d]
+        return out
+
+    def tree(self) -> dict:
+        inf = self.info()
+        nl, nn = inf["nleaves"], inf["nnear"]
+        perm = np.empty(self.n, np.int64)
+        lb = np.empty(nl + 1, np.int32)
+        lv = np.empty(nl, np.int32)
+        pf = np.empty(nl, np.uint64)
+        npt = np.empty(nl + 1, np.int32)
+        nid = np.empty(max(nn, 1), np.int32)
+        L.check(L.load().rbf_fmm_tree_export(self._h, perm.ctypes.data, lb.ctypes.data, lv.ctypes.data,
+                                             pf.ctypes.data, npt.ctypes.data, nid.ctypes.data))
+        return {"perm": perm, "leaf_begin": lb, "leaf_level": lv, "leaf_prefix": pf, "near_ptr": npt,
+                "near_idx": nid[:nn]}
+
+    def set_profiling(self, on: bool = True):
+        L.check(L.load().rbf_fmm_set_profiling(self._h, 1 if on else 0))
+
+    def phase_times(self) -> dict:
+        ms = (ctypes.c_double * L.RBF_NPHASES)()
+        calls = ctypes.c_int64()
+        L.check(L.load().rbf_fmm_phase_times(self._h, ms, ctypes.byref(calls)))
+        return {"calls": calls.value, **{L.PHASES[k]: ms[k] for k in range(L.RBF_NPHASES)}}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().rbf_fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,210 @@
+"""GPU parity of the fast product against the oracle (through the C ABI).
+
+* tree: keys order, leaves and near lists bit-exact against oracle.tree;
+* plan: parameters equal to oracle.params' rule;
+* FP64 fast product equal to oracle B (same split, brute force) up to rounding;
+* FP64 / FP32 fast product within the tolerance of oracle A (direct sum);
+* device direct sum against oracle A;
+* edge cases: one point, one leaf, duplicate points, ragged leaves;
+* full size (2^20 mixed points): sampled targets against oracle A.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct, params, splitref
+from oracle import tree as T
+from workloads import c1, c2, mixed_points, normal_weights, uniform_points
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def plan(x, **kw):
+    from paper_1606_07652_amd import FmmPlan
+    print(f"[plan] n={x.shape[0]} d={x.shape[1]} {kw}", flush=True)
+    return FmmPlan(x, **kw)
+
+
+def compare_tree(p, x, n_max, max_level, min_level):
+    tr = T.build(x, n_max, max_level, min_level)
+    g = p.tree()
+    assert np.array_equal(g["perm"], tr.perm)
+    assert np.array_equal(g["leaf_begin"], tr.leaf_begin)
+    assert np.array_equal(g["leaf_level"], tr.leaf_level)
+    assert np.array_equal(g["leaf_prefix"], tr.leaf_prefix)
+    ptr, idx = T.near_lists(tr)
+    assert np.array_equal(g["near_ptr"], ptr)
+    assert np.array_equal(g["near_idx"], idx)
+    return tr
+
+
+@pytest.mark.parametrize("case", ["c1_depth3", "mixed3d", "mixed2d_f32", "uniform5d", "duplicates"])
+def test_tree_bit_exact(case):
+    if case == "c1_depth3":
+        x = c1().points
+        kw = dict(n_max=10 ** 9, max_level=3, min_level=3, coarse_level=3, coarse_radius=3, nodes=8)
+        tdt = torch.float64
+    elif case == "mixed3d":
+        x = mixed_points(30000, 3, 7, 8, 0.01)
+        kw = dict(n_max=64, coarse_level=2, coarse_radius=1, nodes=8)
+        tdt = torch.float64
+    elif case == "mixed2d_f32":
+        x = mixed_points(20000, 2, 8, 5, 0.01, dtype=np.float32)
+        kw = dict(n_max=40, coarse_level=3, coarse_radius=2, nodes=8)
+        tdt = torch.float32
+    elif case == "uniform5d":
+        x = uniform_points(5000, 5, 9)
+        kw = dict(n_max=100, coarse_level=1, coarse_radius=0, nodes=4)
+        tdt = torch.float64
+    else:
+        x = np.repeat(uniform_points(40, 3, 10), 5, axis=0)  # every point five times
+        kw = dict(n_max=3, coarse_level=1, coarse_radius=1, nodes=4)
+        tdt = torch.float64
+    p = plan(dev(x, tdt), kernel="gaussian", shape=0.05, tol=1e-6, **kw)
+    inf = p.info()
+    compare_tree(p, x, kw["n_max"], kw.get("max_level", 64), max(kw.get("min_level", 0), kw["coarse_level"]))
+    lo, ext = T.root_cube(x)
+    assert inf["ext"] == ext
+    assert np.array_equal(np.array(inf["lo"]), lo)
+
+
+@pytest.mark.parametrize("s,tol,n,d,nmax", [(0.05, 1e-6, 4096, 2, 64), (0.03, 1e-6, 1 << 20, 3, 128),
+                                            (0.03, 1e-4, 1 << 20, 3, 128), (0.2, 1e-5, 1 << 14, 5, 512)])
+def test_plan_parameters_follow_the_rule(s, tol, n, d, nmax):
+    x = uniform_points(n, d, 3, dtype=np.float32)
+    p = plan(dev(x, torch.float32), kernel="gaussian", shape=s, tol=tol, n_max=nmax)
+    inf = p.info()
+    lo, ext = T.root_cube(x)
+    pr = params.gauss_params(s, tol, d, n, ext, nmax)
+    assert abs(inf["band"] / pr.sigma - 1) < 1e-12
+    assert (inf["nodes"], inf["coarse_level"], inf["coarse_radius"]) == (pr.mn, pr.lc, pr.r)
+    assert abs(inf["rfar"] - pr.rfar) < 1e-12
+
+
+SPLIT_CASES = {
+    # name: (points, kwargs)   -- forced parameters, both sides use the same split
+    "c1_depth3": (lambda: c1().points, dict(shape=0.05, n_max=10 ** 9, max_level=3, min_level=3,
+                                             coarse_level=3, coarse_radius=3, nodes=28, band=103.15)),
+    "c1_root": (lambda: c1().points, dict(shape=0.05, n_max=64, coarse_level=0, coarse_radius=0,
+                                          nodes=46, band=110.0)),
+    "mixed3d": (lambda: mixed_points(6000, 3, 12, 4, 0.01), dict(shape=0.03, n_max=48, coarse_level=2,
+                                                                  coarse_radius=1, nodes=14, band=160.0)),
+    "mixed2d_ragged": (lambda: mixed_points(3001, 2, 13, 3, 0.01), dict(shape=0.04, n_max=37, coarse_level=2,
+                                                                         coarse_radius=1, nodes=18, band=120.0)),
+    "uniform5d": (lambda: uniform_points(900, 5, 14), dict(shape=0.3, n_max=60, coarse_level=1,
+                                                          coarse_radius=0, nodes=6, band=15.0)),
+}
+
+
+@pytest.mark.parametrize("case", list(SPLIT_CASES))
+def test_fp64_fast_product_equals_split_reference(case):
+    """eq. (37) is an exact factorisation: the FP64 fast product reproduces oracle B to rounding."""
+    mk, kw = SPLIT_CASES[case]
+    x = mk()
+    n = x.shape[0]
+    lam = normal_weights(n, 77)
+    p = plan(dev(x), kernel="gaussian", tol=1e-6, **kw)
+    u = p.matvec(dev(lam)).cpu().numpy()
+    ref = splitref.split_reference(x, lam, "gaussian", kw["shape"], n_max=kw["n_max"],
+                                   lc=kw["coarse_level"], r=kw["coarse_radius"], sigma=kw["band"],
+                                   mn=kw["nodes"], max_level=kw.get("max_level", 64))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(u - ref)) / scale
+    print(f"[{case}] max|fmm - splitref|/max|u| = {err:.3e}", flush=True)
+    assert err < 1e-11
+
+
+def test_fp64_c1_meets_tolerance_of_direct_sum():
+    p1 = c1()
+    p = plan(dev(p1.points), kernel="gaussian", shape=p1.shape, tol=1e-6, n_max=10 ** 9, max_level=3,
+             min_level=3)
+    u = p.matvec(dev(p1.lam)).cpu().numpy()
+    ref = direct.direct_sum(p1.points, p1.lam, "gaussian", p1.shape)
+    err = direct.rel_l2(u, ref)
+    print(f"[c1 fp64] rel-L2 vs direct = {err:.3e}", flush=True)
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol,bound", [(torch.float64, 1e-6, 1e-6), (torch.float32, 1e-4, 1e-4)])
+def test_mixed3d_meets_tolerance(dtype, tol, bound):
+    x = mixed_points(40000, 3, 15, 8, 0.01)
+    lam = normal_weights(40000, 16)
+    p = plan(dev(x, dtype), kernel="gaussian", shape=0.03, tol=tol, n_max=64)
+    u = p.matvec(dev(lam, dtype)).double().cpu().numpy()
+    xs = x.astype(np.float32).astype(np.float64) if dtype == torch.float32 else x
+    ls = lam.astype(np.float32).astype(np.float64) if dtype == torch.float32 else lam
+    ref = direct.direct_sum(xs, ls, "gaussian", 0.03)
+    err = direct.rel_l2(u, ref)
+    print(f"[mixed3d {dtype}] rel-L2 vs direct = {err:.3e} info={p.info()['nodes']}", flush=True)
+    assert err <= bound
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_device_direct_sum(dtype):
+    x = uniform_points(3000, 3, 17)
+    lam = normal_weights(3000, 18)
+    p = plan(dev(x, dtype), kernel="gaussian", shape=0.1, tol=1e-6, n_max=64)
+    u = p.direct(dev(lam, dtype)).double().cpu().numpy()
+    xs = x.astype(np.float32).astype(np.float64) if dtype == torch.float32 else x
+    ls = lam.astype(np.float32).astype(np.float64) if dtype == torch.float32 else lam
+    ref = direct.direct_sum(xs, ls, "gaussian", 0.1)
+    assert direct.rel_l2(u, ref) < (1e-13 if dtype == torch.float64 else 2e-6)
+
+
+def test_single_point_and_single_leaf():
+    x = np.array([[0.25, 0.5]])
+    p = plan(dev(x), kernel="gaussian", shape=0.05, tol=1e-6)
+    u = p.matvec(dev(np.array([3.0]))).cpu().numpy()
+    assert abs(u[0] - 3.0) < 1e-15
+    x = uniform_points(100, 3, 19)
+    lam = normal_weights(100, 20)
+    p = plan(dev(x), kernel="gaussian", shape=0.1, tol=1e-6, n_max=128)
+    u = p.matvec(dev(lam)).cpu().numpy()
+    ref = direct.direct_sum(x, lam, "gaussian", 0.1)
+    assert np.max(np.abs(u - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_bad_arguments_raise():
+    from paper_1606_07652_amd import FmmPlan, RbfError
+    x = dev(uniform_points(10, 2, 1))
+    with pytest.raises(RbfError):
+        FmmPlan(x, kernel="gaussian", shape=-1.0, tol=1e-6)
+    with pytest.raises(RbfError):
+        FmmPlan(x, kernel="gaussian", shape=0.1, tol=2.0)
+    with pytest.raises(RbfError):
+        FmmPlan(dev(uniform_points(10, 4, 1)), kernel="gaussian", shape=0.1, tol=1e-6)
+    with pytest.raises(RbfError):
+        FmmPlan(x, kernel="gaussian", shape=0.1, tol=1e-6, nodes=7)
+
+
+def test_full_size_mixed_sampled_targets():
+    """2^20 mixed float32 points, Gaussian s=0.03: the benchmark's launch configuration,
+    checked on 512 seeded targets against the FP64 direct sum over all sources."""
+    w = c2("gaussian")
+    rng = np.random.default_rng(123)
+    idx = np.sort(rng.choice(w.points.shape[0], 512, replace=False))
+    xs = w.points.astype(np.float64)
+    ls = w.lam.astype(np.float64)
+    ref = direct.direct_sum(xs, ls, "gaussian", w.shape, targets=xs[idx])
+    for dtype, tol in ((torch.float64, 1e-6), (torch.float32, 1e-4)):
+        p = plan(dev(w.points, dtype), kernel="gaussian", shape=w.shape, tol=tol, n_max=128)
+        u = p.matvec(dev(w.lam, dtype)).double().cpu().numpy()
+        err = direct.rel_l2(u[idx], ref)
+        print(f"[c2 {dtype}] sampled rel-L2 = {err:.3e} info={p.info()}", flush=True)
+        assert err <= tol
+        p.close()
+        torch.cuda.empty_cache()
