@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--n-max", type=int, default=128)
+    ap.add_argument("--n-max", type=int, default=256)
     ap.add_argument("--cpu-targets", type=int, default=2048)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")

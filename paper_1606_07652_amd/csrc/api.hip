@@ -78,6 +78,12 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
         best_r = (o->coarse_radius >= 0) ? o->coarse_radius : (best_l == 0 ? 0 : 1 + (int)std::floor(p->rcut / w));
         best_far = (best_l == 0) ? p->ext : std::min((best_r + 1) * w, p->ext);
     }
+    if (best_l >= 1 && best_r < 1) {
+        // every near leaf must lie inside the coarse stencil for the leaf translation
+        // (stencil sum minus near sum) to leave exactly the far field
+        set_error("coarse_radius must be >= 1 when coarse_level >= 1 (got %d)", best_r);
+        return RBF_EINVAL;
+    }
     p->lc = best_l;
     p->r = best_r;
     p->rfar = best_far;
@@ -97,6 +103,11 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
     }
     p->mn = mn;
     p->H = mn / 2;
+    {
+        static const int hp[] = {4, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+        p->HP = 0;
+        for (int v : hp) if (v >= p->H) { p->HP = v; break; }
+    }
     p->R = 1;
     for (int k = 0; k < d - 1; ++k) p->R *= mn;
     p->P = p->R * p->H;
@@ -130,7 +141,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (rc == RBF_OK) rc = build_tree(p, points);
     const size_t tsz = dtype == RBF_F32 ? 4 : 8, csz = 2 * tsz;
     if (rc == RBF_OK) {
-        double need = (double)csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) + 2.0 * tsz * n;
+        double need = (double)csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) + (2.0 * tsz + csz * p->HP) * n;
         if (need > 200e9) {
             set_error("rbf_fmm_plan: expansions need %.1f GB (nodes=%d, leaves=%d); raise tol or n_max", need / 1e9,
                       p->mn, p->nleaves);
@@ -141,7 +152,8 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (rc == RBF_OK) rc = ar.alloc(&p->lam_s, tsz * n);
     if (rc == RBF_OK) rc = ar.alloc(&p->u_s, tsz * n);
     if (rc == RBF_OK) rc = ar.alloc(&p->W, csz * p->P * p->nleaves);
-    if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->P * p->nleaves);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->R * p->HP * p->nleaves);
+    if (rc == RBF_OK) rc = ar.alloc(&p->dl, csz * p->HP * n);
     if (rc == RBF_OK) rc = ar.alloc(&p->Wc, csz * p->P * p->ncells);
     if (rc == RBF_OK) rc = ar.alloc(&p->Lc, csz * p->P * p->ncells);
     if (rc == RBF_OK) rc = ar.alloc(&p->Tmp, csz * p->P * p->ncells);

@@ -32,6 +32,14 @@ template <class C> __device__ __forceinline__ C cmul(C a, C b) {
     return r;
 }
 
+// acc += a * b as four fused multiply-adds
+template <class C> __device__ __forceinline__ void cmac(C &acc, const C a, const C b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
 template <class T> struct KFun;
 
 // Gaussian exp(-r^2/(2 s^2)): coef = -log2(e)/(2 s^2) for float (hardware exp2),
@@ -57,67 +65,67 @@ constexpr int kTile = 256;
 
 template <int D> struct Pad { static constexpr int v = (D + 2) & ~1; };
 
-// One workgroup per leaf: targets are the leaf's points, sources the merged point
-// ranges of its near list, staged through LDS in tiles of kTile points (x_1..x_d, lam).
+// One wave per task (up to 64 targets of one leaf); sources are the merged point ranges
+// of the leaf's near list, staged through LDS in tiles of kTile points (x_1..x_d, lam).
 template <class T, int D, int KER>
-__global__ void __launch_bounds__(kThreads) k_p2p(const T *__restrict__ xs, int64_t n, const T *__restrict__ lam_s,
-                                                  const int *__restrict__ leaf_begin, const int *__restrict__ src_ptr,
-                                                  const int2 *__restrict__ src_rng, T coef, T *__restrict__ u_s) {
+__global__ void __launch_bounds__(kWave) k_p2p(const T *__restrict__ xs, int64_t n, const T *__restrict__ lam_s,
+                                               const int2 *__restrict__ tasks, const int *__restrict__ leaf_begin,
+                                               const int *__restrict__ src_ptr, const int2 *__restrict__ src_rng,
+                                               T coef, T *__restrict__ u_s) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     __shared__ int rb[kTile], roff[kTile + 1];
-    const int a = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int t0 = leaf_begin[a], t1 = leaf_begin[a + 1];
+    const int2 tk = tasks[xcd_swizzle(blockIdx.x, gridDim.x)];
+    const int a = tk.x;
+    const int t1 = leaf_begin[a + 1];
+    const int ti = leaf_begin[a] + tk.y + threadIdx.x;
+    const bool act = ti < t1;
     const int r0 = src_ptr[a], r1 = src_ptr[a + 1];
-    for (int tb = t0; tb < t1; tb += blockDim.x) {
-        const int ti = tb + threadIdx.x;
-        const bool act = ti < t1;
-        T y[D];
+    T y[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
-        T acc = 0;
-        for (int rbase = r0; rbase < r1; rbase += kTile) {
-            const int nr = min(kTile, r1 - rbase);
+    for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
+    T acc = 0;
+    for (int rbase = r0; rbase < r1; rbase += kTile) {
+        const int nr = min(kTile, r1 - rbase);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int o = 0;
+            for (int q = 0; q < nr; ++q) {
+                int2 g = src_rng[rbase + q];
+                rb[q] = g.x;
+                roff[q] = o;
+                o += g.y - g.x;
+            }
+            roff[nr] = o;
+        }
+        __syncthreads();
+        const int tot = roff[nr];
+        for (int base = 0; base < tot; base += kTile) {
+            const int cnt = min(kTile, tot - base);
             __syncthreads();
-            if (threadIdx.x == 0) {
-                int o = 0;
-                for (int q = 0; q < nr; ++q) {
-                    int2 g = src_rng[rbase + q];
-                    rb[q] = g.x;
-                    roff[q] = o;
-                    o += g.y - g.x;
-                }
-                roff[nr] = o;
+            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+                int g = base + e;
+                int q = 0;
+                while (roff[q + 1] <= g) ++q;
+                int j = rb[q] + (g - roff[q]);
+#pragma unroll
+                for (int k = 0; k < D; ++k) sdat[e * DP + k] = xs[k * n + j];
+                sdat[e * DP + D] = lam_s[j];
             }
             __syncthreads();
-            const int tot = roff[nr];
-            for (int base = 0; base < tot; base += kTile) {
-                const int cnt = min(kTile, tot - base);
-                __syncthreads();
-                for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                    int g = base + e;
-                    int q = 0;
-                    while (roff[q + 1] <= g) ++q;
-                    int j = rb[q] + (g - roff[q]);
+            for (int e = 0; e < cnt; ++e) {
+                T r2 = 0;
 #pragma unroll
-                    for (int k = 0; k < D; ++k) sdat[e * DP + k] = xs[k * n + j];
-                    sdat[e * DP + D] = lam_s[j];
+                for (int k = 0; k < D; ++k) {
+                    T t = y[k] - sdat[e * DP + k];
+                    r2 += t * t;
                 }
-                __syncthreads();
-                for (int e = 0; e < cnt; ++e) {
-                    T r2 = 0;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        T t = y[k] - sdat[e * DP + k];
-                        r2 += t * t;
-                    }
-                    T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
-                    acc += sdat[e * DP + D] * ph;
-                }
+                T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
+                acc += sdat[e * DP + D] * ph;
             }
         }
-        if (act) u_s[ti] = acc;
     }
+    if (act) u_s[ti] = acc;
 }
 
 // Exact product over all pairs (rows of targets per workgroup, all sources tiled).
@@ -156,25 +164,50 @@ __global__ void __launch_bounds__(kThreads) k_direct(const T *__restrict__ xs, i
 }
 
 // ---- aggregation (P2M) -------------------------------------------------------------
-// Workgroups (leaf, part): thread = one row (m_1..m_{d-1}) of the half grid, all H
-// half-nodes of the last dimension in registers.  Per chunk of CH points, LDS holds
-// e^{-i xi_m x_k} for k < d-1 and lam e^{-i xi_{H+h} x_d}, built by an FP64
-// rotation recurrence from FP64 phases (accurate for |xi x| in the hundreds).
+// Last-dimension phases, weighted by lambda: dl[i][h] = lam_i e^{-i xi_{H+h} x_{i,d}} for
+// h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).
+template <class T, int HMAX>
+__global__ void k_phase_dl(const T *__restrict__ xlast, const T *__restrict__ lam_s, int64_t n, int H, double xiH,
+                           double dxi, typename cplx<T>::type *__restrict__ dl) {
+    using C = typename cplx<T>::type;
+    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double x = (double)xlast[i], l = (double)lam_s[i];
+    double sb, cb, ss, cs;
+    sincos(-xiH * x, &sb, &cb);
+    sincos(-dxi * x, &ss, &cs);
+    double er = l * cb, ei = l * sb;
+    C *o = dl + i * HMAX;
+#pragma unroll
+    for (int h = 0; h < HMAX; ++h) {
+        o[h] = (h < H) ? C{(T)er, (T)ei} : C{0, 0};
+        double nr = er * cs - ei * ss;
+        ei = er * ss + ei * cs;
+        er = nr;
+    }
+}
+
+// Workgroups (leaf, part): thread = one row (m_1..m_{d-1}) of the half grid, all HMAX
+// last-dimension nodes in registers.  Per chunk of CH points the workgroup builds the
+// per-thread factors e^{-i xi_m x_k} (k < d-1) in LDS; the lambda-weighted last-dimension
+// phases of a point are uniform across the workgroup and come through scalar loads.
 template <class T, int D, int HMAX>
-__global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int64_t n, const T *__restrict__ lam_s,
+__global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int64_t n,
+                                                  const typename cplx<T>::type *__restrict__ dl,
                                                   const int *__restrict__ leaf_begin, int wpl, int mn, int H, int R,
-                                                  int CH, double xi0, double xiH, double dxi,
+                                                  int CH, double xi0, double dxi,
                                                   typename cplx<T>::type *__restrict__ W) {
     using C = typename cplx<T>::type;
     extern __shared__ char smem_raw[];
     C *tab = reinterpret_cast<C *>(smem_raw);
-    const int ST = (D - 1) * mn + H;
+    constexpr int DM = D > 1 ? D - 1 : 1;
+    const int ST = DM * mn;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int a = bid / wpl, part = bid % wpl;
     const int t0 = leaf_begin[a], t1 = leaf_begin[a + 1];
     const int row = part * blockDim.x + threadIdx.x;
     const bool act = row < R;
-    int md[D > 1 ? D - 1 : 1];
+    int md[DM];
     {
         int rr = act ? row : 0;
         for (int k = D - 2; k >= 0; --k) { md[k] = rr % mn; rr /= mn; }
@@ -185,54 +218,50 @@ __global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int6
     for (int c0 = t0; c0 < t1; c0 += CH) {
         const int cn = min(CH, t1 - c0);
         __syncthreads();
-        for (int t = threadIdx.x; t < CH * D; t += blockDim.x) {
-            const int j = t / D, k = t % D;
+        for (int t = threadIdx.x; t < cn * DM; t += blockDim.x) {
+            const int j = t / DM, k = t % DM;
             C *dst = tab + j * ST + k * mn;
-            if (j >= cn) {
-                const int len = (k < D - 1) ? mn : H;
-                for (int m = 0; m < len; ++m) dst[m] = C{0, 0};
-                continue;
-            }
             const double x = (double)xs[k * n + c0 + j];
             double sb, cb, ss, cs;
             sincos(-dxi * x, &ss, &cs);
-            if (k < D - 1) {
-                sincos(-xi0 * x, &sb, &cb);
-                double er = cb, ei = sb;
-                for (int m = 0; m < mn; ++m) {
-                    dst[m] = C{(T)er, (T)ei};
-                    double nr = er * cs - ei * ss;
-                    ei = er * ss + ei * cs;
-                    er = nr;
-                }
-            } else {
-                const double l = (double)lam_s[c0 + j];
-                sincos(-xiH * x, &sb, &cb);
-                double er = l * cb, ei = l * sb;
-                for (int h = 0; h < H; ++h) {
-                    dst[h] = C{(T)er, (T)ei};
-                    double nr = er * cs - ei * ss;
-                    ei = er * ss + ei * cs;
-                    er = nr;
-                }
+            sincos(-xi0 * x, &sb, &cb);
+            double er = cb, ei = sb;
+            for (int m = 0; m < mn; ++m) {
+                dst[m] = C{(T)er, (T)ei};
+                double nr = er * cs - ei * ss;
+                ei = er * ss + ei * cs;
+                er = nr;
             }
         }
         __syncthreads();
-        if (act) {
+        if constexpr (sizeof(T) == 4) {
+            // prefetch the next point's uniform operands while the current one is used
+            C cur[HMAX], nxt[HMAX];
+            const C *d0 = dl + (int64_t)c0 * HMAX;
+#pragma unroll
+            for (int h = 0; h < HMAX; ++h) cur[h] = d0[h];
+            for (int j = 0; j < cn; ++j) {
+                const C *dn = dl + (int64_t)(c0 + min(j + 1, cn - 1)) * HMAX;
+#pragma unroll
+                for (int h = 0; h < HMAX; ++h) nxt[h] = dn[h];
+                const C *pt = tab + j * ST;
+                C kv = pt[md[0]];
+#pragma unroll
+                for (int k = 1; k < D - 1; ++k) kv = cmul(kv, pt[k * mn + md[k]]);
+#pragma unroll
+                for (int h = 0; h < HMAX; ++h) cmac(acc[h], kv, cur[h]);
+#pragma unroll
+                for (int h = 0; h < HMAX; ++h) cur[h] = nxt[h];
+            }
+        } else {
             for (int j = 0; j < cn; ++j) {
                 const C *pt = tab + j * ST;
                 C kv = pt[md[0]];
 #pragma unroll
                 for (int k = 1; k < D - 1; ++k) kv = cmul(kv, pt[k * mn + md[k]]);
-                const C *dl = pt + (D - 1) * mn;
+                const C *dj = dl + (int64_t)(c0 + j) * HMAX;
 #pragma unroll
-                for (int h = 0; h < HMAX; ++h) {
-                    if (h < H) {
-                        C v = dl[h];
-                        acc[h].x += kv.x * v.x - kv.y * v.y;
-                        acc[h].y += kv.x * v.y + kv.y * v.x;
-                    }
-                }
+                for (int h = 0; h < HMAX; ++h) cmac(acc[h], kv, dj[h]);
             }
         }
     }
@@ -291,19 +320,27 @@ __global__ void k_m2l_axis(const C *__restrict__ in, int64_t P, int lc, int r, i
 }
 
 // ---- leaf translation + downward pass --------------------------------------------------
+// Output rows are padded to HMAX entries (zeros beyond H) so that the disaggregation
+// can load a whole row unconditionally.
 template <class T, int D>
 __global__ void k_m2l_leaf(const typename cplx<T>::type *__restrict__ W, const typename cplx<T>::type *__restrict__ Lc,
                            const int *__restrict__ leaf_cell, const int *__restrict__ near_ptr,
                            const int *__restrict__ near_idx, const double *__restrict__ wc1, int mn, int H,
-                           int64_t P, typename cplx<T>::type *__restrict__ L) {
+                           int HP, int64_t P, typename cplx<T>::type *__restrict__ L) {
     using C = typename cplx<T>::type;
     const int a = blockIdx.x;
-    const int64_t p = blockIdx.y * (int64_t)kThreads + threadIdx.x;
-    if (p >= P) return;
+    const int64_t q = blockIdx.y * (int64_t)kThreads + threadIdx.x;   // padded index
+    const int64_t RP = P / H * HP;
+    if (q >= RP) return;
+    const int64_t rowq = q / HP;
+    const int h = (int)(q % HP);
+    if (h >= H) {
+        L[(int64_t)a * RP + q] = C{0, 0};
+        return;
+    }
+    const int64_t p = rowq * H + h;
     // separable weight w C(xi) = prod_k wc1[m_k]
-    int64_t rest = p;
-    const int h = (int)(rest % H);
-    rest /= H;
+    int64_t rest = rowq;
     double f = wc1[H + h];
 #pragma unroll
     for (int k = 0; k < D - 1; ++k) {
@@ -317,90 +354,86 @@ __global__ void k_m2l_leaf(const typename cplx<T>::type *__restrict__ W, const t
         s.x -= v.x;
         s.y -= v.y;
     }
-    L[(int64_t)a * P + p] = C{(T)(f * s.x), (T)(f * s.y)};
+    L[(int64_t)a * RP + q] = C{(T)(f * s.x), (T)(f * s.y)};
 }
 
 // ---- disaggregation (L2P) + combine ---------------------------------------------------
-// One workgroup per leaf, one thread per target: e^{i xi_{H+h} x_d} for all h in
-// registers, the other factors by an FP64 odometer recurrence over the rows; the
-// leaf's L rows are uniform across the workgroup.
+// One wave per task (up to 64 target points of one leaf), one lane per target.  The lane
+// keeps e^{+i xi_{H+h} x_d} for all h in registers and walks the rows with an FP64
+// odometer recurrence for the other factors; the leaf's L rows (padded to HMAX) are
+// uniform across the wave and come through scalar loads.
 template <class T, int D, int HMAX>
-__global__ void __launch_bounds__(kThreads) k_l2p(const T *__restrict__ xs, int64_t n,
-                                                  const int *__restrict__ leaf_begin,
-                                                  const typename cplx<T>::type *__restrict__ L, int mn, int H, int R,
-                                                  double xi0, double xiH, double dxi, const T *__restrict__ u_near,
-                                                  const int *__restrict__ perm, T *__restrict__ u) {
+__global__ void __launch_bounds__(kWave) k_l2p(const T *__restrict__ xs, int64_t n, const int2 *__restrict__ tasks,
+                                               const int *__restrict__ leaf_begin,
+                                               const typename cplx<T>::type *__restrict__ L, int mn, int H, int R,
+                                               double xi0, double xiH, double dxi, const T *__restrict__ u_near,
+                                               const int *__restrict__ perm, T *__restrict__ u) {
     using C = typename cplx<T>::type;
-    const int a = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int t0 = leaf_begin[a], t1 = leaf_begin[a + 1];
-    const C *La = L + (int64_t)a * R * H;
-    for (int tb = t0; tb < t1; tb += blockDim.x) {
-        const int ti = tb + threadIdx.x;
-        const bool act = ti < t1;
-        const int tj = act ? ti : t0;
-        double x[D];
+    constexpr int DM = D > 1 ? D - 1 : 1;
+    const int2 tk = tasks[xcd_swizzle(blockIdx.x, gridDim.x)];
+    const int a = tk.x;
+    const int t1 = leaf_begin[a + 1];
+    const int ti = leaf_begin[a] + tk.y + threadIdx.x;
+    const bool act = ti < t1;
+    const int tj = act ? ti : t1 - 1;
+    const C *La = L + (int64_t)a * R * HMAX;
+    double x[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = (double)xs[k * n + tj];
-        C e[HMAX];
-        {
-            double sb, cb, ss, cs;
-            sincos(xiH * x[D - 1], &sb, &cb);
-            sincos(dxi * x[D - 1], &ss, &cs);
-            double er = cb, ei = sb;
+    for (int k = 0; k < D; ++k) x[k] = (double)xs[k * n + tj];
+    C e[HMAX];
+    {
+        double sb, cb, ss, cs;
+        sincos(xiH * x[D - 1], &sb, &cb);
+        sincos(dxi * x[D - 1], &ss, &cs);
+        double er = cb, ei = sb;
 #pragma unroll
-            for (int h = 0; h < HMAX; ++h) {
-                e[h] = C{(T)er, (T)ei};
-                double nr = er * cs - ei * ss;
-                ei = er * ss + ei * cs;
-                er = nr;
-            }
+        for (int h = 0; h < HMAX; ++h) {
+            e[h] = C{(T)er, (T)ei};
+            double nr = er * cs - ei * ss;
+            ei = er * ss + ei * cs;
+            er = nr;
         }
-        double br[D > 1 ? D - 1 : 1], bi[D > 1 ? D - 1 : 1], sr[D > 1 ? D - 1 : 1], si[D > 1 ? D - 1 : 1];
-        double cr[D > 1 ? D - 1 : 1], ci[D > 1 ? D - 1 : 1];
-        int dig[D > 1 ? D - 1 : 1];
+    }
+    double br[DM], bi[DM], sr[DM], si[DM], cr[DM], ci[DM];
+    int dig[DM];
 #pragma unroll
-        for (int k = 0; k < D - 1; ++k) {
-            sincos(xi0 * x[k], &bi[k], &br[k]);
-            sincos(dxi * x[k], &si[k], &sr[k]);
+    for (int k = 0; k < D - 1; ++k) {
+        sincos(xi0 * x[k], &bi[k], &br[k]);
+        sincos(dxi * x[k], &si[k], &sr[k]);
+        cr[k] = br[k];
+        ci[k] = bi[k];
+        dig[k] = 0;
+    }
+    T acc = 0;
+    for (int row = 0; row < R; ++row) {
+        const C *lr = La + (int64_t)row * HMAX;
+        C g{0, 0};
+#pragma unroll
+        for (int h = 0; h < HMAX; ++h) cmac(g, lr[h], e[h]);
+        const T gr = g.x, gi = g.y;
+        double kr = cr[0], ki = ci[0];
+#pragma unroll
+        for (int k = 1; k < D - 1; ++k) {
+            double t = kr * cr[k] - ki * ci[k];
+            ki = kr * ci[k] + ki * cr[k];
+            kr = t;
+        }
+        acc = fma((T)kr, gr, acc);
+        acc = fma(-(T)ki, gi, acc);
+        // odometer: advance the fastest digit (k = d-2), carry towards k = 0
+        for (int k = D - 2; k >= 0; --k) {
+            if (++dig[k] < mn) {
+                double t = cr[k] * sr[k] - ci[k] * si[k];
+                ci[k] = cr[k] * si[k] + ci[k] * sr[k];
+                cr[k] = t;
+                break;
+            }
+            dig[k] = 0;
             cr[k] = br[k];
             ci[k] = bi[k];
-            dig[k] = 0;
         }
-        T acc = 0;
-        for (int row = 0; row < R; ++row) {
-            double kr = cr[0], ki = ci[0];
-#pragma unroll
-            for (int k = 1; k < D - 1; ++k) {
-                double t = kr * cr[k] - ki * ci[k];
-                ki = kr * ci[k] + ki * cr[k];
-                kr = t;
-            }
-            const C *lr = La + (int64_t)row * H;
-            T gr = 0, gi = 0;
-#pragma unroll
-            for (int h = 0; h < HMAX; ++h) {
-                if (h < H) {
-                    C l = lr[h];
-                    gr += l.x * e[h].x - l.y * e[h].y;
-                    gi += l.x * e[h].y + l.y * e[h].x;
-                }
-            }
-            acc += (T)kr * gr - (T)ki * gi;
-            // odometer: advance the fastest digit (k = D-2), carry towards k = 0
-            for (int k = D - 2; k >= 0; --k) {
-                if (++dig[k] < mn) {
-                    double t = cr[k] * sr[k] - ci[k] * si[k];
-                    ci[k] = cr[k] * si[k] + ci[k] * sr[k];
-                    cr[k] = t;
-                    break;
-                }
-                dig[k] = 0;
-                cr[k] = br[k];
-                ci[k] = bi[k];
-            }
-        }
-        if (act) u[perm[ti]] = u_near[ti] + T(2) * acc;
     }
+    if (act) u[perm[ti]] = u_near[ti] + T(2) * acc;
 }
 
 template <class T> T kernel_coef(int kernel, double shape) {
@@ -433,15 +466,19 @@ int far_field(rbf_plan *p, PhaseTimer &pt) {
     // P2M
     RBF_HIP(pt.begin(2));
     {
+        const T *xlast = (const T *)p->xs + (int64_t)(p->d - 1) * p->n;
+        k_phase_dl<T, HMAX><<<(unsigned)((p->n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+            xlast, (const T *)p->lam_s, p->n, H, xiH, dxi, (C *)p->dl);
+        RBF_HIP(hipGetLastError());
         int wpl = (R + kThreads - 1) / kThreads;
         int rows = (R + wpl - 1) / wpl;
         int bd = std::min(kThreads, ((rows + kWave - 1) / kWave) * kWave);
-        // point chunk sized so the LDS tables stay within 48 KB
-        const size_t per_point = sizeof(C) * (size_t)((D - 1) * mn + H);
-        int CH = (int)std::max<size_t>(4, std::min<size_t>(32, (48 * 1024) / per_point));
+        // point chunk sized so the LDS tables stay within 32 KB
+        const size_t per_point = sizeof(C) * (size_t)((D > 1 ? D - 1 : 1) * mn);
+        int CH = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point));
         size_t sh = per_point * CH;
-        k_p2m<T, D, HMAX><<<p->nleaves * wpl, bd, sh, s>>>((const T *)p->xs, p->n, (const T *)p->lam_s,
-                                                           p->leaf_begin, wpl, mn, H, R, CH, xi0, xiH, dxi, (C *)p->W);
+        k_p2m<T, D, HMAX><<<p->nleaves * wpl, bd, sh, s>>>((const T *)p->xs, p->n, (const C *)p->dl, p->leaf_begin,
+                                                           wpl, mn, H, R, CH, xi0, dxi, (C *)p->W);
         RBF_HIP(hipGetLastError());
     }
     RBF_HIP(pt.end());
@@ -465,12 +502,13 @@ int far_field(rbf_plan *p, PhaseTimer &pt) {
         }
     }
     RBF_HIP(pt.end());
-    // leaf translation
+    // leaf translation (output rows padded to HMAX)
     RBF_HIP(pt.begin(5));
     {
-        dim3 gl((unsigned)p->nleaves, (unsigned)((P + kThreads - 1) / kThreads));
+        const int64_t RP = (int64_t)R * HMAX;
+        dim3 gl((unsigned)p->nleaves, (unsigned)((RP + kThreads - 1) / kThreads));
         k_m2l_leaf<T, D><<<gl, kThreads, 0, s>>>((const C *)p->W, (const C *)p->Lc, p->leaf_cell, p->near_ptr,
-                                                 p->near_idx, p->wc1, mn, H, P, (C *)p->Lx);
+                                                 p->near_idx, p->wc1, mn, H, HMAX, P, (C *)p->Lx);
         RBF_HIP(hipGetLastError());
     }
     RBF_HIP(pt.end());
@@ -484,9 +522,9 @@ int l2p(rbf_plan *p, T *u, PhaseTimer &pt) {
     const double dxi = 2.0 * p->sigma / (mn - 1);
     const double xi0 = -p->sigma, xiH = -p->sigma + H * dxi;
     RBF_HIP(pt.begin(6));
-    int bd = std::min(kThreads, ((std::min(p->n_max, kThreads) + kWave - 1) / kWave) * kWave);
-    k_l2p<T, D, HMAX><<<p->nleaves, bd, 0, p->stream>>>((const T *)p->xs, p->n, p->leaf_begin, (const C *)p->Lx, mn, H,
-                                                        R, xi0, xiH, dxi, (const T *)p->u_s, p->perm, u);
+    k_l2p<T, D, HMAX><<<p->ntasks, kWave, 0, p->stream>>>((const T *)p->xs, p->n, p->tasks, p->leaf_begin,
+                                                          (const C *)p->Lx, mn, H, R, xi0, xiH, dxi,
+                                                          (const T *)p->u_s, p->perm, u);
     RBF_HIP(hipGetLastError());
     RBF_HIP(pt.end());
     return RBF_OK;
@@ -502,31 +540,36 @@ int matvec_d(rbf_plan *p, const T *lam, T *u, PhaseTimer &pt) {
     RBF_HIP(pt.end());
     RBF_HIP(pt.begin(1));
     const T coef = kernel_coef<T>(p->kernel, p->shape);
-    int bd = std::min(kThreads, ((std::min(p->n_max, kThreads) + kWave - 1) / kWave) * kWave);
     if (p->kernel == RBF_GAUSSIAN)
-        k_p2p<T, D, RBF_GAUSSIAN><<<p->nleaves, bd, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s, p->leaf_begin,
-                                                            p->src_ptr, p->src_rng, coef, (T *)p->u_s);
+        k_p2p<T, D, RBF_GAUSSIAN><<<p->ntasks, kWave, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s, p->tasks,
+                                                              p->leaf_begin, p->src_ptr, p->src_rng, coef,
+                                                              (T *)p->u_s);
     else
-        k_p2p<T, D, RBF_MULTIQUADRIC><<<p->nleaves, bd, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s,
-                                                                p->leaf_begin, p->src_ptr, p->src_rng, coef,
-                                                                (T *)p->u_s);
+        k_p2p<T, D, RBF_MULTIQUADRIC><<<p->ntasks, kWave, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s,
+                                                                  p->tasks, p->leaf_begin, p->src_ptr, p->src_rng,
+                                                                  coef, (T *)p->u_s);
     RBF_HIP(hipGetLastError());
     RBF_HIP(pt.end());
-    const int H = p->H;
 #define FAR(HM)                                         \
     do {                                                \
         RBF_TRY((far_field<T, D, HM>(p, pt)));          \
         RBF_TRY((l2p<T, D, HM>(p, u, pt)));             \
     } while (0)
-    if (H <= 4) FAR(4);
-    else if (H <= 8) FAR(8);
-    else if (H <= 12) FAR(12);
-    else if (D < 5 && H <= 16) FAR((D < 5 ? 16 : 12));
-    else if (D < 5 && H <= 24) FAR((D < 5 ? 24 : 12));
-    else if (D < 5 && H <= 32) FAR((D < 5 ? 32 : 12));
-    else {
-        set_error("quadrature half-grid %d not compiled for d=%d", H, D);
-        return RBF_EUNSUPPORTED;
+    switch (p->HP) {
+        case 4: FAR(4); break;
+        case 6: FAR(6); break;
+        case 8: FAR(8); break;
+        case 10: FAR(10); break;
+        case 12: FAR(12); break;
+#define BIGH(V) case V: if constexpr (D < 5) { FAR(V); break; } else { set_error("half grid %d not compiled for d=5", V); return RBF_EUNSUPPORTED; }
+        BIGH(14)
+        BIGH(16)
+        BIGH(20)
+        BIGH(24)
+        BIGH(28)
+        BIGH(32)
+#undef BIGH
+        default: set_error("padded half grid %d not compiled", p->HP); return RBF_EUNSUPPORTED;
     }
 #undef FAR
     return RBF_OK;

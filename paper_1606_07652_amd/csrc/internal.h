@@ -65,7 +65,7 @@ struct rbf_plan {
     hipStream_t stream = nullptr;
 
     // tree and quadrature parameters
-    int n_max = 0, max_level = 0, min_level = 0, lc = 0, r = 0, mn = 0, H = 0, B = 0;
+    int n_max = 0, max_level = 0, min_level = 0, lc = 0, r = 0, mn = 0, H = 0, HP = 0, B = 0;
     int64_t R = 0, P = 0;   // rows (nodes^(d-1)) and half-grid length R*H per expansion
     double sigma = 0, L = 0, rcut = 0, rfar = 0, ext = 0;
     double lo[rbf::kMaxDim] = {0, 0, 0, 0, 0};
@@ -86,12 +86,15 @@ struct rbf_plan {
     int *src_ptr = nullptr;          // merged source point ranges of the near field [nleaves + 1]
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
+    int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    int ntasks = 0;
+    void *dl = nullptr;              // lambda-weighted last-dimension phases [n][HP] complex
     double *xi = nullptr;            // quadrature nodes [mn]
     double *wc1 = nullptr;           // w_k C1(xi_k) per dimension (separable kernels) [mn]
     void *lam_s = nullptr;           // sorted coefficients [n]
     void *u_s = nullptr;             // sorted near-field result [n]
     void *W = nullptr;               // leaf expansions [nleaves][P] complex
-    void *Lx = nullptr;              // leaf local expansions [nleaves][P] complex
+    void *Lx = nullptr;              // leaf local expansions, rows padded: [nleaves][R][HP] complex
     void *Wc = nullptr;              // coarse expansions [ncells][P]
     void *Lc = nullptr;              // coarse local expansions [ncells][P]
     void *Tmp = nullptr;             // stencil pass buffer [ncells][P]

@@ -321,11 +321,28 @@ __global__ void k_near(int nleaves, const uint64_t *keys, int n, int B, const in
         uint64_t k0 = pf << sh;
         uint64_t k1 = (pf + 1) << sh;
         int i0 = lower_bound_u64(keys, n, k0);
-        if (i0 >= n || keys[i0] >= k1) continue;
-        int lb = leaf_of_point[i0];
+        const bool nonempty = (i0 < n && keys[i0] < k1);
+        int lb = -1;
+        if (nonempty) {
+            lb = leaf_of_point[i0];
+        } else {
+            // an empty cell can still lie inside a coarser leaf: walk up to the first
+            // ancestor that holds points; it is inside a leaf iff that leaf is not finer
+            for (int l = la - 1; l >= 0; --l) {
+                const int sh2 = D * (B - l);
+                uint64_t pa = pf >> (D * (la - l));
+                int j0 = lower_bound_u64(keys, n, pa << sh2);
+                if (j0 < n && keys[j0] < ((pa + 1) << sh2)) {
+                    int cand = leaf_of_point[j0];
+                    if (leaf_level[cand] <= l) lb = cand;
+                    break;
+                }
+            }
+            if (lb < 0) continue;
+        }
         int lbl = leaf_level[lb];
         if (lbl <= la) {
-            // a coarser (or equal) leaf covers this cell; count it from its first covering offset
+            // a coarser (or equal) leaf covers this cell; count it at its first covering offset
             int64_t cb[D];
             deinterleave<D>(leaf_prefix[lb], lbl, cb);
             bool first = true;
@@ -339,16 +356,7 @@ __global__ void k_near(int nleaves, const uint64_t *keys, int n, int B, const in
                     in2 = in2 && c2 >= 0 && c2 < side;
                     cov = cov && ((c2 >> (la - lbl)) == cb[k]);
                 }
-                if (in2 && cov) {
-                    // an earlier offset inside the same leaf counts it only if that cell holds points
-                    int64_t nc2[D];
-                    int t3 = o2;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) { nc2[k] = ca[k] + (t3 % 3) - 1; t3 /= 3; }
-                    uint64_t pf2 = interleave<D>(nc2, la);
-                    int j0 = lower_bound_u64(keys, n, pf2 << sh);
-                    if (j0 < n && keys[j0] < ((pf2 + 1) << sh)) first = false;
-                }
+                if (in2 && cov) first = false;
             }
             if (first) {
                 if (FILL) dst[count] = lb;
@@ -596,6 +604,19 @@ int tree_typed(rbf_plan *p, const void *points_v) {
     k_ranges<true><<<nlb, kThreads, 0, s>>>(nleaves, p->near_ptr, p->near_idx, p->leaf_begin, p->src_ptr, nullptr,
                                             p->src_rng, nullptr);
     RBF_HIP(hipGetLastError());
+    // wave tasks: (leaf, offset) for every 64 consecutive points of a leaf
+    {
+        std::vector<int> hb(nleaves + 1);
+        RBF_HIP(hipMemcpyAsync(hb.data(), p->leaf_begin, sizeof(int) * (nleaves + 1), hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipStreamSynchronize(s));
+        std::vector<int2> tk;
+        tk.reserve(nleaves + n / kWave + 1);
+        for (int a = 0; a < nleaves; ++a)
+            for (int o = 0; o < hb[a + 1] - hb[a]; o += kWave) tk.push_back(make_int2(a, o));
+        p->ntasks = (int)tk.size();
+        RBF_TRY(ar.alloc((void **)&p->tasks, sizeof(int2) * tk.size()));
+        RBF_HIP(hipMemcpyAsync(p->tasks, tk.data(), sizeof(int2) * tk.size(), hipMemcpyHostToDevice, s));
+    }
     RBF_HIP(hipStreamSynchronize(s));
     RBF_HIP(hipFree(pacc));
     RBF_HIP(hipFree(head));

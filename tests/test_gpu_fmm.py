@@ -68,7 +68,7 @@ def test_tree_bit_exact(case):
         tdt = torch.float32
     elif case == "uniform5d":
         x = uniform_points(5000, 5, 9)
-        kw = dict(n_max=100, coarse_level=1, coarse_radius=0, nodes=4)
+        kw = dict(n_max=100, coarse_level=1, coarse_radius=1, nodes=4)
         tdt = torch.float64
     else:
         x = np.repeat(uniform_points(40, 3, 10), 5, axis=0)  # every point five times
@@ -105,8 +105,8 @@ SPLIT_CASES = {
                                                                   coarse_radius=1, nodes=14, band=160.0)),
     "mixed2d_ragged": (lambda: mixed_points(3001, 2, 13, 3, 0.01), dict(shape=0.04, n_max=37, coarse_level=2,
                                                                          coarse_radius=1, nodes=18, band=120.0)),
-    "uniform5d": (lambda: uniform_points(900, 5, 14), dict(shape=0.3, n_max=60, coarse_level=1,
-                                                          coarse_radius=0, nodes=6, band=15.0)),
+    "uniform5d": (lambda: uniform_points(3000, 5, 14), dict(shape=0.3, n_max=40, coarse_level=1,
+                                                           coarse_radius=1, nodes=6, band=15.0)),
 }
 
 
@@ -189,6 +189,8 @@ def test_bad_arguments_raise():
         FmmPlan(dev(uniform_points(10, 4, 1)), kernel="gaussian", shape=0.1, tol=1e-6)
     with pytest.raises(RbfError):
         FmmPlan(x, kernel="gaussian", shape=0.1, tol=1e-6, nodes=7)
+    with pytest.raises(RbfError):
+        FmmPlan(x, kernel="gaussian", shape=0.1, tol=1e-6, coarse_level=1, coarse_radius=0)
 
 
 def test_full_size_mixed_sampled_targets():

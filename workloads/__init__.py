@@ -28,7 +28,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "uniform_points", "mixed_points", "normal_weights", "Problem",
+    "uniform_points", "mixed_points", "jittered_grid", "normal_weights", "Problem",
     "c1", "c2", "c3", "c4", "c5", "small_mixed", "fourier_modes_rhs", "bumps_rhs",
 ]
 
@@ -58,6 +58,17 @@ def mixed_points(n: int, d: int, seed: int, nblobs: int = 32, blob_sd: float = 0
     owner = np.minimum(np.arange(nb) // max(per, 1), nblobs - 1)
     b = centres[owner] + offs
     return np.concatenate([u, b], axis=0).astype(dtype)
+
+
+def jittered_grid(side: int, d: int, seed: int, jitter: float = 0.25, dtype=np.float64) -> np.ndarray:
+    """side^d points: cell centres of a regular grid on [0,1]^d, each moved by a uniform offset
+    of at most jitter * spacing per coordinate (one draw: ``rng.random((side**d, d))``).
+    Quasi-uniform: the separation stays above (1 - 2 jitter) * spacing."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / side
+    g = np.stack(np.meshgrid(*([np.arange(side)] * d), indexing="ij"), -1).reshape(-1, d)
+    off = (rng.random((side ** d, d)) * 2.0 - 1.0) * jitter * h
+    return ((g + 0.5) * h + off).astype(dtype)
 
 
 def normal_weights(n: int, seed: int, dtype=np.float64) -> np.ndarray:
