@@ -51,6 +51,30 @@ def phase_model(info, dtype_bytes, n):
     }
 
 
+def measured_traffic(phase):
+    """HBM bytes per launch of a phase from the committed counter table, if that table was taken
+    on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_3d_mixed_gauss_n1m.json")
+    src = os.path.join(ROOT, "paper_1606_07652_amd", "csrc", "fmm.hip")
+    if not os.path.exists(path):
+        return None
+    tab = json.load(open(path))
+    if tab.get("fmm_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return tab.get("bytes_per_launch", {}).get(phase)
+
+
+def roofline_of(kind, amount, ms, fp_peak):
+    secs = ms * 1e-3
+    if kind == "hbm":
+        r = {"bound": "hbm", "achieved": amount / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        r = {"bound": "alu", "achieved": amount / secs / 1e12, "peak": fp_peak, "unit": "TFLOP/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
 def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max):
     dev = torch.device("cuda:0")
     x = torch.as_tensor(w.points, dtype=dtype, device=dev)
@@ -97,7 +121,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--n-max", type=int, default=256)
-    ap.add_argument("--cpu-targets", type=int, default=2048)
+    ap.add_argument("--cpu-targets", type=int, default=32768)
+    ap.add_argument("--copy-check", action="store_true",
+                    help="copy a 1 GiB buffer once (a plain copy kernel of known size, used to scale "
+                         "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -111,6 +138,15 @@ def main():
     from paper_1606_07652_amd import FmmPlan
     from workloads import c2
 
+    if args.copy_check:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy check: 1 GiB read + 1 GiB written")
+        del src, dst
+        torch.cuda.empty_cache()
+
     w = c2("gaussian", n=args.n)
     n = w.points.shape[0]
     log(f"[bench] workload {w.name}: n={n}")
@@ -123,15 +159,10 @@ def main():
     model = phase_model(info, 8, n)
     ph = main_run["phase_ms"]
     dom = max((k for k in ph if k in model), key=lambda k: ph[k])
-    kind, amount = model[dom]
-    secs = ph[dom] * 1e-3
-    if kind == "hbm":
-        roof = {"bound": "hbm", "achieved": amount / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": amount / secs / 1e12, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof = roofline_of(*model[dom], ph[dom], FP64_VEC_TFLOPS)
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
+    phase_roof = {k: roofline_of(*model[k], ph[k], FP64_VEC_TFLOPS) for k in model if ph.get(k, 0) > 0}
 
     result = {
         "metric": "RBF-FMM matvec points/s @ rel-L2<=1e-6",
@@ -153,6 +184,8 @@ def main():
         "plan_ms": main_run["plan_ms"],
         "phase_ms": main_run["phase_ms"],
         "roofline": roof,
+        "phase_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4), "achieved": round(v["achieved"], 3),
+                               "unit": v["unit"]} for k, v in phase_roof.items()},
     }
     if f32_run is not None:
         result["fp32_path"] = {"value": n / (f32_run["ms_per_step"] * 1e-3), "unit": "points/s", "tol": 1e-4,
