@@ -75,13 +75,13 @@ def roofline_of(kind, amount, ms, fp_peak):
     return r
 
 
-def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max):
+def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max, m2l_schedule=0):
     dev = torch.device("cuda:0")
     x = torch.as_tensor(w.points, dtype=dtype, device=dev)
     lam = torch.as_tensor(w.lam, dtype=dtype, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = FmmPlan(x, kernel=w.kernel, shape=w.shape, tol=tol, n_max=n_max)
+    plan = FmmPlan(x, kernel=w.kernel, shape=w.shape, tol=tol, n_max=n_max, m2l_schedule=m2l_schedule)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
@@ -114,6 +114,77 @@ def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max):
             "u": out}
 
 
+def run_batched(args):
+    """512 independent 3-D problems (N log-uniform in [2e3, 2e5], Gaussian s log-uniform in
+    [0.01, 0.1], float32, tol 1e-4); all products of one step in one graph launch."""
+    import torch
+
+    from paper_1606_07652_amd import BatchPlan
+    from workloads import c3
+
+    probs = c3(args.nprob)
+    off = np.concatenate([[0], np.cumsum([p.points.shape[0] for p in probs])]).astype(np.int64)
+    X = torch.as_tensor(np.concatenate([p.points for p in probs]), device="cuda:0")
+    lam = torch.as_tensor(np.concatenate([p.lam for p in probs]), device="cuda:0")
+    shapes = np.array([p.shape for p in probs])
+    n = int(off[-1])
+    log(f"[bench] batched workload: {len(probs)} problems, total n={n}")
+    t0 = time.perf_counter()
+    b = BatchPlan(X, off, shapes, kernel="gaussian", tol=1e-4, autotune=not args.no_autotune)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    inf = b.info()
+    log(f"[bench] batch plan {plan_s:.1f} s: groups={inf['ngroups']} far={inf['nfar']} leaves={inf['total_leaves']}")
+    u = torch.empty_like(lam)
+    for _ in range(args.warmup):
+        b.matvec(lam, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.matvec(lam, u)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms = total * 1e3 / args.steps
+    b.set_graph(False)
+    for _ in range(args.warmup):
+        b.matvec(lam, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.matvec(lam, u)
+    torch.cuda.synchronize()
+    ms_nograph = (time.perf_counter() - t0) * 1e3 / args.steps
+    b.set_graph(True)
+    result = {"metric": "batched RBF-FMM matvec points/s @ rel-L2<=1e-4", "value": n / (ms * 1e-3),
+              "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "batched_512x3d_uniform_gaussian_logN_logs", "nprob": len(probs), "n": n,
+                         "tol": 1e-4, "autotune": not args.no_autotune, "groups": inf["ngroups"],
+                         "far_problems": inf["nfar"]},
+              "plan_seconds": plan_s, "ms_per_step_without_graph": ms_nograph}
+    if not args.no_cpu:
+        from oracle import direct
+        u_h = u.double().cpu().numpy()
+        rng = np.random.default_rng(7)
+        errs = []
+        t_full = 0.0   # estimated oracle time for the sampled problems in full
+        sample = rng.choice(len(probs), 16, replace=False)
+        for q in sample:
+            p = probs[q]
+            idx = np.sort(rng.choice(p.points.shape[0], min(256, p.points.shape[0]), replace=False))
+            xs = p.points.astype(np.float64)
+            t0 = time.perf_counter()
+            ref = direct.direct_sum(xs, p.lam.astype(np.float64), "gaussian", p.shape, targets=xs[idx])
+            t_full += (time.perf_counter() - t0) * p.points.shape[0] / idx.size
+            errs.append(direct.rel_l2(u_h[off[q]:off[q + 1]][idx], ref))
+        n_sample = sum(probs[q].points.shape[0] for q in sample)
+        result["rel_l2_sampled_max"] = max(errs)
+        result["cpu_baseline"] = {"value": n_sample / t_full if t_full > 0 else None, "unit": "points/s",
+                                  "cores": direct.threads(), "kind": "oracle",
+                                  "sample": "16 problems x 256 targets each against all of that problem's sources"}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,11 +198,18 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="single", choices=["single", "batched"])
+    ap.add_argument("--nprob", type=int, default=512)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--m2l-schedule", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return run_batched(args)
 
     import torch
 
@@ -150,9 +228,10 @@ def main():
     w = c2("gaussian", n=args.n)
     n = w.points.shape[0]
     log(f"[bench] workload {w.name}: n={n}")
-    main_run = run_path(torch, FmmPlan, w, torch.float64, 1e-6, args.steps, args.warmup, args.n_max)
+    main_run = run_path(torch, FmmPlan, w, torch.float64, 1e-6, args.steps, args.warmup, args.n_max,
+                        args.m2l_schedule)
     f32_run = None if args.no_fp32 else run_path(torch, FmmPlan, w, torch.float32, 1e-4, args.steps,
-                                                  args.warmup, args.n_max)
+                                                  args.warmup, args.n_max, args.m2l_schedule)
 
     # dominant kernel of the headline path and its roofline
     info = main_run["info"]

@@ -53,7 +53,9 @@ typedef struct rbf_opts {
     int    coarse_radius;/* stencil radius r in cells at l_c (-1 = rule) */
     int    nodes;        /* quadrature nodes per dimension Mn, even (0 = rule) */
     double band;         /* band limit sigma (0 = rule) */
-    int    reserved[8];
+    int    m2l_schedule; /* leaf-translation block order: 0 or 1 = contiguous leaf ranges per
+                            XCD (default), 2 = leaf-major over the whole grid */
+    int    reserved[7];
 } rbf_opts;
 
 typedef struct rbf_plan rbf_plan;
@@ -132,6 +134,8 @@ typedef struct rbf_plan_info {
     double  shape, tol, band, period, rcut, rfar, ext;
     double  lo[5];
     int64_t device_bytes;
+    int     far_field;    /* 0 when every kept pair is a near pair (no expansions) */
+    int     reserved;
 } rbf_plan_info;
 
 /* Parameters and sizes chosen by the plan (host struct). */
@@ -158,6 +162,48 @@ int rbf_fmm_set_profiling(rbf_plan *plan, int on);
 /* ms: host double[RBF_NPHASES], summed durations since profiling was enabled;
  * calls: host, number of profiled products. */
 int rbf_fmm_phase_times(const rbf_plan *plan, double *ms, int64_t *calls);
+
+/* ---- measuring autotuner ------------------------------------------------------------
+ * Plans each candidate configuration for the given points (leaf capacity 64, 128, 256,
+ * 512 on top of *base, and a near-only tree: uniform at the deepest level whose cells are
+ * at least the pruning radius wide, so that every kept pair is a near pair), times `reps`
+ * products of each with HIP events on `stream`, and writes the fastest configuration to
+ * *best (host) and its time per product to *best_ms (host, may be NULL).  Arguments as in
+ * rbf_fmm_plan; base may be NULL.  Synchronous; allocates and frees temporary plans. */
+int rbf_fmm_autotune(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
+                     const rbf_opts *base, int reps, void *stream, rbf_opts *best, double *best_ms);
+
+/* ---- batches of independent problems --------------------------------------------------
+ * Many interpolation problems of uneven size, each with its own point set and shape, in
+ * one set of launches: every phase of the product runs as one grid over all problems, and
+ * the whole batched product is captured once into a HIP graph and replayed.
+ *   points   device, concatenated (sum n_p, d) row-major, dtype.
+ *   offsets  host int64[nprob + 1]: problem p owns rows offsets[p] .. offsets[p+1]-1
+ *            (strictly increasing, offsets[0] = 0).
+ *   shapes   host double[nprob]: kernel shape of each problem.
+ *   opts     host, may be NULL: applied to every problem (base of the autotuner).
+ *   autotune nonzero: choose each problem's configuration with rbf_fmm_autotune (2 reps).
+ * The batch owns a private stream ordered after `stream` with events; products are
+ * asynchronous with respect to the host and ordered on `stream`. */
+typedef struct rbf_batch rbf_batch;
+int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, int nprob, int d, int dtype, int kernel,
+                       const double *shapes, double tol, const rbf_opts *opts, int autotune, void *stream,
+                       rbf_batch **out);
+/* u = A_p lambda_p for every problem p; lambda and u are device, concatenated like the
+ * points (caller order within each problem), plan dtype, not aliased.  The graph is
+ * re-captured when the vector pointers differ from the previous call. */
+int rbf_fmm_matvec_batch(rbf_batch *batch, const void *lambda, void *u);
+/* on = 0: launch the kernels directly instead of replaying the captured graph. */
+int rbf_fmm_batch_set_graph(rbf_batch *batch, int on);
+typedef struct rbf_batch_info {
+    int     nprob, ngroups, nfar, use_graph;
+    int64_t total_n, total_leaves, device_bytes;
+    double  plan_seconds;
+} rbf_batch_info;
+/* Sizes of a batch; n_max and nodes (host int32[nprob], may be NULL) receive each
+ * problem's leaf capacity and nodes per dimension (0 for near-only problems). */
+int rbf_fmm_batch_info(const rbf_batch *batch, rbf_batch_info *info, int32_t *n_max, int32_t *nodes);
+int rbf_fmm_batch_destroy(rbf_batch *batch);
 
 #ifdef __cplusplus
 }

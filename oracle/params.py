@@ -18,7 +18,10 @@ relative scale:
   with the smallest R_far among l = 1 .. min(floor(log_{2^d}(n / n_max)), floor(18 / d)),
   ties going to the coarser level, and falls back to the root (l = 0, r = 0, R_far = ext)
   when no level prunes anything;
-* nodes: Mn = ceil(sigma L / pi) + 1, rounded up to an even number, at least 4.
+* nodes: Mn = ceil(sigma L / pi) + 1, rounded up to an even number, at least 4;
+* if Mn exceeds the compiled maximum (64 per dimension; 24 for d = 5) and some level l* >= 1
+  has cells at least R_cut wide, the plan is near-only instead: a uniform tree at the deepest
+  such level, stencil radius 1, every kept pair near (no far field, Mn = 4).
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ class Params:
     rcut: float
     rfar: float
     L_req: float
+    near_only: bool = False
 
 
 def band_t(tol: float) -> float:
@@ -73,4 +77,10 @@ def gauss_params(s: float, tol: float, d: int, n: int, ext: float, n_max: int) -
     if mn % 2:
         mn += 1
     mn = max(mn, 4)
+    if mn > (24 if d == 5 else 64):
+        lstar = 0
+        while lstar + 1 <= 18 // d and ext / 2 ** (lstar + 1) >= rcut:
+            lstar += 1
+        if lstar >= 1:
+            return Params(sigma, 4, lstar, 1, rcut, min(2.0 * ext / 2 ** lstar, ext), L, True)
     return Params(sigma, mn, best_l, best_r, rcut, best_far, L)

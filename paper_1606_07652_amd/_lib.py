@@ -18,7 +18,7 @@ PHASES = ["permute", "p2p", "p2m", "m2m", "m2l_coarse", "m2l_leaf", "l2p"]
 class RbfOpts(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int), ("max_level", ctypes.c_int), ("min_level", ctypes.c_int),
                 ("coarse_level", ctypes.c_int), ("coarse_radius", ctypes.c_int), ("nodes", ctypes.c_int),
-                ("band", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+                ("band", ctypes.c_double), ("m2l_schedule", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 class RbfSolveOpts(ctypes.Structure):
@@ -41,7 +41,13 @@ class RbfPlanInfo(ctypes.Structure):
                 ("near_pairs", ctypes.c_int64), ("shape", ctypes.c_double), ("tol", ctypes.c_double),
                 ("band", ctypes.c_double), ("period", ctypes.c_double), ("rcut", ctypes.c_double),
                 ("rfar", ctypes.c_double), ("ext", ctypes.c_double), ("lo", ctypes.c_double * 5),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("far_field", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class RbfBatchInfo(ctypes.Structure):
+    _fields_ = [("nprob", ctypes.c_int), ("ngroups", ctypes.c_int), ("nfar", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("total_n", ctypes.c_int64), ("total_leaves", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double)]
 
 
 # name -> (restype, argtypes)
@@ -60,6 +66,17 @@ SIGNATURES = {
     "rbf_fmm_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rbf_fmm_phase_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
+    "rbf_fmm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, ctypes.POINTER(RbfOpts), ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.POINTER(RbfOpts), ctypes.POINTER(ctypes.c_double)]),
+    "rbf_fmm_plan_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(RbfOpts),
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_fmm_matvec_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_fmm_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "rbf_fmm_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfBatchInfo), ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "rbf_fmm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None

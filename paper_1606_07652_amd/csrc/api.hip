@@ -96,10 +96,25 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
         mn = o->nodes;
     }
     const int hmax = (d == 5) ? 12 : 32;
+    p->nodes_needed = mn;
     if (mn / 2 > hmax) {
-        set_error("tolerance %g needs %d quadrature nodes per dimension; at most %d are supported for d=%d",
-                  tol, mn, 2 * hmax, d);
-        return RBF_EUNSUPPORTED;
+        // The grid the kernel's width needs is too large.  If cells at least the pruning
+        // radius wide exist, every kept pair can be a near pair instead: a uniform tree at
+        // the deepest such level with the adjacent cells as stencil has no far field.
+        int lstar = 0;
+        while (lstar + 1 <= 18 / d && p->ext / std::ldexp(1.0, lstar + 1) >= p->rcut) ++lstar;
+        const bool forced = o && (o->coarse_level >= 0 || o->nodes > 0);
+        if (lstar >= 1 && !forced) {
+            p->lc = lstar;
+            p->r = 1;
+            p->rfar = std::min(2.0 * p->ext / std::ldexp(1.0, lstar), p->ext);
+            p->max_level = lstar;
+            p->n_max = 1 << 30;
+            p->nodes_needed = 4;
+            mn = 4;
+        } else {
+            mn = 2 * hmax;   // an error later unless the far field turns out empty
+        }
     }
     p->mn = mn;
     p->H = mn / 2;
@@ -113,6 +128,7 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
     p->P = p->R * p->H;
     p->L = 2.0 * M_PI / (2.0 * p->sigma / (mn - 1));
     p->min_level = std::max(p->lc, (o && o->min_level > 0) ? o->min_level : 0);
+    if (p->max_level < p->min_level) p->max_level = p->min_level;
     return RBF_OK;
 }
 
@@ -135,13 +151,30 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     p->n = n; p->d = d; p->dtype = dtype; p->kernel = kernel; p->shape = shape; p->tol = tol;
     p->stream = (hipStream_t)stream;
     p->n_max = (opts && opts->n_max > 0) ? opts->n_max : 128;
+    // leaf translation block order: XCD leaf ranges unless the caller asks for leaf-major
+    // (m2l_schedule = 2 selects 0 explicitly, since 0 is the "automatic" value of the field)
+    p->m2l_sched = (opts && opts->m2l_schedule == 2) ? 0 : 1;
     p->max_level = (opts && opts->max_level > 0) ? opts->max_level : 64;
     int rc = compute_bbox(p, points);
     if (rc == RBF_OK) rc = choose_params(p, opts);
     if (rc == RBF_OK) rc = build_tree(p, points);
     const size_t tsz = dtype == RBF_F32 ? 4 : 8, csz = 2 * tsz;
     if (rc == RBF_OK) {
-        double need = (double)csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) + (2.0 * tsz + csz * p->HP) * n;
+        // the far field is empty when every leaf is a coarse cell and the stencil is the
+        // adjacent cells (or the root is the only leaf): then every kept pair is near
+        const bool uniform_at_lc = p->min_leaf_level == p->lc && p->max_leaf_level == p->lc;
+        if (uniform_at_lc && (p->lc == 0 || p->r <= 1)) p->far = 0;
+        if (p->far && p->nodes_needed > p->mn) {
+            set_error("tolerance %g needs %d quadrature nodes per dimension; at most %d are supported for d=%d "
+                      "(a deeper coarse level or a near-only tree, see rbf_fmm_autotune, avoids the far field)",
+                      tol, p->nodes_needed, p->mn, d);
+            rc = RBF_EUNSUPPORTED;
+        }
+    }
+    const int64_t fboxes = p->far ? 1 : 0;   // expansions are allocated only with a far field
+    if (rc == RBF_OK) {
+        double need = (double)fboxes * csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) +
+                      (2.0 * tsz + fboxes * csz * p->HP) * n;
         if (need > 200e9) {
             set_error("rbf_fmm_plan: expansions need %.1f GB (nodes=%d, leaves=%d); raise tol or n_max", need / 1e9,
                       p->mn, p->nleaves);
@@ -151,14 +184,22 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     Arena &ar = p->arena;
     if (rc == RBF_OK) rc = ar.alloc(&p->lam_s, tsz * n);
     if (rc == RBF_OK) rc = ar.alloc(&p->u_s, tsz * n);
-    if (rc == RBF_OK) rc = ar.alloc(&p->W, csz * p->P * p->nleaves);
-    if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->R * p->HP * p->nleaves);
-    if (rc == RBF_OK) rc = ar.alloc(&p->dl, csz * p->HP * n);
-    if (rc == RBF_OK) rc = ar.alloc(&p->Wc, csz * p->P * p->ncells);
-    if (rc == RBF_OK) rc = ar.alloc(&p->Lc, csz * p->P * p->ncells);
-    if (rc == RBF_OK) rc = ar.alloc(&p->Tmp, csz * p->P * p->ncells);
+    if (rc == RBF_OK) rc = ar.alloc(&p->W, csz * p->P * p->nleaves * fboxes);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->R * p->HP * p->nleaves * fboxes);
+    if (rc == RBF_OK) rc = ar.alloc(&p->dl, csz * p->HP * n * fboxes);
+    if (rc == RBF_OK && fboxes) {
+        // the padding entries (h >= H) of the local expansions stay zero from here on
+        if (hipMemset(p->Lx, 0, csz * p->R * p->HP * p->nleaves) != hipSuccess) {
+            set_error("rbf_fmm_plan: clearing the local expansions failed");
+            rc = RBF_EHIP;
+        }
+    }
+    if (rc == RBF_OK) rc = ar.alloc(&p->Wc, csz * p->P * p->ncells * fboxes);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Lc, csz * p->P * p->ncells * fboxes);
+    if (rc == RBF_OK) rc = ar.alloc(&p->Tmp, csz * p->P * p->ncells * fboxes);
     if (rc == RBF_OK) rc = ar.alloc((void **)&p->xi, sizeof(double) * p->mn);
     if (rc == RBF_OK) rc = ar.alloc((void **)&p->wc1, sizeof(double) * p->mn);
+    if (rc == RBF_OK) rc = ar.alloc((void **)&p->wtab, sizeof(double) * p->P * fboxes);
     if (rc == RBF_OK) {
         // tensor trapezoid nodes on [-sigma, sigma] and w_k C1(xi_k) for the Gaussian:
         // C(xi) = (2 pi)^-d Phi_hat(xi) = prod_k s/sqrt(2 pi) exp(-s^2 xi_k^2 / 2).
@@ -171,7 +212,25 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
         }
         hipError_t e1 = hipMemcpy(p->xi, xi.data(), sizeof(double) * p->mn, hipMemcpyHostToDevice);
         hipError_t e2 = hipMemcpy(p->wc1, wc.data(), sizeof(double) * p->mn, hipMemcpyHostToDevice);
-        if (e1 != hipSuccess || e2 != hipSuccess) { set_error("rbf_fmm_plan: table upload failed"); rc = RBF_EHIP; }
+        hipError_t e3 = hipSuccess;
+        if (fboxes) {
+            // w(xi) C(xi) = prod_k wc1[m_k] for every stored node (row digits m_1..m_{d-1}, m_d = H + h)
+            std::vector<double> wt(p->P);
+            for (int64_t q = 0; q < p->P; ++q) {
+                int64_t rest = q / p->H;
+                double f = wc[p->H + (int)(q % p->H)];
+                for (int k = 0; k < d - 1; ++k) {
+                    f *= wc[rest % p->mn];
+                    rest /= p->mn;
+                }
+                wt[q] = f;
+            }
+            e3 = hipMemcpy(p->wtab, wt.data(), sizeof(double) * p->P, hipMemcpyHostToDevice);
+        }
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            set_error("rbf_fmm_plan: table upload failed");
+            rc = RBF_EHIP;
+        }
     }
     if (rc == RBF_OK) {
         for (int k = 0; k < 2 * RBF_NPHASES && rc == RBF_OK; ++k)
@@ -188,6 +247,12 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
 }
 
 }  // namespace
+
+int plan_create(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
+                const rbf_opts *opts, hipStream_t stream, rbf_plan **out) {
+    return plan_impl(points, n, d, dtype, kernel, shape, tol, opts, stream, out);
+}
+
 }  // namespace rbf
 
 using namespace rbf;
@@ -236,6 +301,7 @@ int rbf_fmm_plan_info(const rbf_plan *p, rbf_plan_info *info) {
     info->rcut = p->rcut; info->rfar = p->rfar; info->ext = p->ext;
     for (int k = 0; k < kMaxDim; ++k) info->lo[k] = p->lo[k];
     info->device_bytes = p->arena.bytes + p->solver_arena.bytes;
+    info->far_field = p->far;
     return RBF_OK;
 }
 

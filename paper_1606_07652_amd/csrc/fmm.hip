@@ -15,15 +15,22 @@
 // and the far field is 2 Re of the half sum.
 //
 // Expansion layout: [box][row][h], row = (m_1 .. m_{d-1}) with m_{d-1} fastest, h = m_d - Mn/2.
+//
+// Every kernel body is a device function over a per-problem descriptor (Desc) and a
+// problem-local block id.  A single plan launches one grid per phase; a batch of plans
+// launches one grid per phase for all its problems, each block finding its problem by a
+// binary search over the per-problem block counts.
 #include <algorithm>
 #include <cmath>
 
+#include "fmm_desc.h"
 #include "internal.h"
 
 namespace rbf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kTile = 256;
 
 template <class C> __device__ __forceinline__ C cmul(C a, C b) {
     C r;
@@ -42,45 +49,94 @@ template <class C> __device__ __forceinline__ void cmac(C &acc, const C a, const
 
 template <class T> struct KFun;
 
-// Gaussian exp(-r^2/(2 s^2)): coef = -log2(e)/(2 s^2) for float (hardware exp2),
-// -1/(2 s^2) for double.
+// Coefficient n of the Taylor series of 2^f = e^{f ln 2}: (ln 2)^n / n!.
+constexpr double exp2_taylor(int n) {
+    double c = 1.0;
+    for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / k;
+    return c;
+}
+
+// 2^t in FP64: t = k + f with k = rint(t) and |f| <= 1/2 (t - k is exact), 2^f from its
+// degree-11 Taylor polynomial (truncation error below 7e-15 relative), scaled by 2^k.  Very
+// negative t underflows to 0 in the scaling.  Used for the Gaussian with
+// t = -r^2 log2(e) / (2 s^2) <= 0.
+__device__ __forceinline__ double exp2_fp64(double t) {
+    const double k = rint(t);
+    const double f = t - k;
+    double p = exp2_taylor(11);
+    p = fma(p, f, exp2_taylor(10));
+    p = fma(p, f, exp2_taylor(9));
+    p = fma(p, f, exp2_taylor(8));
+    p = fma(p, f, exp2_taylor(7));
+    p = fma(p, f, exp2_taylor(6));
+    p = fma(p, f, exp2_taylor(5));
+    p = fma(p, f, exp2_taylor(4));
+    p = fma(p, f, exp2_taylor(3));
+    p = fma(p, f, exp2_taylor(2));
+    p = fma(p, f, exp2_taylor(1));
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)k);   // the conversion saturates, so k below the int range gives 0
+}
+
+// Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32,
+// exp2_fp64 in FP64.  Multiquadric sqrt(r^2 + c^2): coef = c^2.
 template <> struct KFun<float> {
     static __device__ __forceinline__ float gauss(float r2, float coef) { return __builtin_amdgcn_exp2f(r2 * coef); }
     static __device__ __forceinline__ float mq(float r2, float c2) { return __builtin_amdgcn_sqrtf(r2 + c2); }
 };
 template <> struct KFun<double> {
-    static __device__ __forceinline__ double gauss(double r2, double coef) { return exp(r2 * coef); }
+    static __device__ __forceinline__ double gauss(double r2, double coef) { return exp2_fp64(r2 * coef); }
     static __device__ __forceinline__ double mq(double r2, double c2) { return sqrt(r2 + c2); }
 };
 
-// ---- permutation --------------------------------------------------------------------
-template <class T>
-__global__ void k_gather(const T *__restrict__ lam, const int *__restrict__ perm, int64_t n, T *__restrict__ out) {
-    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    if (i < n) out[i] = lam[perm[i]];
-}
-
-// ---- near field (P2P) ---------------------------------------------------------------
-constexpr int kTile = 256;
-
 template <int D> struct Pad { static constexpr int v = (D + 2) & ~1; };
 
-// One wave per task (up to 64 targets of one leaf); sources are the merged point ranges
-// of the leaf's near list, staged through LDS in tiles of kTile points (x_1..x_d, lam).
+// Read-only view for operands that are uniform across a wave and not written by the
+// kernel: the constant address space lets the compiler fetch them with scalar loads.
+template <class T> using cptr = const __attribute__((address_space(4))) T *;
+// complex element i of a read-only array of (re, im) pairs
+template <class T> struct CView {
+    cptr<T> p;
+    __device__ __forceinline__ typename cplx<T>::type operator[](int64_t i) const {
+        return typename cplx<T>::type{p[2 * i], p[2 * i + 1]};
+    }
+    __device__ __forceinline__ CView operator+(int64_t o) const { return CView{p + 2 * o}; }
+};
+// The base address is made explicitly wave-uniform (readfirstlane), so that element
+// addresses built from it and from uniform loop counters stay in scalar registers.
+template <class T> __device__ __forceinline__ CView<T> as_const(const typename cplx<T>::type *q) {
+    const uint64_t a = (uint64_t)q;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return CView<T>{(cptr<T>)(const T *)(((uint64_t)hi << 32) | lo)};
+}
+
+// ---- bodies --------------------------------------------------------------------------
+
+// permutation of the coefficients into Morton order
+template <class T>
+__device__ __forceinline__ void gather_body(const Desc<T> &d, const T *__restrict__ lam, int bid) {
+    int64_t i = bid * (int64_t)kThreads + threadIdx.x;
+    if (i < d.n) d.lam_s[i] = lam[d.off + d.perm[i]];
+}
+
+// Near field (P2P): one wave per task (up to 64 targets of one leaf); sources are the
+// merged point ranges of the leaf's near list, staged through LDS in tiles of kTile
+// points (x_1..x_d, lam).
 template <class T, int D, int KER>
-__global__ void __launch_bounds__(kWave) k_p2p(const T *__restrict__ xs, int64_t n, const T *__restrict__ lam_s,
-                                               const int2 *__restrict__ tasks, const int *__restrict__ leaf_begin,
-                                               const int *__restrict__ src_ptr, const int2 *__restrict__ src_rng,
-                                               T coef, T *__restrict__ u_s) {
+__device__ __forceinline__ void p2p_body(const Desc<T> &d, T *__restrict__ u, int bid) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     __shared__ int rb[kTile], roff[kTile + 1];
-    const int2 tk = tasks[xcd_swizzle(blockIdx.x, gridDim.x)];
+    const T *__restrict__ xs = d.xs;
+    const int64_t n = d.n;
+    const int2 tk = d.tasks[bid];
     const int a = tk.x;
-    const int t1 = leaf_begin[a + 1];
-    const int ti = leaf_begin[a] + tk.y + threadIdx.x;
+    const int t1 = d.leaf_begin[a + 1];
+    const int ti = d.leaf_begin[a] + tk.y + threadIdx.x;
     const bool act = ti < t1;
-    const int r0 = src_ptr[a], r1 = src_ptr[a + 1];
+    const int r0 = d.src_ptr[a], r1 = d.src_ptr[a + 1];
+    const T coef = d.coef;
     T y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
@@ -91,7 +147,7 @@ __global__ void __launch_bounds__(kWave) k_p2p(const T *__restrict__ xs, int64_t
         if (threadIdx.x == 0) {
             int o = 0;
             for (int q = 0; q < nr; ++q) {
-                int2 g = src_rng[rbase + q];
+                int2 g = d.src_rng[rbase + q];
                 rb[q] = g.x;
                 roff[q] = o;
                 o += g.y - g.x;
@@ -99,7 +155,7 @@ __global__ void __launch_bounds__(kWave) k_p2p(const T *__restrict__ xs, int64_t
             roff[nr] = o;
         }
         __syncthreads();
-        const int tot = roff[nr];
+        const int tot = __builtin_amdgcn_readfirstlane(roff[nr]);
         for (int base = 0; base < tot; base += kTile) {
             const int cnt = min(kTile, tot - base);
             __syncthreads();
@@ -110,31 +166,36 @@ __global__ void __launch_bounds__(kWave) k_p2p(const T *__restrict__ xs, int64_t
                 int j = rb[q] + (g - roff[q]);
 #pragma unroll
                 for (int k = 0; k < D; ++k) sdat[e * DP + k] = xs[k * n + j];
-                sdat[e * DP + D] = lam_s[j];
+                sdat[e * DP + D] = d.lam_s[j];
             }
             __syncthreads();
+#pragma unroll 4
             for (int e = 0; e < cnt; ++e) {
                 T r2 = 0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     T t = y[k] - sdat[e * DP + k];
-                    r2 += t * t;
+                    r2 = fma(t, t, r2);
                 }
                 T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
-                acc += sdat[e * DP + D] * ph;
+                acc = fma(sdat[e * DP + D], ph, acc);
             }
         }
     }
-    if (act) u_s[ti] = acc;
+    if (act) {
+        if (d.far) d.u_s[ti] = acc;
+        else u[d.off + d.perm[ti]] = acc;   // near-only plan: this is the result
+    }
 }
 
 // Exact product over all pairs (rows of targets per workgroup, all sources tiled).
 template <class T, int D, int KER>
-__global__ void __launch_bounds__(kThreads) k_direct(const T *__restrict__ xs, int64_t n, const T *__restrict__ lam_s,
-                                                     T coef, const int *__restrict__ perm, T *__restrict__ u) {
+__device__ __forceinline__ void direct_body(const Desc<T> &d, T *__restrict__ u, int bid) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
-    const int64_t ti = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    const T *__restrict__ xs = d.xs;
+    const int64_t n = d.n;
+    const int64_t ti = bid * (int64_t)kThreads + threadIdx.x;
     const bool act = ti < n;
     T y[D];
 #pragma unroll
@@ -146,7 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_direct(const T *__restrict__ xs, i
         if (threadIdx.x < cnt) {
 #pragma unroll
             for (int k = 0; k < D; ++k) sdat[threadIdx.x * DP + k] = xs[k * n + base + threadIdx.x];
-            sdat[threadIdx.x * DP + D] = lam_s[base + threadIdx.x];
+            sdat[threadIdx.x * DP + D] = d.lam_s[base + threadIdx.x];
         }
         __syncthreads();
         for (int e = 0; e < cnt; ++e) {
@@ -156,57 +217,52 @@ __global__ void __launch_bounds__(kThreads) k_direct(const T *__restrict__ xs, i
                 T t = y[k] - sdat[e * DP + k];
                 r2 += t * t;
             }
-            T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
+            T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, d.coef) : KFun<T>::mq(r2, d.coef);
             acc += sdat[e * DP + D] * ph;
         }
     }
-    if (act) u[perm[ti]] = acc;
+    if (act) u[d.off + d.perm[ti]] = acc;
 }
 
-// ---- aggregation (P2M) -------------------------------------------------------------
 // Last-dimension phases, weighted by lambda: dl[i][h] = lam_i e^{-i xi_{H+h} x_{i,d}} for
 // h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).
-template <class T, int HMAX>
-__global__ void k_phase_dl(const T *__restrict__ xlast, const T *__restrict__ lam_s, int64_t n, int H, double xiH,
-                           double dxi, typename cplx<T>::type *__restrict__ dl) {
+template <class T, int D, int HMAX>
+__device__ __forceinline__ void phase_dl_body(const Desc<T> &d, int bid) {
     using C = typename cplx<T>::type;
-    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    if (i >= n) return;
-    const double x = (double)xlast[i], l = (double)lam_s[i];
+    const int64_t i = bid * (int64_t)kThreads + threadIdx.x;
+    if (i >= d.n) return;
+    const double x = (double)d.xs[(int64_t)(D - 1) * d.n + i], l = (double)d.lam_s[i];
     double sb, cb, ss, cs;
-    sincos(-xiH * x, &sb, &cb);
-    sincos(-dxi * x, &ss, &cs);
+    sincos(-d.xiH * x, &sb, &cb);
+    sincos(-d.dxi * x, &ss, &cs);
     double er = l * cb, ei = l * sb;
-    C *o = dl + i * HMAX;
+    C *o = d.dl + i * HMAX;
 #pragma unroll
     for (int h = 0; h < HMAX; ++h) {
-        o[h] = (h < H) ? C{(T)er, (T)ei} : C{0, 0};
+        o[h] = (h < d.H) ? C{(T)er, (T)ei} : C{0, 0};
         double nr = er * cs - ei * ss;
         ei = er * ss + ei * cs;
         er = nr;
     }
 }
 
-// Workgroups (leaf, part): thread = one row (m_1..m_{d-1}) of the half grid, all HMAX
-// last-dimension nodes in registers.  Per chunk of CH points the workgroup builds the
-// per-thread factors e^{-i xi_m x_k} (k < d-1) in LDS; the lambda-weighted last-dimension
-// phases of a point are uniform across the workgroup and come through scalar loads.
+// Aggregation (P2M).  Blocks (leaf, part): thread = one row (m_1..m_{d-1}) of the half
+// grid, all HMAX last-dimension nodes in registers.  Per chunk of CH points the block
+// builds the per-thread factors e^{-i xi_m x_k} (k < d-1) in LDS; the lambda-weighted
+// last-dimension phases of a point are uniform across the block and come through scalar
+// loads.
 template <class T, int D, int HMAX>
-__global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int64_t n,
-                                                  const typename cplx<T>::type *__restrict__ dl,
-                                                  const int *__restrict__ leaf_begin, int wpl, int mn, int H, int R,
-                                                  int CH, double xi0, double dxi,
-                                                  typename cplx<T>::type *__restrict__ W) {
+__device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_raw) {
     using C = typename cplx<T>::type;
-    extern __shared__ char smem_raw[];
     C *tab = reinterpret_cast<C *>(smem_raw);
     constexpr int DM = D > 1 ? D - 1 : 1;
+    const int mn = d.mn, R = d.R, CH = d.p2m_ch;
     const int ST = DM * mn;
-    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int a = bid / wpl, part = bid % wpl;
-    const int t0 = leaf_begin[a], t1 = leaf_begin[a + 1];
+    const int a = bid / d.wpl, part = bid % d.wpl;
+    const int t0 = d.leaf_begin[a], t1 = d.leaf_begin[a + 1];
     const int row = part * blockDim.x + threadIdx.x;
     const bool act = row < R;
+    const int64_t n = d.n;
     int md[DM];
     {
         int rr = act ? row : 0;
@@ -221,10 +277,10 @@ __global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int6
         for (int t = threadIdx.x; t < cn * DM; t += blockDim.x) {
             const int j = t / DM, k = t % DM;
             C *dst = tab + j * ST + k * mn;
-            const double x = (double)xs[k * n + c0 + j];
+            const double x = (double)d.xs[k * n + c0 + j];
             double sb, cb, ss, cs;
-            sincos(-dxi * x, &ss, &cs);
-            sincos(-xi0 * x, &sb, &cb);
+            sincos(-d.dxi * x, &ss, &cs);
+            sincos(-d.xi0 * x, &sb, &cb);
             double er = cb, ei = sb;
             for (int m = 0; m < mn; ++m) {
                 dst[m] = C{(T)er, (T)ei};
@@ -237,11 +293,11 @@ __global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int6
         if constexpr (sizeof(T) == 4) {
             // prefetch the next point's uniform operands while the current one is used
             C cur[HMAX], nxt[HMAX];
-            const C *d0 = dl + (int64_t)c0 * HMAX;
+            const CView<T> d0 = as_const<T>(d.dl + (int64_t)c0 * HMAX);
 #pragma unroll
             for (int h = 0; h < HMAX; ++h) cur[h] = d0[h];
             for (int j = 0; j < cn; ++j) {
-                const C *dn = dl + (int64_t)(c0 + min(j + 1, cn - 1)) * HMAX;
+                const CView<T> dn = as_const<T>(d.dl + (int64_t)(c0 + min(j + 1, cn - 1)) * HMAX);
 #pragma unroll
                 for (int h = 0; h < HMAX; ++h) nxt[h] = dn[h];
                 const C *pt = tab + j * ST;
@@ -259,55 +315,65 @@ __global__ void __launch_bounds__(kThreads) k_p2m(const T *__restrict__ xs, int6
                 C kv = pt[md[0]];
 #pragma unroll
                 for (int k = 1; k < D - 1; ++k) kv = cmul(kv, pt[k * mn + md[k]]);
-                const C *dj = dl + (int64_t)(c0 + j) * HMAX;
+                const CView<T> dj = as_const<T>(d.dl + (int64_t)(c0 + j) * HMAX);
 #pragma unroll
                 for (int h = 0; h < HMAX; ++h) cmac(acc[h], kv, dj[h]);
             }
         }
     }
     if (act) {
-        C *out = W + (int64_t)a * R * H + (int64_t)row * H;
+        const int H = d.H;
+        C *out = d.W + (int64_t)a * R * H + (int64_t)row * H;
 #pragma unroll
         for (int h = 0; h < HMAX; ++h)
             if (h < H) out[h] = acc[h];
     }
 }
 
-// ---- upward pass: coarse cell = sum of its leaves ------------------------------------
-template <class C>
-__global__ void k_m2m(const C *__restrict__ W, const int *__restrict__ cell_begin, int64_t P, C *__restrict__ Wc) {
-    const int64_t c = blockIdx.x;
-    const int64_t p = blockIdx.y * (int64_t)kThreads + threadIdx.x;
+// Upward pass: coarse cell = sum of its leaves.  Blocks (cell, 256-node chunk).
+template <class T>
+__device__ __forceinline__ void m2m_body(const Desc<T> &d, int bid) {
+    using C = typename cplx<T>::type;
+    const int64_t P = d.P;
+    const int nch = (int)((P + kThreads - 1) / kThreads);
+    const int64_t c = bid / nch;
+    const int64_t p = (int64_t)(bid % nch) * kThreads + threadIdx.x;
     if (p >= P) return;
-    const int a0 = cell_begin[c], a1 = cell_begin[c + 1];
+    const int a0 = d.cell_begin[c], a1 = d.cell_begin[c + 1];
     C s{0, 0};
     for (int a = a0; a < a1; ++a) {
-        C v = W[(int64_t)a * P + p];
+        C v = d.W[(int64_t)a * P + p];
         s.x += v.x;
         s.y += v.y;
     }
-    Wc[c * P + p] = s;
+    d.Wc[c * P + p] = s;
 }
 
-// ---- coarse translation: box sum of radius r along one axis of the dense grid ---------
-template <class C, int D>
-__global__ void k_m2l_axis(const C *__restrict__ in, int64_t P, int lc, int r, int axis, C *__restrict__ out) {
-    const int64_t c = blockIdx.x;
-    const int64_t p = blockIdx.y * (int64_t)kThreads + threadIdx.x;
+// Coarse translation: box sum of radius r along one axis of the dense coarse grid.
+// Pass k reads the output of pass k-1 (the first reads Wc) and the last writes Lc.
+template <class T, int D>
+__device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bid) {
+    using C = typename cplx<T>::type;
+    const int64_t P = d.P;
+    const int nch = (int)((P + kThreads - 1) / kThreads);
+    const int64_t c = bid / nch;
+    const int64_t p = (int64_t)(bid % nch) * kThreads + threadIdx.x;
     if (p >= P) return;
-    int64_t cc[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) cc[k] = 0;
-    for (int b = 0; b < lc; ++b)
-#pragma unroll
-        for (int k = 0; k < D; ++k) cc[k] |= (int64_t)((c >> (b * D + k)) & 1) << b;
+    const int lc = d.lc;
+    if (lc == 0 || d.r == 0) {   // single cell: the stencil sum is the cell itself
+        if (axis == 0) d.Lc[c * P + p] = d.Wc[c * P + p];
+        return;
+    }
+    const C *in = (axis == 0) ? d.Wc : ((axis % 2 == 1) ? d.Tmp : d.Wc);
+    C *out = (axis == D - 1) ? d.Lc : ((axis % 2 == 0) ? d.Tmp : d.Wc);
+    int64_t cc = 0, mask = 0;
+    for (int b = 0; b < lc; ++b) {
+        cc |= ((c >> (b * D + axis)) & 1) << b;
+        mask |= (int64_t)1 << (b * D + axis);
+    }
     const int64_t side = (int64_t)1 << lc;
-    const int64_t lo = max((int64_t)0, cc[axis] - r), hi = min(side - 1, cc[axis] + r);
-    const int64_t base = c & ~(int64_t)0;
-    // Morton index with the axis coordinate replaced: clear that axis' bits, then insert.
-    int64_t mask = 0;
-    for (int b = 0; b < lc; ++b) mask |= (int64_t)1 << (b * D + axis);
-    const int64_t rest = base & ~mask;
+    const int64_t lo = max((int64_t)0, cc - d.r), hi = min(side - 1, cc + d.r);
+    const int64_t rest = c & ~mask;
     C s{0, 0};
     for (int64_t v = lo; v <= hi; ++v) {
         int64_t ins = 0;
@@ -319,72 +385,70 @@ __global__ void k_m2l_axis(const C *__restrict__ in, int64_t P, int lc, int r, i
     out[c * P + p] = s;
 }
 
-// ---- leaf translation + downward pass --------------------------------------------------
-// Output rows are padded to HMAX entries (zeros beyond H) so that the disaggregation
-// can load a whole row unconditionally.
+// Leaf translation + downward pass.  Blocks (leaf, 256-entry chunk of the expansion);
+// each thread subtracts the leaf's near rows from the coarse cell's local expansion and
+// applies the quadrature weight w(xi) C(xi) (a plan-time table).  Output rows are padded
+// to HP entries; the padding was zeroed at plan time and is not written.
+// Block order (d.m2l_sched): 0 = leaf fastest, chunk slowest; 1 = the same order split
+// into 8 contiguous leaf ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
+// the near rows a range re-reads stay in one XCD's L2 (measured on the 2^20-point
+// workload: 3.2 GB fetched from memory per launch instead of 25 GB).  Batches use 0.
 template <class T, int D>
-__global__ void k_m2l_leaf(const typename cplx<T>::type *__restrict__ W, const typename cplx<T>::type *__restrict__ Lc,
-                           const int *__restrict__ leaf_cell, const int *__restrict__ near_ptr,
-                           const int *__restrict__ near_idx, const double *__restrict__ wc1, int mn, int H,
-                           int HP, int64_t P, typename cplx<T>::type *__restrict__ L) {
+__device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
     using C = typename cplx<T>::type;
-    const int a = blockIdx.x;
-    const int64_t q = blockIdx.y * (int64_t)kThreads + threadIdx.x;   // padded index
-    const int64_t RP = P / H * HP;
-    if (q >= RP) return;
-    const int64_t rowq = q / HP;
-    const int h = (int)(q % HP);
-    if (h >= H) {
-        L[(int64_t)a * RP + q] = C{0, 0};
-        return;
+    const int nleaves = d.nleaves, H = d.H, HP = d.HP;
+    const int P = (int)d.P;
+    int a, chunk;
+    if (d.m2l_sched == 1) {
+        const int x = g & 7, k = g >> 3;
+        const int per = (nleaves + 7) >> 3;            // leaves per XCD range (last may be short)
+        const int lo = min(x * per, nleaves), hi = min(lo + per, nleaves);
+        const int len = max(hi - lo, 1);
+        a = lo + k % len;
+        chunk = k / len;
+        if (hi - lo == 0 || a >= hi) return;
+    } else {
+        a = g % nleaves;
+        chunk = g / nleaves;
     }
-    const int64_t p = rowq * H + h;
-    // separable weight w C(xi) = prod_k wc1[m_k]
-    int64_t rest = rowq;
-    double f = wc1[H + h];
-#pragma unroll
-    for (int k = 0; k < D - 1; ++k) {
-        f *= wc1[rest % mn];
-        rest /= mn;
-    }
-    C s = Lc[(int64_t)leaf_cell[a] * P + p];
-    const int e0 = near_ptr[a], e1 = near_ptr[a + 1];
+    const int p = chunk * kThreads + (int)threadIdx.x;
+    if (p >= P) return;
+    C s = d.Lc[(int64_t)d.leaf_cell[a] * P + p];
+    const int e0 = d.near_ptr[a], e1 = d.near_ptr[a + 1];
     for (int e = e0; e < e1; ++e) {
-        C v = W[(int64_t)near_idx[e] * P + p];
+        const C v = d.W[(int64_t)d.near_idx[e] * P + p];
         s.x -= v.x;
         s.y -= v.y;
     }
-    L[(int64_t)a * RP + q] = C{(T)(f * s.x), (T)(f * s.y)};
+    const double f = d.wtab[p];
+    const int row = p / H, h = p - row * H;
+    d.Lx[((int64_t)a * d.R + row) * HP + h] = C{(T)(f * s.x), (T)(f * s.y)};
 }
 
-// ---- disaggregation (L2P) + combine ---------------------------------------------------
-// One wave per task (up to 64 target points of one leaf), one lane per target.  The lane
-// keeps e^{+i xi_{H+h} x_d} for all h in registers and walks the rows with an FP64
-// odometer recurrence for the other factors; the leaf's L rows (padded to HMAX) are
-// uniform across the wave and come through scalar loads.
+// Disaggregation (L2P) + combine.  One wave per task (up to 64 target points of one
+// leaf), one lane per target.  The lane keeps e^{+i xi_{H+h} x_d} for all h in registers
+// and walks the rows with an FP64 odometer recurrence for the other factors; the leaf's
+// L rows (padded to HMAX) are uniform across the wave and come through scalar loads.
 template <class T, int D, int HMAX>
-__global__ void __launch_bounds__(kWave) k_l2p(const T *__restrict__ xs, int64_t n, const int2 *__restrict__ tasks,
-                                               const int *__restrict__ leaf_begin,
-                                               const typename cplx<T>::type *__restrict__ L, int mn, int H, int R,
-                                               double xi0, double xiH, double dxi, const T *__restrict__ u_near,
-                                               const int *__restrict__ perm, T *__restrict__ u) {
+__device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, int bid) {
     using C = typename cplx<T>::type;
     constexpr int DM = D > 1 ? D - 1 : 1;
-    const int2 tk = tasks[xcd_swizzle(blockIdx.x, gridDim.x)];
+    const int2 tk = d.tasks[bid];
     const int a = tk.x;
-    const int t1 = leaf_begin[a + 1];
-    const int ti = leaf_begin[a] + tk.y + threadIdx.x;
+    const int t1 = d.leaf_begin[a + 1];
+    const int ti = d.leaf_begin[a] + tk.y + threadIdx.x;
     const bool act = ti < t1;
     const int tj = act ? ti : t1 - 1;
-    const C *La = L + (int64_t)a * R * HMAX;
+    const int R = d.R, mn = d.mn;
+    const CView<T> La = as_const<T>(d.Lx + (int64_t)a * R * HMAX);
     double x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = (double)xs[k * n + tj];
+    for (int k = 0; k < D; ++k) x[k] = (double)d.xs[k * d.n + tj];
     C e[HMAX];
     {
         double sb, cb, ss, cs;
-        sincos(xiH * x[D - 1], &sb, &cb);
-        sincos(dxi * x[D - 1], &ss, &cs);
+        sincos(d.xiH * x[D - 1], &sb, &cb);
+        sincos(d.dxi * x[D - 1], &ss, &cs);
         double er = cb, ei = sb;
 #pragma unroll
         for (int h = 0; h < HMAX; ++h) {
@@ -398,19 +462,18 @@ __global__ void __launch_bounds__(kWave) k_l2p(const T *__restrict__ xs, int64_t
     int dig[DM];
 #pragma unroll
     for (int k = 0; k < D - 1; ++k) {
-        sincos(xi0 * x[k], &bi[k], &br[k]);
-        sincos(dxi * x[k], &si[k], &sr[k]);
+        sincos(d.xi0 * x[k], &bi[k], &br[k]);
+        sincos(d.dxi * x[k], &si[k], &sr[k]);
         cr[k] = br[k];
         ci[k] = bi[k];
         dig[k] = 0;
     }
     T acc = 0;
     for (int row = 0; row < R; ++row) {
-        const C *lr = La + (int64_t)row * HMAX;
+        const CView<T> lr = La + (int64_t)row * HMAX;
         C g{0, 0};
 #pragma unroll
         for (int h = 0; h < HMAX; ++h) cmac(g, lr[h], e[h]);
-        const T gr = g.x, gi = g.y;
         double kr = cr[0], ki = ci[0];
 #pragma unroll
         for (int k = 1; k < D - 1; ++k) {
@@ -418,8 +481,8 @@ __global__ void __launch_bounds__(kWave) k_l2p(const T *__restrict__ xs, int64_t
             ki = kr * ci[k] + ki * cr[k];
             kr = t;
         }
-        acc = fma((T)kr, gr, acc);
-        acc = fma(-(T)ki, gi, acc);
+        acc = fma((T)kr, g.x, acc);
+        acc = fma(-(T)ki, g.y, acc);
         // odometer: advance the fastest digit (k = d-2), carry towards k = 0
         for (int k = D - 2; k >= 0; --k) {
             if (++dig[k] < mn) {
@@ -433,159 +496,246 @@ __global__ void __launch_bounds__(kWave) k_l2p(const T *__restrict__ xs, int64_t
             ci[k] = bi[k];
         }
     }
-    if (act) u[perm[ti]] = u_near[ti] + T(2) * acc;
+    if (act) u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * acc;
 }
 
-template <class T> T kernel_coef(int kernel, double shape) {
-    if (kernel == RBF_GAUSSIAN) {
-        if (sizeof(T) == 4) return (T)(-1.4426950408889634 / (2.0 * shape * shape));
-        return (T)(-1.0 / (2.0 * shape * shape));
+// ---- kernels: single problem (descriptor by value) or batch (descriptor array) --------
+__device__ __forceinline__ int find_prob(const int *__restrict__ bstart, int nprob, int g) {
+    int lo = 0, hi = nprob;   // largest q with bstart[q] <= g
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (bstart[mid] <= g) lo = mid; else hi = mid;
     }
-    return (T)(shape * shape);
+    return lo;
 }
 
-struct PhaseTimer {
-    rbf_plan *p;
-    int ph = -1;
-    explicit PhaseTimer(rbf_plan *pp) : p(pp) {}
-    hipError_t begin(int k) {
-        ph = k;
-        return p->profiling ? hipEventRecord(p->ev[2 * k], p->stream) : hipSuccess;
-    }
-    hipError_t end() { return p->profiling ? hipEventRecord(p->ev[2 * ph + 1], p->stream) : hipSuccess; }
+// Launch argument: either one descriptor (nprob == 0) or a descriptor array with the
+// exclusive prefix of per-problem block counts.
+template <class T> struct Work {
+    Desc<T> one;
+    const Desc<T> *many;
+    const int *bstart;
+    int nprob;
+    const T *lam;
+    T *u;
 };
 
-template <class T, int D, int HMAX>
-int far_field(rbf_plan *p, PhaseTimer &pt) {
-    using C = typename cplx<T>::type;
-    hipStream_t s = p->stream;
-    const int mn = p->mn, H = p->H, R = (int)p->R;
-    const int64_t P = p->P;
-    const double dxi = 2.0 * p->sigma / (mn - 1);
-    const double xi0 = -p->sigma, xiH = -p->sigma + H * dxi;
-    // P2M
-    RBF_HIP(pt.begin(2));
-    {
-        const T *xlast = (const T *)p->xs + (int64_t)(p->d - 1) * p->n;
-        k_phase_dl<T, HMAX><<<(unsigned)((p->n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-            xlast, (const T *)p->lam_s, p->n, H, xiH, dxi, (C *)p->dl);
-        RBF_HIP(hipGetLastError());
-        int wpl = (R + kThreads - 1) / kThreads;
-        int rows = (R + wpl - 1) / wpl;
-        int bd = std::min(kThreads, ((rows + kWave - 1) / kWave) * kWave);
-        // point chunk sized so the LDS tables stay within 32 KB
-        const size_t per_point = sizeof(C) * (size_t)((D > 1 ? D - 1 : 1) * mn);
-        int CH = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point));
-        size_t sh = per_point * CH;
-        k_p2m<T, D, HMAX><<<p->nleaves * wpl, bd, sh, s>>>((const T *)p->xs, p->n, (const C *)p->dl, p->leaf_begin,
-                                                           wpl, mn, H, R, CH, xi0, dxi, (C *)p->W);
-        RBF_HIP(hipGetLastError());
+// Resolves the calling block to (descriptor, problem-local block id).
+template <class T, bool SWIZZLE = true>
+__device__ __forceinline__ const Desc<T> &resolve(const Work<T> &w, int &lb) {
+    const int g = SWIZZLE ? xcd_swizzle(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (w.nprob == 0) {
+        lb = g;
+        return w.one;
     }
-    RBF_HIP(pt.end());
-    // M2M
-    RBF_HIP(pt.begin(3));
-    dim3 gp((unsigned)p->ncells, (unsigned)((P + kThreads - 1) / kThreads));
-    k_m2m<C><<<gp, kThreads, 0, s>>>((const C *)p->W, p->cell_leaf_begin, P, (C *)p->Wc);
-    RBF_HIP(hipGetLastError());
-    RBF_HIP(pt.end());
-    // coarse stencil, one axis at a time: Wc -> Tmp -> Wc -> ... -> Lc
-    RBF_HIP(pt.begin(4));
-    if (p->lc == 0 || p->r == 0) {
-        RBF_HIP(hipMemcpyAsync(p->Lc, p->Wc, sizeof(C) * P * p->ncells, hipMemcpyDeviceToDevice, s));
-    } else {
-        C *src = (C *)p->Wc;
-        for (int ax = 0; ax < D; ++ax) {
-            C *dst = (ax == D - 1) ? (C *)p->Lc : ((ax % 2 == 0) ? (C *)p->Tmp : (C *)p->Wc);
-            k_m2l_axis<C, D><<<gp, kThreads, 0, s>>>(src, P, p->lc, p->r, ax, dst);
-            RBF_HIP(hipGetLastError());
-            src = dst;
+    const int q = find_prob(w.bstart, w.nprob, g);
+    lb = g - w.bstart[q];
+    return w.many[q];
+}
+
+template <class T> __global__ void __launch_bounds__(kThreads) k_gather(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    gather_body<T>(d, w.lam, lb);
+}
+template <class T, int D, int KER> __global__ void __launch_bounds__(kWave) k_p2p(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    p2p_body<T, D, KER>(d, w.u, lb);
+}
+template <class T, int D, int KER> __global__ void __launch_bounds__(kThreads) k_direct(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    direct_body<T, D, KER>(d, w.u, lb);
+}
+template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_phase_dl(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    phase_dl_body<T, D, HMAX>(d, lb);
+}
+template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_p2m(Work<T> w) {
+    extern __shared__ char smem_raw[];
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    p2m_body<T, D, HMAX>(d, lb, smem_raw);
+}
+template <class T> __global__ void __launch_bounds__(kThreads) k_m2m(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    m2m_body<T>(d, lb);
+}
+template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_axis(Work<T> w, int axis) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    m2l_axis_body<T, D>(d, axis, lb);
+}
+template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_leaf(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve<T, false>(w, lb);
+    m2l_leaf_body<T, D>(d, lb);
+}
+template <class T, int D, int HMAX> __global__ void __launch_bounds__(kWave) k_l2p(Work<T> w) {
+    int lb;
+    const Desc<T> &d = resolve(w, lb);
+    l2p_body<T, D, HMAX>(d, w.u, lb);
+}
+
+// ---- host side -----------------------------------------------------------------------
+struct PhaseTimer {
+    rbf_plan *p;   // null: no timing
+    int ph = -1;
+    explicit PhaseTimer(rbf_plan *pp) : p(pp && pp->profiling ? pp : nullptr) {}
+    hipError_t begin(int k) {
+        ph = k;
+        return p ? hipEventRecord(p->ev[2 * k], p->stream) : hipSuccess;
+    }
+    hipError_t end() { return p ? hipEventRecord(p->ev[2 * ph + 1], p->stream) : hipSuccess; }
+};
+
+// Per-phase block counts of one problem (the grid of a single-problem launch).
+template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
+    const int64_t nb_pts = (d.n + kThreads - 1) / kThreads;
+    const int64_t nch = (d.P + kThreads - 1) / kThreads;
+    if (!d.far && phase != PH_GATHER && phase != PH_P2P && phase != PH_DIRECT) return 0;
+    switch (phase) {
+        case PH_GATHER: case PH_PHASE_DL: case PH_DIRECT: return nb_pts;
+        case PH_P2P: case PH_L2P: return d.ntasks;
+        case PH_P2M: return (int64_t)d.nleaves * d.wpl;
+        case PH_M2M: case PH_M2L_AXIS: return d.ncells * nch;
+        case PH_M2L_LEAF: {
+            const int64_t nch_l = (d.P + kThreads - 1) / kThreads;
+            if (d.m2l_sched == 1) return 8 * nch_l * ((d.nleaves + 7) / 8);
+            return nch_l * d.nleaves;
         }
     }
-    RBF_HIP(pt.end());
-    // leaf translation (output rows padded to HMAX)
-    RBF_HIP(pt.begin(5));
-    {
-        const int64_t RP = (int64_t)R * HMAX;
-        dim3 gl((unsigned)p->nleaves, (unsigned)((RP + kThreads - 1) / kThreads));
-        k_m2l_leaf<T, D><<<gl, kThreads, 0, s>>>((const C *)p->W, (const C *)p->Lc, p->leaf_cell, p->near_ptr,
-                                                 p->near_idx, p->wc1, mn, H, HMAX, P, (C *)p->Lx);
-        RBF_HIP(hipGetLastError());
+    return 0;
+}
+
+template <class T> size_t p2m_shmem(const Desc<T> &d, int D) {
+    return sizeof(typename cplx<T>::type) * (size_t)((D > 1 ? D - 1 : 1) * d.mn) * d.p2m_ch;
+}
+
+// Launch one phase for a single problem or a batch (see Work).
+template <class T, int D, int HMAX>
+int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, int axis, size_t shmem, int kernel) {
+    if (nblocks <= 0) return RBF_OK;
+    const unsigned g = (unsigned)nblocks;
+    switch (phase) {
+        case PH_GATHER: k_gather<T><<<g, kThreads, 0, s>>>(w); break;
+        case PH_P2P:
+            if (kernel == RBF_GAUSSIAN) k_p2p<T, D, RBF_GAUSSIAN><<<g, kWave, 0, s>>>(w);
+            else k_p2p<T, D, RBF_MULTIQUADRIC><<<g, kWave, 0, s>>>(w);
+            break;
+        case PH_DIRECT:
+            if (kernel == RBF_GAUSSIAN) k_direct<T, D, RBF_GAUSSIAN><<<g, kThreads, 0, s>>>(w);
+            else k_direct<T, D, RBF_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w);
+            break;
+        case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kThreads, 0, s>>>(w); break;
+        case PH_P2M: k_p2m<T, D, HMAX><<<g, (D > 2 ? kThreads : kWave), shmem, s>>>(w); break;
+        case PH_M2M: k_m2m<T><<<g, kThreads, 0, s>>>(w); break;
+        case PH_M2L_AXIS: k_m2l_axis<T, D><<<g, kThreads, 0, s>>>(w, axis); break;
+        case PH_M2L_LEAF: k_m2l_leaf<T, D><<<g, kThreads, 0, s>>>(w); break;
+        case PH_L2P: k_l2p<T, D, HMAX><<<g, kWave, 0, s>>>(w); break;
     }
-    RBF_HIP(pt.end());
+    RBF_HIP(hipGetLastError());
     return RBF_OK;
 }
 
+// The whole product for one problem or one batch group (all problems with the same HP).
+// bstarts[phase] holds the per-problem block prefix of each phase (batch only).
 template <class T, int D, int HMAX>
-int l2p(rbf_plan *p, T *u, PhaseTimer &pt) {
-    using C = typename cplx<T>::type;
-    const int mn = p->mn, H = p->H, R = (int)p->R;
-    const double dxi = 2.0 * p->sigma / (mn - 1);
-    const double xi0 = -p->sigma, xiH = -p->sigma + H * dxi;
+int product_d(const Work<T> &w0, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh, int kernel,
+              hipStream_t s, PhaseTimer &pt) {
+    Work<T> w = w0;
+    auto bs = [&](int ph) {
+        if (w0.nprob) w.bstart = bstarts[ph];
+    };
+    RBF_HIP(pt.begin(0));
+    bs(PH_GATHER);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_GATHER, nblocks[PH_GATHER], s, 0, 0, kernel)));
+    RBF_HIP(pt.end());
+    RBF_HIP(pt.begin(1));
+    bs(PH_P2P);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2P, nblocks[PH_P2P], s, 0, 0, kernel)));
+    RBF_HIP(pt.end());
+    RBF_HIP(pt.begin(2));
+    bs(PH_PHASE_DL);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_PHASE_DL, nblocks[PH_PHASE_DL], s, 0, 0, kernel)));
+    bs(PH_P2M);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2M, nblocks[PH_P2M], s, 0, p2m_sh, kernel)));
+    RBF_HIP(pt.end());
+    RBF_HIP(pt.begin(3));
+    bs(PH_M2M);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2M, nblocks[PH_M2M], s, 0, 0, kernel)));
+    RBF_HIP(pt.end());
+    RBF_HIP(pt.begin(4));
+    bs(PH_M2L_AXIS);
+    for (int ax = 0; ax < D; ++ax)
+        RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_AXIS, nblocks[PH_M2L_AXIS], s, ax, 0, kernel)));
+    RBF_HIP(pt.end());
+    RBF_HIP(pt.begin(5));
+    bs(PH_M2L_LEAF);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_LEAF, nblocks[PH_M2L_LEAF], s, 0, 0, kernel)));
+    RBF_HIP(pt.end());
     RBF_HIP(pt.begin(6));
-    k_l2p<T, D, HMAX><<<p->ntasks, kWave, 0, p->stream>>>((const T *)p->xs, p->n, p->tasks, p->leaf_begin,
-                                                          (const C *)p->Lx, mn, H, R, xi0, xiH, dxi,
-                                                          (const T *)p->u_s, p->perm, u);
-    RBF_HIP(hipGetLastError());
+    bs(PH_L2P);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_L2P, nblocks[PH_L2P], s, 0, 0, kernel)));
     RBF_HIP(pt.end());
     return RBF_OK;
 }
 
 template <class T, int D>
-int matvec_d(rbf_plan *p, const T *lam, T *u, PhaseTimer &pt) {
-    hipStream_t s = p->stream;
-    const int64_t n = p->n;
-    RBF_HIP(pt.begin(0));
-    k_gather<T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(lam, p->perm, n, (T *)p->lam_s);
-    RBF_HIP(hipGetLastError());
-    RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(1));
-    const T coef = kernel_coef<T>(p->kernel, p->shape);
-    if (p->kernel == RBF_GAUSSIAN)
-        k_p2p<T, D, RBF_GAUSSIAN><<<p->ntasks, kWave, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s, p->tasks,
-                                                              p->leaf_begin, p->src_ptr, p->src_rng, coef,
-                                                              (T *)p->u_s);
-    else
-        k_p2p<T, D, RBF_MULTIQUADRIC><<<p->ntasks, kWave, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s,
-                                                                  p->tasks, p->leaf_begin, p->src_ptr, p->src_rng,
-                                                                  coef, (T *)p->u_s);
-    RBF_HIP(hipGetLastError());
-    RBF_HIP(pt.end());
-#define FAR(HM)                                         \
-    do {                                                \
-        RBF_TRY((far_field<T, D, HM>(p, pt)));          \
-        RBF_TRY((l2p<T, D, HM>(p, u, pt)));             \
-    } while (0)
-    switch (p->HP) {
-        case 4: FAR(4); break;
-        case 6: FAR(6); break;
-        case 8: FAR(8); break;
-        case 10: FAR(10); break;
-        case 12: FAR(12); break;
-#define BIGH(V) case V: if constexpr (D < 5) { FAR(V); break; } else { set_error("half grid %d not compiled for d=5", V); return RBF_EUNSUPPORTED; }
-        BIGH(14)
-        BIGH(16)
-        BIGH(20)
-        BIGH(24)
-        BIGH(28)
-        BIGH(32)
-#undef BIGH
-        default: set_error("padded half grid %d not compiled", p->HP); return RBF_EUNSUPPORTED;
+int product_dispatch(int HP, const Work<T> &w, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh,
+                     int kernel, hipStream_t s, PhaseTimer &pt) {
+#define CASE_H(V) \
+    case V: return product_d<T, D, V>(w, nblocks, bstarts, p2m_sh, kernel, s, pt);
+    switch (HP) {
+        CASE_H(4)
+        CASE_H(6)
+        CASE_H(8)
+        CASE_H(10)
+        CASE_H(12)
+        default: break;
     }
-#undef FAR
-    return RBF_OK;
+    if constexpr (D < 5) {
+        switch (HP) {
+            CASE_H(14)
+            CASE_H(16)
+            CASE_H(20)
+            CASE_H(24)
+            CASE_H(28)
+            CASE_H(32)
+            default: break;
+        }
+    }
+#undef CASE_H
+    set_error("padded half grid %d not compiled for d=%d", HP, D);
+    return RBF_EUNSUPPORTED;
+}
+
+template <class T>
+int product_t(int d, int HP, const Work<T> &w, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh,
+              int kernel, hipStream_t s, PhaseTimer &pt) {
+    switch (d) {
+        case 2: return product_dispatch<T, 2>(HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
+        case 3: return product_dispatch<T, 3>(HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
+        case 5: return product_dispatch<T, 5>(HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
+    }
+    set_error("dimension %d not compiled", d);
+    return RBF_EUNSUPPORTED;
 }
 
 template <class T>
 int matvec_t(rbf_plan *p, const void *lam, void *u) {
+    Work<T> w{};
+    fill_desc<T>(p, &w.one);
+    w.nprob = 0;
+    w.lam = (const T *)lam;
+    w.u = (T *)u;
+    int64_t nb[PH_COUNT];
+    for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
     PhaseTimer pt(p);
-    int rc;
-    switch (p->d) {
-        case 2: rc = matvec_d<T, 2>(p, (const T *)lam, (T *)u, pt); break;
-        case 3: rc = matvec_d<T, 3>(p, (const T *)lam, (T *)u, pt); break;
-        case 5: rc = matvec_d<T, 5>(p, (const T *)lam, (T *)u, pt); break;
-        default: set_error("dimension %d not compiled", p->d); return RBF_EUNSUPPORTED;
-    }
-    if (rc != RBF_OK) return rc;
+    RBF_TRY(product_t<T>(p->d, p->HP, w, nb, nullptr, p2m_shmem<T>(w.one, p->d), p->kernel, p->stream, pt));
     if (p->profiling) {
         RBF_HIP(hipEventSynchronize(p->ev[2 * RBF_NPHASES - 1]));
         for (int k = 0; k < RBF_NPHASES; ++k) {
@@ -600,18 +750,13 @@ int matvec_t(rbf_plan *p, const void *lam, void *u) {
 
 template <class T, int D>
 int direct_d(rbf_plan *p, const T *lam, T *u) {
-    hipStream_t s = p->stream;
-    const int64_t n = p->n;
-    unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
-    k_gather<T><<<nb, kThreads, 0, s>>>(lam, p->perm, n, (T *)p->lam_s);
-    RBF_HIP(hipGetLastError());
-    const T coef = kernel_coef<T>(p->kernel, p->shape);
-    if (p->kernel == RBF_GAUSSIAN)
-        k_direct<T, D, RBF_GAUSSIAN><<<nb, kThreads, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s, coef, p->perm, u);
-    else
-        k_direct<T, D, RBF_MULTIQUADRIC><<<nb, kThreads, 0, s>>>((const T *)p->xs, n, (const T *)p->lam_s, coef,
-                                                                 p->perm, u);
-    RBF_HIP(hipGetLastError());
+    Work<T> w{};
+    fill_desc<T>(p, &w.one);
+    w.lam = lam;
+    w.u = u;
+    const int64_t nb = phase_blocks<T>(w.one, PH_DIRECT);
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_GATHER, nb, p->stream, 0, 0, p->kernel)));
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_DIRECT, nb, p->stream, 0, 0, p->kernel)));
     return RBF_OK;
 }
 
@@ -627,6 +772,80 @@ int direct_t(rbf_plan *p, const void *lam, void *u) {
 }
 
 }  // namespace
+
+template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
+    using C = typename cplx<T>::type;
+    d->xs = (const T *)p->xs;
+    d->n = p->n;
+    d->off = 0;
+    d->perm = p->perm;
+    d->leaf_begin = p->leaf_begin;
+    d->leaf_cell = p->leaf_cell;
+    d->near_ptr = p->near_ptr;
+    d->near_idx = p->near_idx;
+    d->src_ptr = p->src_ptr;
+    d->cell_begin = p->cell_leaf_begin;
+    d->src_rng = p->src_rng;
+    d->tasks = p->tasks;
+    d->nleaves = p->nleaves;
+    d->ntasks = p->ntasks;
+    d->ncells = p->ncells;
+    d->lc = p->lc;
+    d->r = p->r;
+    d->mn = p->mn;
+    d->H = p->H;
+    d->HP = p->HP;
+    d->R = (int)p->R;
+    d->P = p->P;
+    const double dxi = 2.0 * p->sigma / (p->mn - 1);
+    d->dxi = dxi;
+    d->xi0 = -p->sigma;
+    d->xiH = -p->sigma + p->H * dxi;
+    d->wc1 = p->wc1;
+    if (p->kernel == RBF_GAUSSIAN)
+        d->coef = (T)(-1.4426950408889634 / (2.0 * p->shape * p->shape));
+    else
+        d->coef = (T)(p->shape * p->shape);
+    d->lam_s = (T *)p->lam_s;
+    d->u_s = (T *)p->u_s;
+    d->W = (C *)p->W;
+    d->Lx = (C *)p->Lx;
+    d->Wc = (C *)p->Wc;
+    d->Lc = (C *)p->Lc;
+    d->Tmp = (C *)p->Tmp;
+    d->dl = (C *)p->dl;
+    d->wtab = p->wtab;
+    d->m2l_sched = p->m2l_sched;
+    const int bd = (p->d > 2) ? kThreads : kWave;
+    d->wpl = (int)((p->R + bd - 1) / bd);
+    const size_t per_point = sizeof(C) * (size_t)((p->d > 1 ? p->d - 1 : 1) * p->mn);
+    d->p2m_ch = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point));
+    d->far = p->far;
+}
+template void fill_desc<float>(const rbf_plan *, Desc<float> *);
+template void fill_desc<double>(const rbf_plan *, Desc<double> *);
+
+template <class T> int64_t desc_blocks(const Desc<T> &d, int phase) { return phase_blocks<T>(d, phase); }
+template int64_t desc_blocks<float>(const Desc<float> &, int);
+template int64_t desc_blocks<double>(const Desc<double> &, int);
+
+// Batched product for one group of problems sharing (d, HP, kernel): descriptors and
+// per-phase block prefixes are device arrays prepared by the batch planner.
+template <class T>
+int launch_batch_group(int d, int HP, int kernel, const Desc<T> *descs, int nprob, const int *const *bstarts,
+                       const int64_t *nblocks, size_t p2m_sh, const T *lam, T *u, hipStream_t s) {
+    Work<T> w{};
+    w.many = descs;
+    w.nprob = nprob;
+    w.lam = lam;
+    w.u = u;
+    PhaseTimer pt(nullptr);
+    return product_t<T>(d, HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
+}
+template int launch_batch_group<float>(int, int, int, const Desc<float> *, int, const int *const *, const int64_t *,
+                                       size_t, const float *, float *, hipStream_t);
+template int launch_batch_group<double>(int, int, int, const Desc<double> *, int, const int *const *,
+                                        const int64_t *, size_t, const double *, double *, hipStream_t);
 
 int launch_matvec(rbf_plan *p, const void *lambda, void *u) {
     return p->dtype == RBF_F32 ? matvec_t<float>(p, lambda, u) : matvec_t<double>(p, lambda, u);

@@ -1,0 +1,51 @@
+// Per-problem descriptor of the fast product: everything a kernel body reads, as plain
+// pointers and scalars, so that one problem or many (a batch) can be launched alike.
+#pragma once
+#include "internal.h"
+
+namespace rbf {
+
+enum Phase {
+    PH_GATHER = 0,
+    PH_P2P,
+    PH_PHASE_DL,
+    PH_P2M,
+    PH_M2M,
+    PH_M2L_AXIS,
+    PH_M2L_LEAF,
+    PH_L2P,
+    PH_DIRECT,
+    PH_COUNT
+};
+
+template <class T> struct Desc {
+    using C = typename cplx<T>::type;
+    const T *xs;            // sorted coordinates, SoA [d][n]
+    int64_t n;
+    int64_t off;            // offset of this problem in the caller's (concatenated) vectors
+    const int *perm, *leaf_begin, *leaf_cell, *near_ptr, *near_idx, *src_ptr, *cell_begin;
+    const int2 *src_rng, *tasks;
+    int nleaves, ntasks;
+    int64_t ncells;
+    int lc, r;
+    int mn, H, HP, R;
+    int64_t P;
+    double xi0, xiH, dxi;
+    const double *wc1;
+    T coef;
+    T *lam_s, *u_s;
+    C *W, *Lx, *Wc, *Lc, *Tmp, *dl;
+    int wpl;                // aggregation workgroups per leaf
+    int p2m_ch;             // aggregation point chunk
+    int far;                // 0: every kept pair is near (no far-field phases)
+    const double *wtab;     // w(xi) C(xi) per stored node [P]
+    int m2l_sched;          // block order of the leaf translation
+};
+
+template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);
+template <class T> int64_t desc_blocks(const Desc<T> &d, int phase);
+template <class T>
+int launch_batch_group(int d, int HP, int kernel, const Desc<T> *descs, int nprob, const int *const *bstarts,
+                       const int64_t *nblocks, size_t p2m_sh, const T *lam, T *u, hipStream_t s);
+
+}  // namespace rbf

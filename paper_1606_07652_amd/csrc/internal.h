@@ -70,6 +70,9 @@ struct rbf_plan {
     double sigma = 0, L = 0, rcut = 0, rfar = 0, ext = 0;
     double lo[rbf::kMaxDim] = {0, 0, 0, 0, 0};
     int nleaves = 0, nlevels = 0;
+    int far = 1;            // 0 when every kept pair is near (all leaves at lc, stencil radius <= 1)
+    int nodes_needed = 0;   // nodes per dimension the tolerance rule asked for
+    int min_leaf_level = 0, max_leaf_level = 0;
     int64_t ncells = 0, nnear = 0, near_pairs = 0, nranges = 0;
 
     // device arrays (owned by arena)
@@ -87,6 +90,8 @@ struct rbf_plan {
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
     int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    double *wtab = nullptr;          // quadrature weight times C(xi) per stored node [P]
+    int m2l_sched = 0;               // block order of the leaf translation
     int ntasks = 0;
     void *dl = nullptr;              // lambda-weighted last-dimension phases [n][HP] complex
     double *xi = nullptr;            // quadrature nodes [mn]
@@ -118,6 +123,8 @@ struct rbf_plan {
 };
 
 namespace rbf {
+int plan_create(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
+                const rbf_opts *opts, hipStream_t stream, rbf_plan **out);
 int build_tree(rbf_plan *p, const void *points);
 int build_near_lists(rbf_plan *p);
 int launch_matvec(rbf_plan *p, const void *lambda, void *u);

@@ -606,9 +606,12 @@ int tree_typed(rbf_plan *p, const void *points_v) {
     RBF_HIP(hipGetLastError());
     // wave tasks: (leaf, offset) for every 64 consecutive points of a leaf
     {
-        std::vector<int> hb(nleaves + 1);
+        std::vector<int> hb(nleaves + 1), hl(nleaves);
         RBF_HIP(hipMemcpyAsync(hb.data(), p->leaf_begin, sizeof(int) * (nleaves + 1), hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipMemcpyAsync(hl.data(), p->leaf_level, sizeof(int) * nleaves, hipMemcpyDeviceToHost, s));
         RBF_HIP(hipStreamSynchronize(s));
+        p->min_leaf_level = *std::min_element(hl.begin(), hl.end());
+        p->max_leaf_level = *std::max_element(hl.begin(), hl.end());
         std::vector<int2> tk;
         tk.reserve(nleaves + n / kWave + 1);
         for (int a = 0; a < nleaves; ++a)

@@ -33,13 +33,92 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _opts(n_max=0, max_level=0, min_level=0, coarse_level=-1, coarse_radius=-1, nodes=0, band=0.0,
+          m2l_schedule=0):
+    return L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
+
+
+def _opts_dict(o: "L.RbfOpts") -> dict:
+    return {"n_max": o.n_max, "max_level": o.max_level, "min_level": o.min_level, "coarse_level": o.coarse_level,
+            "coarse_radius": o.coarse_radius, "nodes": o.nodes, "band": o.band, "m2l_schedule": o.m2l_schedule}
+
+
+def autotune(points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05, tol: float = 1e-6,
+             reps: int = 3, stream: Optional[torch.cuda.Stream] = None, **base) -> tuple:
+    """Measure candidate configurations (rbf_fmm_autotune); returns (opts dict, ms per product)."""
+    lib = L.load()
+    stream = stream if stream is not None else torch.cuda.current_stream(points.device)
+    b = _opts(**base)
+    best = L.RbfOpts()
+    ms = ctypes.c_double()
+    L.check(lib.rbf_fmm_autotune(_ptr(points), points.shape[0], points.shape[1], _dtype_code(points),
+                                 _KERNELS[kernel], float(shape), float(tol), ctypes.byref(b), reps,
+                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best), ctypes.byref(ms)))
+    return _opts_dict(best), ms.value
+
+
+class BatchPlan:
+    """Many independent problems (concatenated points, per-problem shapes) in one batched
+    product per call (rbf_fmm_plan_batch / rbf_fmm_matvec_batch)."""
+
+    def __init__(self, points: torch.Tensor, offsets, shapes, kernel: str = "gaussian", tol: float = 1e-4,
+                 autotune: bool = False, stream: Optional[torch.cuda.Stream] = None, **opts):
+        lib = L.load()
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.shapes = np.ascontiguousarray(shapes, dtype=np.float64)
+        self.nprob = len(self.shapes)
+        if self.offsets.shape != (self.nprob + 1,) or self.offsets[-1] != points.shape[0]:
+            raise ValueError("offsets must have nprob + 1 entries ending at the number of points")
+        self.n, self.d = points.shape
+        self.dtype, self.device = points.dtype, points.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
+        o = _opts(**opts) if opts else None
+        h = ctypes.c_void_p()
+        L.check(lib.rbf_fmm_plan_batch(_ptr(points), self.offsets.ctypes.data, self.nprob, self.d,
+                                       _dtype_code(points), _KERNELS[kernel], self.shapes.ctypes.data, float(tol),
+                                       ctypes.byref(o) if o is not None else None, 1 if autotune else 0,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def matvec(self, lam: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if lam.shape != (self.n,) or lam.dtype != self.dtype:
+            raise ValueError("lambda must be the concatenated vector of all problems")
+        if out is None:
+            out = torch.empty_like(lam)
+        L.check(L.load().rbf_fmm_matvec_batch(self._h, _ptr(lam), _ptr(out)))
+        return out
+
+    def set_graph(self, on: bool):
+        L.check(L.load().rbf_fmm_batch_set_graph(self._h, 1 if on else 0))
+
+    def info(self) -> dict:
+        inf = L.RbfBatchInfo()
+        nm = np.empty(self.nprob, np.int32)
+        nd = np.empty(self.nprob, np.int32)
+        L.check(L.load().rbf_fmm_batch_info(self._h, ctypes.byref(inf), nm.ctypes.data, nd.ctypes.data))
+        out = {name: getattr(inf, name) for name, _ in L.RbfBatchInfo._fields_}
+        out["n_max"], out["nodes"] = nm, nd
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().rbf_fmm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class FmmPlan:
     """Plan for u = A lambda with A_ij = Phi(x_i - x_j) on a fixed point set."""
 
     def __init__(self, points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05,
                  tol: float = 1e-6, n_max: int = 0, max_level: int = 0, min_level: int = 0,
                  coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0, band: float = 0.0,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 m2l_schedule: int = 0, stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         if points.dim() != 2:
             raise ValueError("points must be (n, d)")
@@ -47,7 +126,7 @@ class FmmPlan:
         self.dtype = points.dtype
         self.device = points.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
-        opts = L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
         h = ctypes.c_void_p()
         L.check(lib.rbf_fmm_plan(_ptr(points), self.n, self.d, _dtype_code(points), _KERNELS[kernel],
                                  float(shape), float(tol), ctypes.byref(opts),

@@ -1,0 +1,133 @@
+"""Batched products, the autotuner and near-only plans (GPU, through the C ABI)."""
+import numpy as np
+import pytest
+
+from oracle import direct, splitref
+from workloads import normal_weights, uniform_points
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def small_batch(nprob=12, seed=5):
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(300, 6000, nprob)
+    ss = np.exp(rng.uniform(np.log(0.02), np.log(0.1), nprob))
+    pts = [uniform_points(int(n), 3, 1000 + q) for q, n in enumerate(ns)]
+    lams = [normal_weights(int(n), 2000 + q) for q, n in enumerate(ns)]
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    return pts, lams, ss, off
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-6), (torch.float32, 1e-4)])
+def test_batch_equals_single_plans(dtype, tol):
+    """The batched launch runs the same kernels on the same descriptors: results are
+    identical to one plan per problem, and each meets the tolerance of the direct sum."""
+    from paper_1606_07652_amd import BatchPlan, FmmPlan
+    pts, lams, ss, off = small_batch()
+    X = dev(np.concatenate(pts), dtype)
+    lam = dev(np.concatenate(lams), dtype)
+    print(f"[batch] {len(ss)} problems, n={off[-1]}, {dtype}", flush=True)
+    b = BatchPlan(X, off, ss, kernel="gaussian", tol=tol, n_max=64)
+    u = b.matvec(lam).double().cpu().numpy()
+    for q in range(len(ss)):
+        sl = slice(off[q], off[q + 1])
+        p = FmmPlan(X[sl].contiguous(), kernel="gaussian", shape=float(ss[q]), tol=tol, n_max=64)
+        uq = p.matvec(lam[sl].contiguous()).double().cpu().numpy()
+        assert np.array_equal(u[sl], uq), q
+        xs = X[sl].double().cpu().numpy()
+        ls = lam[sl].double().cpu().numpy()
+        ref = direct.direct_sum(xs, ls, "gaussian", float(ss[q]))
+        assert direct.rel_l2(u[sl], ref) <= tol, q
+        p.close()
+    b.close()
+
+
+def test_graph_replays_match_eager():
+    """Graph replays (same vectors, new contents, eager work in between) equal direct launches."""
+    from paper_1606_07652_amd import BatchPlan
+    pts, lams, ss, off = small_batch(8, 7)
+    X = dev(np.concatenate(pts), torch.float32)
+    b = BatchPlan(X, off, ss, kernel="gaussian", tol=1e-4, n_max=64)
+    lam = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
+    out_g = torch.empty_like(lam)
+    out_e = torch.empty_like(lam)
+    for it in range(4):
+        torch.manual_seed(it)
+        lam.copy_(torch.randn(int(off[-1]), device="cuda"))
+        b.set_graph(True)
+        b.matvec(lam, out_g)
+        junk = (lam * 2.0).sum()          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        b.set_graph(False)
+        b.matvec(lam, out_e)
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, out_e), it
+        assert torch.isfinite(junk)
+    # new output pointer: the graph is captured again
+    b.set_graph(True)
+    out2 = b.matvec(lam)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out_e)
+    b.close()
+
+
+def test_autotuned_batch_meets_tolerance():
+    from paper_1606_07652_amd import BatchPlan
+    pts, lams, ss, off = small_batch(6, 11)
+    ss = np.array([0.01, 0.1, 0.03, 0.015, 0.06, 0.02])
+    X = dev(np.concatenate(pts), torch.float32)
+    lam = dev(np.concatenate(lams), torch.float32)
+    b = BatchPlan(X, off, ss, kernel="gaussian", tol=1e-4, autotune=True)
+    inf = b.info()
+    print(f"[autotune batch] n_max={inf['n_max']} nodes={inf['nodes']} far={inf['nfar']}", flush=True)
+    u = b.matvec(lam).double().cpu().numpy()
+    for q in range(len(ss)):
+        sl = slice(off[q], off[q + 1])
+        xs = X[sl].double().cpu().numpy()
+        ls = lam[sl].double().cpu().numpy()
+        ref = direct.direct_sum(xs, ls, "gaussian", float(ss[q]))
+        assert direct.rel_l2(u[sl], ref) <= 1e-4, q
+    b.close()
+
+
+def test_near_only_plan_is_exact_split():
+    """Narrow Gaussian on a uniform tree at the pruning level: every kept pair is near, so
+    the product equals the oracle's split reference (which then has no far pairs)."""
+    from paper_1606_07652_amd import FmmPlan
+    x = uniform_points(4000, 3, 21)
+    lam = normal_weights(4000, 22)
+    s = 0.01
+    kw = dict(n_max=1 << 30, min_level=4, max_level=4, coarse_level=4, coarse_radius=1, nodes=4)
+    p = FmmPlan(dev(x, torch.float64), kernel="gaussian", shape=s, tol=1e-6, **kw)
+    assert p.info()["far_field"] == 0
+    u = p.matvec(dev(lam, torch.float64)).cpu().numpy()
+    ref = splitref.split_reference(x, lam, "gaussian", s, n_max=1 << 30, lc=4, r=1, sigma=100.0, mn=4,
+                                   max_level=4)
+    assert np.max(np.abs(u - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert direct.rel_l2(u, direct.direct_sum(x, lam, "gaussian", s)) < 1e-6
+
+
+def test_autotune_single_problem():
+    from paper_1606_07652_amd import FmmPlan, autotune
+    x = uniform_points(20000, 3, 31)
+    lam = normal_weights(20000, 32)
+    X = dev(x, torch.float32)
+    opts, ms = autotune(X, kernel="gaussian", shape=0.03, tol=1e-4, reps=2)
+    print(f"[autotune] {opts} {ms:.3f} ms", flush=True)
+    assert ms > 0
+    p = FmmPlan(X, kernel="gaussian", shape=0.03, tol=1e-4, **opts)
+    u = p.matvec(dev(lam, torch.float32)).double().cpu().numpy()
+    ref = direct.direct_sum(x.astype(np.float32).astype(np.float64), lam.astype(np.float32).astype(np.float64),
+                            "gaussian", 0.03)
+    assert direct.rel_l2(u, ref) <= 1e-4
