@@ -46,7 +46,10 @@ def phase_model(info, dtype_bytes, n):
         "l2p": ("alu", 8.0 * n * P),
         "m2m": ("hbm", (nl + nc) * P * cb),
         "m2l_coarse": ("hbm", 2.0 * d * nc * P * cb),
-        "m2l_leaf": ("hbm", (info["nnear"] + 2.0 * nl) * P * cb),
+        # compulsory bytes: every leaf expansion read once, every coarse local expansion
+        # read once, every leaf local expansion written once (the near-list re-reads are
+        # meant to hit in L2 and are not counted)
+        "m2l_leaf": ("hbm", (2.0 * nl + nc) * P * cb),
         "permute": ("hbm", n * (2 * dtype_bytes + 4)),
     }
 
