@@ -90,8 +90,9 @@ typedef struct rbf_solve_opts {
     int    max_iters;    /* total inner-iteration cap (default 1000) */
     int    precond;      /* RBF_PC_NONE, RBF_PC_BLOCK_JACOBI or RBF_PC_LEARNED */
     int    zero_init;    /* nonzero: start from lambda = 0, else from the given lambda */
-    int    fallback;     /* nonzero: on breakdown, stagnation or non-finite output of the
-                            preconditioner, restart without it (default on) */
+    int    fallback;     /* nonzero: on a non-finite preconditioner output or a restart cycle
+                            that did not reduce the true residual, step down one
+                            preconditioner (learned -> block-Jacobi -> none) and restart */
     double time_limit_s; /* wall-time cap in seconds (0 = none) */
     int    reserved[8];
 } rbf_solve_opts;
@@ -100,7 +101,7 @@ typedef struct rbf_solve_info {
     int    iters;        /* inner iterations (matrix-vector products inside Arnoldi) */
     int    restarts;
     int    converged;
-    int    fallback_used;/* 1 if the preconditioner was switched off during the solve */
+    int    fallback_used;/* number of preconditioner step-downs during the solve */
     double true_res;     /* ||f - A lambda|| / ||f|| with a fresh product at exit */
     double seconds;      /* wall time of the solve */
     double history[256]; /* true relative residual at each restart (first 256) */
@@ -204,6 +205,116 @@ typedef struct rbf_batch_info {
  * problem's leaf capacity and nodes per dimension (0 for near-only problems). */
 int rbf_fmm_batch_info(const rbf_batch *batch, rbf_batch_info *info, int32_t *n_max, int32_t *nodes);
 int rbf_fmm_batch_destroy(rbf_batch *batch);
+
+/* ---- right preconditioners of the solve ----------------------------------------------
+ * Neither preconditioner is part of the paper (which names GMRES and says nothing about
+ * preconditioning); rbf_interp_solve applies them as right preconditioners of flexible
+ * GMRES, so a nonlinear map is allowed.
+ *
+ * Blocks: the plan's points in its Morton order are cut into blocks of RBF_PC_BLOCK
+ * consecutive points; block b holds sorted points [64 b, min(64 b + 64, n)).
+ *
+ * Block-Jacobi: y_b = (A_bb + reg I)^{-1} v_b for every block, A_bb the exact kernel
+ * matrix of the block's points (built in FP64 by Gauss-Jordan elimination in LDS, stored
+ * as one explicit 64 x 64 FP64 inverse per block: 32 KiB per block).
+ *
+ * Learned: z_b = y_b + s_b g(y_b / s_b), y the block solve of v with the feature
+ * regularisation (rbf_pc_learned_features), s_b = ||y_b||_2 (z_b = 0 if s_b = 0), with g the
+ * network below evaluated in BF16 with FP32 accumulation.  Trained on pairs (r, e) of a
+ * residual and its error e = A^{-1} r to make z close to e.  In rbf_interp_solve a
+ * GMRES(m) cycle with the learned preconditioner is block-Jacobi FGMRES for its first
+ * m - 1 directions and takes z_{m-1} = learned(v_0) last (v_0 is the normalised residual,
+ * the kind of vector the network is trained on): the cycle minimises the residual over
+ * the block-Jacobi Krylov directions augmented with the learned error estimate.
+ */
+#define RBF_PC_BLOCK 64
+#define RBF_MLP_IN 64
+#define RBF_MLP_HIDDEN 256
+#define RBF_MLP_NPARAMS 164672
+enum { RBF_MLP_BF16 = 0, RBF_MLP_F32 = 1 };
+
+/* Build (or rebuild) the block-Jacobi inverses with regularisation reg >= 0 (reg < 0: the
+ * default, reg = 1e-2 Phi(0)).  Synchronous.  RBF_EINVAL if a block is numerically
+ * singular at this reg (a pivot <= 0). */
+int rbf_pc_block_jacobi(rbf_plan *plan, double reg);
+/* Build the block inverses that form the learned map's features y (and those of
+ * rbf_pc_pairs / rbf_pc_harvest) with their own regularisation (reg < 0: the default,
+ * 1e-6 Phi(0)).  A network is trained on the features of one reg and should be applied
+ * with the same.  Storage is shared with block-Jacobi when the two regs agree. */
+int rbf_pc_learned_features(rbf_plan *plan, double reg);
+
+/* z = M^{-1} v for kind RBF_PC_BLOCK_JACOBI or RBF_PC_LEARNED.
+ *   v, z  device FP64, length n, caller's point order, not aliased.
+ * Builds the block inverses with the default reg if none exist.  RBF_ESTATE for
+ * RBF_PC_LEARNED without an attached network.  Enqueued on the plan's stream. */
+int rbf_pc_apply(rbf_plan *plan, int kind, const double *v, double *z);
+
+/* Multilayer perceptron g: R^64 -> R^64, hidden layers of 256 units with ReLU, affine
+ * output.  Parameters: host or device FP32 vector of RBF_MLP_NPARAMS values in the order
+ * W1 (256 x 64, row-major [out][in]), b1 (256), W2 (256 x 256), b2, W3 (256 x 256), b3,
+ * W4 (64 x 256), b4 (64).  The handle owns FP32 master weights, a BF16 copy for inference
+ * and Adam state on the current device. */
+typedef struct rbf_mlp rbf_mlp;
+/* params: host, may be NULL: then hidden weights are He-uniform from `seed`, biases and the
+ * output layer zero (g = 0).  Synchronous. */
+int rbf_mlp_create(const float *params, uint64_t seed, rbf_mlp **out);
+int rbf_mlp_destroy(rbf_mlp *mlp);
+/* params: host float[RBF_MLP_NPARAMS].  Synchronous. */
+int rbf_mlp_get_params(const rbf_mlp *mlp, float *params);
+/* Versioned binary weight file: 8-byte magic "RBF-MLP\0", uint32 version (1), uint32 layer
+ * count (4), uint32 widths 64 256 256 256 64, uint32 activation (1 = ReLU), uint64 parameter
+ * count, then the FP32 parameters, little-endian.  rbf_mlp_load rejects any other layout
+ * with RBF_EINVAL. */
+int rbf_mlp_save(const rbf_mlp *mlp, const char *path);
+int rbf_mlp_load(const char *path, rbf_mlp **out);
+/* y = g(x) for `rows` rows: x device float[rows][64], y device float[rows][64].
+ * precision RBF_MLP_BF16: the inference kernel (BF16 MFMA, FP32 accumulation);
+ * RBF_MLP_F32: the FP32 training kernels.  Enqueued on `stream`. */
+int rbf_mlp_forward(rbf_mlp *mlp, const float *x, int64_t rows, float *y, int precision, void *stream);
+/* Loss L = sum_r w_r ||g(x_r) - t_r||^2 / sum_r w_r of the rows (1 <= rows <= 2^20) in
+ * FP32 and its gradient dL/dparams.  x, t device float[rows][64], w device float[rows];
+ * loss host (may be NULL), grad host float[RBF_MLP_NPARAMS] (may be NULL).  Synchronous. */
+int rbf_mlp_loss_grad(rbf_mlp *mlp, const float *x, const float *t, const float *w, int64_t rows,
+                      double *loss, float *grad, void *stream);
+typedef struct rbf_train_opts {
+    int      epochs;     /* passes over the training rows (default 100) */
+    int      batch;      /* rows per Adam step (default 512) */
+    int      patience;   /* stop after this many epochs without a better held-out loss (0 = never) */
+    int      reserved0;
+    double   lr, beta1, beta2, eps;  /* Adam (defaults 1e-3, 0.9, 0.999, 1e-8) */
+    double   val_frac;   /* the last floor(val_frac * rows) rows are held out (0 <= val_frac < 1) */
+    uint64_t seed;       /* shuffle of the training rows */
+    int      reserved[8];
+} rbf_train_opts;
+typedef struct rbf_train_info {
+    int    epochs_run, best_epoch, nhist, reserved0;
+    double init_val_loss, best_val_loss, final_train_loss, seconds;
+    double train_loss[256], val_loss[256];   /* per epoch (first 256) */
+} rbf_train_info;
+/* Minibatch Adam on rows (x, t, w) as in rbf_mlp_loss_grad (device arrays).  With held-out
+ * rows the parameters with the lowest held-out loss are kept (the initial ones included).
+ * opts may be NULL, info may be NULL.  Synchronous. */
+int rbf_mlp_train(rbf_mlp *mlp, const float *x, const float *t, const float *w, int64_t rows,
+                  const rbf_train_opts *opts, void *stream, rbf_train_info *info);
+
+/* Attach a network for RBF_PC_LEARNED (NULL detaches).  The plan keeps the pointer; the
+ * network must outlive its use by the plan. */
+int rbf_pc_set_learned(rbf_plan *plan, rbf_mlp *mlp);
+/* Training rows of one (residual, error) pair, one row per block:
+ *   r, e   device FP64, length n, caller order (e the error of which r is the residual)
+ *   x, t   device float[nblk][64]: x_b = y_b / s_b, t_b = (e_b - y_b) / s_b (Morton order
+ *          within the block, zero-padded), y = block-Jacobi output of r, s_b = ||y_b||
+ *   w      device float[nblk]: s_b^2 / ||e||^2, 0 for a short last block or s_b = 0
+ * nblk = ceil(n / 64).  Builds the block inverses with the default reg if none exist. */
+int rbf_pc_pairs(rbf_plan *plan, const double *r, const double *e, float *x, float *t, float *w);
+/* Training rows from solves of A lambda = f (f device, plan dtype, caller order):
+ * lambda* from GMRES(50) to rtol (at most max_iters iterations) with preconditioner
+ * `precond` (RBF_PC_NONE or RBF_PC_BLOCK_JACOBI), then for each cap k in caps (host
+ * int[ncaps], k >= 0) lambda_k after k iterations from zero with the same solver,
+ * e_k = lambda* - lambda_k and r_k = A e_k with the fast product.  Rows of cap c go to
+ * x + c nblk 64, t + c nblk 64, w + c nblk (device, sized ncaps nblk rows).  Synchronous. */
+int rbf_pc_harvest(rbf_plan *plan, const void *f, double rtol, int max_iters, int precond, const int *caps,
+                   int ncaps, float *x, float *t, float *w);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,8 @@ RBF_F32, RBF_F64 = 0, 1
 RBF_GAUSSIAN, RBF_MULTIQUADRIC = 0, 1
 RBF_PC_NONE, RBF_PC_BLOCK_JACOBI, RBF_PC_LEARNED = 0, 1, 2
 RBF_NPHASES = 7
+RBF_PC_BLOCK, RBF_MLP_IN, RBF_MLP_HIDDEN, RBF_MLP_NPARAMS = 64, 64, 256, 164672
+RBF_MLP_BF16, RBF_MLP_F32 = 0, 1
 PHASES = ["permute", "p2p", "p2m", "m2m", "m2l_coarse", "m2l_leaf", "l2p"]
 
 
@@ -50,6 +52,21 @@ class RbfBatchInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double)]
 
 
+class RbfTrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("patience", ctypes.c_int),
+                ("reserved0", ctypes.c_int), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("val_frac", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int * 8)]
+
+
+class RbfTrainInfo(ctypes.Structure):
+    _fields_ = [("epochs_run", ctypes.c_int), ("best_epoch", ctypes.c_int), ("nhist", ctypes.c_int),
+                ("reserved0", ctypes.c_int), ("init_val_loss", ctypes.c_double), ("best_val_loss", ctypes.c_double),
+                ("final_train_loss", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("train_loss", ctypes.c_double * 256), ("val_loss", ctypes.c_double * 256)]
+
+
+_P = ctypes.c_void_p
 # name -> (restype, argtypes)
 SIGNATURES = {
     "rbf_fmm_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -77,6 +94,22 @@ SIGNATURES = {
     "rbf_fmm_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfBatchInfo), ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "rbf_fmm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rbf_pc_block_jacobi": (ctypes.c_int, [_P, ctypes.c_double]),
+    "rbf_pc_learned_features": (ctypes.c_int, [_P, ctypes.c_double]),
+    "rbf_pc_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "rbf_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "rbf_mlp_destroy": (ctypes.c_int, [_P]),
+    "rbf_mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "rbf_mlp_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "rbf_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "rbf_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int, _P]),
+    "rbf_mlp_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), _P, _P]),
+    "rbf_mlp_train": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(RbfTrainOpts), _P,
+                                     ctypes.POINTER(RbfTrainInfo)]),
+    "rbf_pc_set_learned": (ctypes.c_int, [_P, _P]),
+    "rbf_pc_pairs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "rbf_pc_harvest": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P, _P,
+                                      _P]),
 }
 
 _lib = None

@@ -284,6 +284,7 @@ int rbf_fmm_destroy(rbf_plan *plan) {
     (void)hipStreamSynchronize(plan->stream);
     for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (plan->ev[k]) (void)hipEventDestroy(plan->ev[k]);
     plan->solver_arena.release();
+    plan->pc_arena.release();
     plan->arena.release();
     delete plan;
     return RBF_OK;
@@ -300,7 +301,7 @@ int rbf_fmm_plan_info(const rbf_plan *p, rbf_plan_info *info) {
     info->shape = p->shape; info->tol = p->tol; info->band = p->sigma; info->period = p->L;
     info->rcut = p->rcut; info->rfar = p->rfar; info->ext = p->ext;
     for (int k = 0; k < kMaxDim; ++k) info->lo[k] = p->lo[k];
-    info->device_bytes = p->arena.bytes + p->solver_arena.bytes;
+    info->device_bytes = p->arena.bytes + p->solver_arena.bytes + p->pc_arena.bytes;
     info->far_field = p->far;
     return RBF_OK;
 }

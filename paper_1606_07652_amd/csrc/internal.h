@@ -118,8 +118,21 @@ struct rbf_plan {
     double *sv = nullptr;            // small device vectors (dots, norms)
     void *tvec = nullptr;            // plan-dtype vectors for products [3][n]
 
-    // learned preconditioner (optional)
-    void *pc = nullptr;
+    // right preconditioners of the solve (built on first use)
+    rbf::Arena pc_arena;
+    int64_t nblk = 0;                // 64-point blocks of the Morton order
+    double bj_reg = -1.0;            // regularisation of the block-Jacobi inverses (< 0: none built)
+    double *bj_inv = nullptr;        // (A_bb + reg I)^{-1}, column-major 64 x 64 per block
+    double lp_reg = -1.0;            // regularisation of the learned map's feature inverses
+    double *lp_inv = nullptr;        // same layout; aliases bj_inv when the two regs agree
+    double *lp_own = nullptr;        // separate storage for lp_inv when they differ
+    double *pc_y = nullptr;          // block-Jacobi output, Morton order [n]
+    double *pc_s = nullptr;          // block norms [nblk]
+    float *pc_x = nullptr;           // network input rows [nblk][64]
+    float *pc_g = nullptr;           // network output rows [nblk][64]
+    int *pc_flag = nullptr;          // device status word of the block factorisation
+    double *pc_scal = nullptr;       // device scalars (||e||^2 of the pair builder)
+    rbf_mlp *mlp = nullptr;          // learned correction (not owned)
 };
 
 namespace rbf {
@@ -129,4 +142,7 @@ int build_tree(rbf_plan *p, const void *points);
 int build_near_lists(rbf_plan *p);
 int launch_matvec(rbf_plan *p, const void *lambda, void *u);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);
+int pc_ready(rbf_plan *p, int kind);                                 // pc.hip
+int pc_apply(rbf_plan *p, int kind, const double *v, double *z);     // pc.hip
+int mlp_infer_bf16(rbf_mlp *m, const float *x, int64_t rows, float *y, hipStream_t s);   // mlp.hip
 }  // namespace rbf

@@ -17,9 +17,6 @@
 #include "internal.h"
 
 namespace rbf {
-int pc_apply(rbf_plan *p, const double *v, double *z);   // learned / block preconditioners (pc.hip)
-int pc_ready(rbf_plan *p, int kind);
-
 namespace {
 
 constexpr int kThreads = 256;
@@ -190,7 +187,11 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     std::memset(&inf, 0, sizeof(inf));
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(m + 2), hh2(m + 2);
     int its = 0, restarts = 0;
-    bool use_pc = pck != RBF_PC_NONE;
+    int cur = pck;   // active preconditioner: steps down learned -> block-Jacobi -> none
+    auto step_down = [&]() {
+        cur = cur == RBF_PC_LEARNED ? RBF_PC_BLOCK_JACOBI : RBF_PC_NONE;
+        ++inf.fallback_used;
+    };
     double best = INFINITY;
     double last_cycle_res = INFINITY;
     if (bnorm == 0.0) {
@@ -207,10 +208,8 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         best = std::min(best, rel);
         double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         if (!(rel > rtol) || its >= maxit || (tlim > 0 && el >= tlim) || !std::isfinite(rel)) break;
-        if (use_pc && fallback && restarts > 0 && rel > 0.999 * last_cycle_res) {
-            use_pc = false;   // preconditioned cycle did not reduce the true residual
-            inf.fallback_used = 1;
-        }
+        if (cur != RBF_PC_NONE && fallback && restarts > 0 && rel > 0.999 * last_cycle_res)
+            step_down();   // the preconditioned cycle did not reduce the true residual
         last_cycle_res = rel;
         k_scale<<<nb, kThreads, 0, s>>>(S.rd, 1.0 / beta, p->V, n);
         RBF_HIP(hipGetLastError());
@@ -219,11 +218,24 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         g[0] = beta;
         int k = 0;
         bool pc_failed = false;
+        const bool use_pc = cur != RBF_PC_NONE;
         for (int j = 0; j < m; ++j) {
             double *vj = p->V + (size_t)j * n;
             double *zj = use_pc ? p->Z + (size_t)j * n : vj;
             if (use_pc) {
-                RBF_TRY(pc_apply(p, vj, zj));
+                // Flexible GMRES accepts any direction z_j.  With the learned map the cycle
+                // is block-Jacobi FGMRES except for its last direction, z_{m-1} =
+                // learned(v_0): the network is trained on residuals and v_0 is the
+                // normalised residual (the cycle's space is augmented with the learned
+                // error estimate, the block-Jacobi directions before it are unchanged).
+                int kind = cur;
+                const double *src = vj;
+                if (cur == RBF_PC_LEARNED) {
+                    const bool last = j == m - 1 && m > 1;
+                    kind = last ? RBF_PC_LEARNED : RBF_PC_BLOCK_JACOBI;
+                    if (last) src = p->V;
+                }
+                RBF_TRY(pc_apply(p, kind, src, zj));
                 int hf = 0;
                 RBF_HIP(hipMemsetAsync(S.flag, 0, sizeof(int), s));
                 k_isfinite<<<nb, kThreads, 0, s>>>(zj, n, S.flag);
@@ -263,8 +275,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         }
         if (pc_failed) {
             if (!fallback) { set_error("rbf_interp_solve: preconditioner produced non-finite values"); return RBF_EINVAL; }
-            use_pc = false;
-            inf.fallback_used = 1;
+            step_down();
             ++restarts;
             continue;
         }

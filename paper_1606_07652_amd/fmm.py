@@ -170,7 +170,7 @@ class FmmPlan:
                                          ctypes.byref(info))
         L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
         return lam, {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
-                     "fallback_used": bool(info.fallback_used), "true_res": info.true_res,
+                     "fallback_used": int(info.fallback_used), "true_res": info.true_res,
                      "seconds": info.seconds, "history": list(info.history[:info.nhistory])}
 
     # -- introspection ---------------------------------------------------------------

@@ -41,24 +41,49 @@ def test_binding_declares_the_same_functions():
     assert set(_lib.SIGNATURES) == set(declared_functions())
 
 
-def test_binding_struct_sizes_match_header():
-    """The ctypes structs must match the C layout (sizes computed by the C compiler)."""
+STRUCTS = {"rbf_opts": "RbfOpts", "rbf_solve_opts": "RbfSolveOpts", "rbf_solve_info": "RbfSolveInfo",
+           "rbf_plan_info": "RbfPlanInfo", "rbf_batch_info": "RbfBatchInfo", "rbf_train_opts": "RbfTrainOpts",
+           "rbf_train_info": "RbfTrainInfo"}
+
+
+def test_binding_struct_layouts_match_header():
+    """Every ctypes struct has the C size and every field the C offset (computed by gcc)."""
     import subprocess
     import tempfile
     from paper_1606_07652_amd import _lib
-    src = r'''
-#include <stdio.h>
-#include "rbf_fmm.h"
-int main(void){printf("%zu %zu %zu %zu\n", sizeof(rbf_opts), sizeof(rbf_solve_opts), sizeof(rbf_solve_info), sizeof(rbf_plan_info));return 0;}
-'''
+    lines, expect = [], []
+    for cname, pyname in STRUCTS.items():
+        st = getattr(_lib, pyname)
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(st))
+        for fname, _ in st._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(st, fname).offset)
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"rbf_fmm.h\"\nint main(void){" + "".join(lines) + "return 0;}\n"
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "s")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
-        sizes = [int(v) for v in subprocess.check_output([exe]).split()]
-    assert sizes == [ctypes.sizeof(_lib.RbfOpts), ctypes.sizeof(_lib.RbfSolveOpts),
-                     ctypes.sizeof(_lib.RbfSolveInfo), ctypes.sizeof(_lib.RbfPlanInfo)]
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert got == expect
+
+
+def test_header_constants_match_binding():
+    import subprocess
+    import tempfile
+    from paper_1606_07652_amd import _lib
+    names = ["RBF_PC_BLOCK", "RBF_MLP_IN", "RBF_MLP_HIDDEN", "RBF_MLP_NPARAMS", "RBF_MLP_BF16", "RBF_MLP_F32",
+             "RBF_PC_NONE", "RBF_PC_BLOCK_JACOBI", "RBF_PC_LEARNED", "RBF_NPHASES", "RBF_ESTATE"]
+    src = "#include <stdio.h>\n#include \"rbf_fmm.h\"\nint main(void){" + "".join(
+        f'printf("%ld\\n", (long)({n}));' for n in names) + "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "s")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert got == [getattr(_lib, n) for n in names]
 
 
 def test_product_path_fails_loudly_without_library(monkeypatch):

@@ -1,0 +1,293 @@
+"""Preconditioners and the network (GPU, through the C ABI) against the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import precond as P
+from workloads import jittered_grid, mixed_points, normal_weights, uniform_points
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rand_params(seed, out_scale=1.0):
+    """He-normal hidden layers, small biases, output layer scaled by out_scale (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (i, o) in enumerate(P.LAYERS):
+        sc = np.sqrt(2.0 / i) * (out_scale if l == 3 else 1.0)
+        parts.append(rng.normal(0, sc, (o, i)).ravel())
+        parts.append(rng.normal(0, 0.05, o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_block_jacobi_matches_oracle(dtype):
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    x = uniform_points(3000, 3, 41)                    # 46 full blocks and a ragged one of 56
+    v = normal_weights(3000, 42)
+    s, reg = 0.05, 1e-3
+    print(f"[pc] block-Jacobi n=3000 {dtype}", flush=True)
+    plan = FmmPlan(dev(x, dtype), kernel="gaussian", shape=s, tol=1e-6 if dtype == torch.float64 else 1e-4)
+    pc.block_jacobi(plan, reg)
+    z = pc.apply(plan, "block_jacobi", dev(v)).cpu().numpy()
+    xo = x.astype(np.float32).astype(np.float64) if dtype == torch.float32 else x
+    inv, perm = P.block_inverses(xo, "gaussian", s, reg)
+    assert rel(z, P.bj_apply(inv, perm, v)) <= 1e-10
+
+
+def test_block_jacobi_clustered_points():
+    """Blob points (nearly singular blocks): the default regularisation 1e-2 and 1e-6."""
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    x = mixed_points(2000, 3, 43)
+    v = normal_weights(2000, 44)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.03, tol=1e-6)
+    z = pc.apply(plan, "block_jacobi", dev(v)).cpu().numpy()     # builds with the default
+    inv, perm = P.block_inverses(x, "gaussian", 0.03, 1e-2)
+    assert rel(z, P.bj_apply(inv, perm, v)) <= 1e-11
+    pc.block_jacobi(plan, 1e-6)
+    z = pc.apply(plan, "block_jacobi", dev(v)).cpu().numpy()
+    inv, perm = P.block_inverses(x, "gaussian", 0.03, 1e-6)
+    # conditioning of the regularised blocks is at most ~64 / 1e-6: rounding error ~1e-9
+    assert rel(z, P.bj_apply(inv, perm, v)) <= 1e-7
+
+
+def test_mlp_forward_matches_oracle():
+    from paper_1606_07652_amd.pc import Mlp
+    params = rand_params(51)
+    m = Mlp(params)
+    rows = 300                                           # 9 full groups of 32 rows and a ragged 12
+    X = np.random.default_rng(52).normal(0, 1, (rows, 64)).astype(np.float32)
+    p64 = params.astype(np.float64)
+    x64 = X.astype(np.float64)
+    ref_bf, _ = P.forward(p64, x64, bf16=True)
+    ref, _ = P.forward(p64, x64)
+    g_bf = m.forward(dev(X, torch.float32), "bf16").cpu().numpy()
+    g_32 = m.forward(dev(X, torch.float32), "f32").cpu().numpy()
+    print(f"[mlp] bf16 vs emulated {rel(g_bf, ref_bf):.2e}, vs fp64 {rel(g_bf, ref):.2e}, "
+          f"f32 vs fp64 {rel(g_32, ref):.2e}", flush=True)
+    # same roundings on both sides, FP32 vs FP64 accumulation; a flipped activation rounding
+    # moves one hidden value by one bfloat16 step (2^-8 relative)
+    assert rel(g_bf, ref_bf) <= 5e-4
+    assert rel(g_bf, ref) <= 3e-2
+    assert rel(g_32, ref) <= 1e-5
+    m.close()
+
+
+def test_mlp_gradient_matches_oracle():
+    from paper_1606_07652_amd.pc import Mlp
+    params = rand_params(53)
+    m = Mlp(params)
+    rng = np.random.default_rng(54)
+    rows = 700                                           # ragged against 64-row tiles and 256-row chunks
+    X = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    T = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    w = rng.uniform(0.0, 2.0, rows).astype(np.float32)
+    w[::17] = 0.0
+    loss, g = m.loss_grad(dev(X, torch.float32), dev(T, torch.float32), dev(w, torch.float32))
+    lref, gref = P.grad(params.astype(np.float64), X.astype(np.float64), T.astype(np.float64), w.astype(np.float64))
+    assert abs(loss - lref) <= 1e-5 * lref
+    k = 0
+    for i, o in P.LAYERS:
+        for size in (i * o, o):
+            e = rel(g[k:k + size], gref[k:k + size])
+            assert e <= 1e-3, (k, size, e)
+            k += size
+    m.close()
+
+
+def test_adam_step_matches_oracle():
+    from paper_1606_07652_amd.pc import Mlp
+    params = rand_params(55)
+    m = Mlp(params)
+    rng = np.random.default_rng(56)
+    rows, lr = 256, 1e-3
+    X = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    T = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, rows).astype(np.float32)
+    info = m.train(dev(X, torch.float32), dev(T, torch.float32), dev(w, torch.float32), epochs=1, batch=rows,
+                   lr=lr, val_frac=0.0)
+    assert info["epochs_run"] == 1
+    step = m.params().astype(np.float64) - params.astype(np.float64)
+    p64 = params.astype(np.float64)
+    _, g = P.grad(p64, X.astype(np.float64), T.astype(np.float64), w.astype(np.float64))
+    ref, _, _ = P.adam(p64, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    ref_step = ref - p64
+    big = np.abs(g) > 1e-3 * np.max(np.abs(g))
+    assert np.max(np.abs(step[big] - ref_step[big])) <= 1e-3 * lr
+    assert np.max(np.abs(step)) <= lr * (1 + 1e-3)   # FP32 parameters: steps round at 2^-24 |p|
+    m.close()
+
+
+def test_training_pairs_match_oracle():
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    x = uniform_points(3000, 3, 57)
+    rng = np.random.default_rng(58)
+    r = rng.normal(0, 1, 3000)
+    e = rng.normal(0, 1, 3000)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.05, tol=1e-6)
+    pc.learned_features(plan, 1e-3)
+    X, T, w = (a.cpu().numpy() for a in pc.pairs(plan, dev(r), dev(e)))
+    inv, perm = P.block_inverses(x, "gaussian", 0.05, 1e-3)
+    Xr, Tr, wr = P.pairs(inv, perm, r, e)
+    assert X.shape == Xr.shape == (47, 64)
+    assert rel(X, Xr) <= 1e-6 and rel(T, Tr) <= 1e-6 and rel(w, wr) <= 1e-6
+    assert w[-1] == 0.0 and np.all(w[:-1] > 0)
+
+
+def test_learned_apply_matches_oracle():
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    x = uniform_points(3000, 3, 59)
+    v = normal_weights(3000, 60)
+    params = rand_params(61, out_scale=0.1)
+    m = pc.Mlp(params)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.05, tol=1e-6)
+    pc.learned_features(plan, 1e-3)
+    pc.set_learned(plan, m)
+    z = pc.apply(plan, "learned", dev(v)).cpu().numpy()
+    inv, perm = P.block_inverses(x, "gaussian", 0.05, 1e-3)
+    zr = P.learned_apply(inv, perm, params.astype(np.float64), v, bf16=True)
+    zb = P.bj_apply(inv, perm, v)
+    print(f"[pc] learned vs oracle {rel(z, zr):.2e} (correction {rel(zr, zb):.2e} of the output)", flush=True)
+    assert rel(z, zr) <= 1e-4
+
+
+def test_weight_file_roundtrip_and_rejects_bad_files(tmp_path):
+    from paper_1606_07652_amd import RbfError
+    from paper_1606_07652_amd.pc import Mlp
+    params = rand_params(62)
+    m = Mlp(params)
+    path = str(tmp_path / "w.bin")
+    m.save(path)
+    m2 = Mlp.load(path)
+    assert np.array_equal(m2.params(), params)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"RBF-MLP\0" and len(raw) == 48 + 4 * P.nparams()
+    for name, data in (("short", raw[:-4]), ("magic", b"X" + raw[1:]), ("long", raw + b"\0"),
+                       ("version", raw[:8] + b"\x02" + raw[9:])):
+        bad = str(tmp_path / f"{name}.bin")
+        open(bad, "wb").write(data)
+        with pytest.raises(RbfError):
+            Mlp.load(bad)
+    m.close()
+    m2.close()
+
+
+def test_default_network_is_block_jacobi():
+    """A fresh network has a zero output layer: the learned preconditioner equals block-Jacobi."""
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    x = uniform_points(1000, 3, 63)
+    v = normal_weights(1000, 64)
+    m = pc.Mlp(seed=7)
+    p = m.params()
+    assert np.all(p[-(256 * 64 + 64):] == 0) and np.any(p[:1000] != 0)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.05, tol=1e-6)
+    pc.block_jacobi(plan, 1e-4)
+    pc.learned_features(plan, 1e-4)       # same reg: the feature inverses are the block-Jacobi ones
+    pc.set_learned(plan, m)
+    z1 = pc.apply(plan, "learned", dev(v))
+    z2 = pc.apply(plan, "block_jacobi", dev(v))
+    assert torch.equal(z1, z2)
+
+
+def well_posed(seed=65):
+    x = jittered_grid(50, 2, seed)          # 2500 points, separation > half the spacing (0.02)
+    f = np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+    return x, f
+
+
+def test_right_preconditioning_keeps_the_solution():
+    from paper_1606_07652_amd import FmmPlan
+    x, f = well_posed()
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.01, tol=1e-10)
+    sols = {}
+    for kind in ("none", "block_jacobi"):
+        lam, info = plan.solve(dev(f), rtol=1e-10, restart=30, max_iters=400, precond=kind)
+        print(f"[pc] {kind}: iters={info['iters']} res={info['true_res']:.2e}", flush=True)
+        assert info["converged"] and info["fallback_used"] == 0
+        u = plan.matvec(lam).cpu().numpy()
+        assert np.linalg.norm(f - u) / np.linalg.norm(f) <= 1e-10 * (1 + 1e-6)
+        sols[kind] = lam.cpu().numpy()
+    assert rel(sols["block_jacobi"], sols["none"]) <= 1e-6
+
+
+def test_nan_network_falls_back():
+    from paper_1606_07652_amd import FmmPlan, RbfError
+    from paper_1606_07652_amd import pc
+    x, f = well_posed(66)
+    params = rand_params(67)
+    params[-1] = np.nan                                  # one output bias: every block's output is NaN
+    m = pc.Mlp(params)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=0.01, tol=1e-10)
+    pc.set_learned(plan, m)
+    # restart 5: the learned direction (the last of a cycle) is taken in the first cycle
+    lam, info = plan.solve(dev(f), rtol=1e-9, restart=5, max_iters=400, precond="learned")
+    assert info["fallback_used"] >= 1 and info["converged"]
+    assert np.all(np.isfinite(lam.cpu().numpy()))
+    with pytest.raises(RbfError):
+        plan.solve(dev(f), rtol=1e-9, restart=5, max_iters=400, precond="learned", fallback=False)
+    # no network attached
+    plan2 = FmmPlan(dev(x), kernel="gaussian", shape=0.01, tol=1e-10)
+    with pytest.raises(RbfError):
+        plan2.solve(dev(f), rtol=1e-9, precond="learned")
+
+
+def test_learned_preconditioner_gain(tmp_path):
+    """Train on harvested pairs of plain solves of four 10^4-point problems, then solve a
+    fifth problem of the same family with identical caps: plain, block-Jacobi, learned."""
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    from workloads import bumps_rhs
+    s = 0.03
+    rows = [[], [], []]
+    for sd in (100, 101, 102, 103):
+        x = jittered_grid(100, 2, sd)
+        plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
+        for k, a in enumerate(pc.harvest(plan, dev(bumps_rhs(x, sd)), rtol=1e-10, max_iters=1000)):
+            rows[k].append(a)
+        plan.close()
+    X, T, W = (torch.cat(r) for r in rows)
+    m = pc.Mlp(seed=0)
+    info = m.train(X, T, W, epochs=150, batch=256, lr=1e-3, val_frac=0.25, patience=30, seed=1)
+    print(f"[gain] rows={X.shape[0]} val loss {info['init_val_loss']:.3f} -> {info['best_val_loss']:.3f} "
+          f"(epoch {info['best_epoch']}, {info['seconds']:.1f} s)", flush=True)
+    assert info["best_val_loss"] <= 0.5 * info["init_val_loss"]
+    path = str(tmp_path / "pc.bin")
+    m.save(path)
+    m2 = pc.Mlp.load(path)                   # the solve below runs on the reloaded weights
+    x = jittered_grid(100, 2, 200)
+    f = dev(bumps_rhs(x, 200))
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
+    pc.set_learned(plan, m2)
+    res = {}
+    for kind in ("none", "block_jacobi", "learned"):
+        lam, inf = plan.solve(f, rtol=1e-8, restart=50, max_iters=300, precond=kind)
+        u = plan.matvec(lam).cpu().numpy()
+        fh = f.cpu().numpy()
+        true_res = np.linalg.norm(fh - u) / np.linalg.norm(fh)
+        assert abs(true_res - inf["true_res"]) <= 1e-9
+        res[kind] = true_res
+        print(f"[gain] {kind}: iters={inf['iters']} true residual {true_res:.3e} fallback={inf['fallback_used']}",
+              flush=True)
+    assert res["learned"] <= 0.5 * res["none"]
+    assert res["learned"] <= 1.5 * res["block_jacobi"]
