@@ -2,7 +2,7 @@
 
 Every source under csrc/ is compiled to an object in parallel, then linked into
 ``paper_1606_07652_amd/lib/librbffmm.so``.  Packed FP32 instructions are disabled for all
-device code (-packed-fp32-ops).
+device code (-packed-fp32-ops); MFMA accumulators stay in VGPRs (-amdgpu-mfma-vgpr-form).
 """
 from __future__ import annotations
 
@@ -20,7 +20,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # keep MFMA accumulators in ordinary VGPRs (otherwise loop-carried accumulators are
+         # copied between VGPRs and AGPRs on every iteration)
+         "-mllvm", "-amdgpu-mfma-vgpr-form", "-Wno-unused-result",
          "-Wno-unused-command-line-argument"]
 
 

@@ -180,8 +180,7 @@ template <class T> int build_groups(rbf_batch *b) {
             d.off = b->offsets[q];
             d.m2l_sched = 0;   // block ids are problem-local here, so the XCD split does not apply
             ds.push_back(d);
-            g.p2m_sh = std::max(g.p2m_sh, sizeof(typename cplx<T>::type) *
-                                               (size_t)((b->d > 1 ? b->d - 1 : 1) * d.mn) * d.p2m_ch);
+            g.p2m_sh = std::max(g.p2m_sh, (size_t)d.p2m_lds);
         }
         g.nprob = (int)ds.size();
         RBF_TRY(b->arena.alloc(&g.descs, sizeof(Desc<T>) * ds.size()));

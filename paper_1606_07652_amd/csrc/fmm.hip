@@ -47,6 +47,58 @@ template <class C> __device__ __forceinline__ void cmac(C &acc, const C a, const
     acc.y = fma(a.y, b.x, acc.y);
 }
 
+// ---- matrix cores ---------------------------------------------------------------------
+// 16x16x4 MFMA with one K element per lane: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and accumulates four C values whose rows depend on the instruction.
+typedef double mfd4 __attribute__((ext_vector_type(4)));
+typedef float mff4 __attribute__((ext_vector_type(4)));
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    using V = mfd4;
+    static __device__ __forceinline__ V mac(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lane) { return 4 * q + (lane >> 4); }   // C[row][lane % 16]
+};
+template <> struct Mfma<float> {
+    using V = mff4;
+    static __device__ __forceinline__ V mac(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lane) { return 4 * (lane >> 4) + q; }
+};
+
+// Load through a global-address-space pointer (a plain pointer read becomes a flat load,
+// which also counts against the LDS wait counter and serialises with LDS traffic).
+template <class X> __device__ __forceinline__ X gld(const X *p) {
+    return *(const __attribute__((address_space(1))) X *)p;
+}
+
+// Row digits (m_0 .. m_{d-2}, fastest last) of an expansion row r < 2^22, dividing by mn
+// with a multiply-high (exact in that range for every mn up to 128).
+template <int DM>
+__device__ __forceinline__ void row_digits(unsigned r, int mn, unsigned magic, int (&md)[DM]) {
+#pragma unroll
+    for (int k = DM - 1; k >= 0; --k) {
+        const unsigned q = __umulhi(r, magic);
+        md[k] = (int)(r - q * (unsigned)mn);
+        r = q;
+    }
+}
+
+// Aggregation geometry: row tiles of 16 per wave and rows per workgroup of four waves.
+__host__ __device__ constexpr int p2m_rtiles(int dim) { return dim > 2 ? 4 : 1; }
+__host__ __device__ constexpr int p2m_rows(int dim) { return 4 * 16 * p2m_rtiles(dim); }
+// Disaggregation: targets per workgroup (32, or 16 where the phase tables of 32 targets
+// would exceed 64 KiB of LDS); a 64-target task is split over 64 / NT workgroups.
+__host__ __device__ constexpr size_t l2p_lds(int csize, int dim, int hmax, int nt) {
+    return (size_t)csize * nt * (hmax + (dim - 1) * 2 * hmax) + (size_t)(csize / 2) * 4 * nt;
+}
+__host__ __device__ constexpr int l2p_targets(int csize, int dim, int hmax) {
+    return l2p_lds(csize, dim, hmax, 32) <= 65536 ? 32 : 16;
+}
+
+template <class T> struct KFun;
 template <class T> struct KFun;
 
 // Coefficient n of the Taylor series of 2^f = e^{f ln 2}: (ln 2)^n / n!.
@@ -246,13 +298,13 @@ __device__ __forceinline__ void phase_dl_body(const Desc<T> &d, int bid) {
     }
 }
 
-// Aggregation (P2M).  Blocks (leaf, part): thread = one row (m_1..m_{d-1}) of the half
+// Aggregation (P2M) on the vector ALUs (the FP64 path).  Blocks (leaf, part): thread = one row (m_1..m_{d-1}) of the half
 // grid, all HMAX last-dimension nodes in registers.  Per chunk of CH points the block
 // builds the per-thread factors e^{-i xi_m x_k} (k < d-1) in LDS; the lambda-weighted
 // last-dimension phases of a point are uniform across the block and come through scalar
 // loads.
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_raw) {
+__device__ __forceinline__ void p2m_valu_body(const Desc<T> &d, int bid, char *smem_raw) {
     using C = typename cplx<T>::type;
     C *tab = reinterpret_cast<C *>(smem_raw);
     constexpr int DM = D > 1 ? D - 1 : 1;
@@ -330,6 +382,119 @@ __device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_r
     }
 }
 
+// Aggregation (P2M) on the matrix cores (the FP32 path): per leaf, W[r][h] = sum_j KV_j[r] DL_j[h] with
+// KV_j[r] = prod_{k<d-1} e^{-i xi_{m_k(r)} x_jk} and DL_j[h] = lambda_j e^{-i xi_{H+h} x_jd}.
+// The complex product is two real products over K' = 2 x points (k' = 2 j + c):
+// A'[r][2j] = Re KV, A'[r][2j+1] = Im KV; B_re = [Re DL; -Im DL], B_im = [Im DL; Re DL].
+// Workgroup (leaf, part) of four waves; each wave owns p2m_rtiles row tiles of 16 and all
+// h tiles.  Per chunk of CH points the factors e^{-i xi_m x_jk} (k < d-1) are built in LDS
+// (FP64 recurrences stored in T); the A fragment of a lane is one complex product of
+// those, the B fragment one entry of the point's lambda-weighted phases.
+template <class T, int D, int HMAX>
+__device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_raw) {
+    using C = typename cplx<T>::type;
+    using M = Mfma<T>;
+    using V = typename M::V;
+    constexpr int DM = D - 1;
+    constexpr int NRT = p2m_rtiles(D);
+    constexpr int HT = (HMAX + 15) / 16;
+    C *tab = reinterpret_cast<C *>(smem_raw);       // [CH][DM][mn]
+    C *dls = tab + d.p2m_ch * DM * d.mn;            // [CH][HMAX] phases of the chunk's points
+    const int mn = d.mn, R = d.R, CH = d.p2m_ch, H = d.H;
+    const int ST = DM * mn;
+    const int a = bid / d.wpl, part = bid % d.wpl;
+    const int t0 = d.leaf_begin[a], t1 = d.leaf_begin[a + 1];
+    const int64_t n = d.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, jsel = lane >> 5, csel = (lane >> 4) & 1;
+    const int rbase = part * p2m_rows(D) + wave * 16 * NRT;
+    // row digits of this lane's A rows (fastest digit k = d-2)
+    int md[NRT][DM];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) row_digits<DM>((unsigned)min(rbase + 16 * t + lr, R - 1), mn, d.mn_magic, md[t]);
+    V wr[NRT][HT], wi[NRT][HT];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t)
+#pragma unroll
+        for (int u = 0; u < HT; ++u) { wr[t][u] = V{0, 0, 0, 0}; wi[t][u] = V{0, 0, 0, 0}; }
+    for (int c0 = t0; c0 < t1; c0 += CH) {
+        const int cn = min(CH, t1 - c0);
+        __syncthreads();
+        for (int e = tid; e < cn * HMAX; e += blockDim.x) dls[e] = d.dl[(int64_t)c0 * HMAX + e];
+        for (int job = tid; job < cn * DM; job += blockDim.x) {
+            const int j = job / DM, k = job % DM;
+            C *dst = tab + j * ST + k * mn;
+            const double x = (double)d.xs[k * n + c0 + j];
+            double sb, cb, ss, cs;
+            sincos(-d.dxi * x, &ss, &cs);
+            sincos(-d.xi0 * x, &sb, &cb);
+            double er = cb, ei = sb;
+            for (int m = 0; m < mn; ++m) {
+                dst[m] = C{(T)er, (T)ei};
+                double nr = er * cs - ei * ss;
+                ei = er * ss + ei * cs;
+                er = nr;
+            }
+        }
+        __syncthreads();
+        // B fragments of K step j0 (points j0, j0 + 1): the point's phases for h = 16 u + lr,
+        // read from LDS at a clamped index and masked, one step ahead
+        auto load_b = [&](int j0, T (&vr)[HT], T (&vi)[HT]) {
+            const int jl = j0 + jsel;
+            const int jc = min(jl, cn - 1);
+#pragma unroll
+            for (int u = 0; u < HT; ++u) {
+                const int h = min(16 * u + lr, HMAX - 1);
+                const C v = dls[jc * HMAX + h];
+                const bool ok = jl < cn && 16 * u + lr < HMAX;
+                vr[u] = ok ? (csel ? -v.y : v.x) : T(0);
+                vi[u] = ok ? (csel ? v.x : v.y) : T(0);
+            }
+        };
+        // A fragments of K step j0: one entry of KV_j[r] per row tile (a point past the end
+        // of the leaf is clamped; its B entries are zero)
+        auto load_a = [&](int j0, T (&av)[NRT]) {
+            const C *pt = tab + min(j0 + jsel, cn - 1) * ST;
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                C kv = pt[md[t][0]];
+#pragma unroll
+                for (int k = 1; k < DM; ++k) kv = cmul(kv, pt[k * mn + md[t][k]]);
+                av[t] = csel ? kv.y : kv.x;
+            }
+        };
+        T bre[HT], bim[HT], av[NRT];
+        load_b(0, bre, bim);
+        load_a(0, av);
+        for (int j0 = 0; j0 < cn; j0 += 2) {
+            T nre[HT], nim[HT], nav[NRT];
+            load_b(j0 + 2, nre, nim);                 // next step (clamped past the end)
+            load_a(j0 + 2, nav);
+#pragma unroll
+            for (int t = 0; t < NRT; ++t)
+#pragma unroll
+                for (int u = 0; u < HT; ++u) {
+                    wr[t][u] = M::mac(av[t], bre[u], wr[t][u]);
+                    wi[t][u] = M::mac(av[t], bim[u], wi[t][u]);
+                }
+#pragma unroll
+            for (int u = 0; u < HT; ++u) { bre[u] = nre[u]; bim[u] = nim[u]; }
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) av[t] = nav[t];
+        }
+    }
+    C *out = d.W + (int64_t)a * R * H;
+#pragma unroll
+    for (int t = 0; t < NRT; ++t)
+#pragma unroll
+        for (int u = 0; u < HT; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = rbase + 16 * t + M::row(q, lane), h = 16 * u + lr;
+                if (r < R && h < H) out[(int64_t)r * H + h] = C{wr[t][u][q], wi[t][u][q]};
+            }
+}
+
 // Upward pass: coarse cell = sum of its leaves.  Blocks (cell, 256-node chunk).
 template <class T>
 __device__ __forceinline__ void m2m_body(const Desc<T> &d, int bid) {
@@ -385,52 +550,78 @@ __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bi
     out[c * P + p] = s;
 }
 
-// Leaf translation + downward pass.  Blocks (leaf, 256-entry chunk of the expansion);
-// each thread subtracts the leaf's near rows from the coarse cell's local expansion and
-// applies the quadrature weight w(xi) C(xi) (a plan-time table).  Output rows are padded
-// to HP entries; the padding was zeroed at plan time and is not written.
-// Block order (d.m2l_sched): 0 = leaf fastest, chunk slowest; 1 = the same order split
-// into 8 contiguous leaf ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
-// the near rows a range re-reads stay in one XCD's L2 (measured on the 2^20-point
-// workload: 3.2 GB fetched from memory per launch instead of 25 GB).  Batches use 0.
+// Leaf translation + downward pass.  Blocks (sibling group, 256-entry chunk of the
+// expansion): the group's members (at most 8 consecutive leaves with one parent) share one
+// ascending list of the leaves near any of them, with a mask of the members each entry is
+// near to; every near row is loaded once for the whole group and subtracted from the
+// members' copies of their coarse cell's local expansion (the same sequence of operations
+// per member as a per-leaf walk of its own near list).  The quadrature weight w(xi) C(xi)
+// is applied on output.  Output rows are padded to HP entries; the padding was zeroed at
+// plan time and is not written.
+// Block order (d.m2l_sched): 0 = group fastest, chunk slowest; 1 = the same order split
+// into 8 contiguous group ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
+// the near rows a range re-reads stay in one XCD's L2.  Batches use 0.
 template <class T, int D>
 __device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
     using C = typename cplx<T>::type;
-    const int nleaves = d.nleaves, H = d.H, HP = d.HP;
+    const int ng = d.ngroups, H = d.H, HP = d.HP;
     const int P = (int)d.P;
-    int a, chunk;
+    int grp, chunk;
     if (d.m2l_sched == 1) {
         const int x = g & 7, k = g >> 3;
-        const int per = (nleaves + 7) >> 3;            // leaves per XCD range (last may be short)
-        const int lo = min(x * per, nleaves), hi = min(lo + per, nleaves);
+        const int per = (ng + 7) >> 3;                 // groups per XCD range (last may be short)
+        const int lo = min(x * per, ng), hi = min(lo + per, ng);
         const int len = max(hi - lo, 1);
-        a = lo + k % len;
+        grp = lo + k % len;
         chunk = k / len;
-        if (hi - lo == 0 || a >= hi) return;
+        if (hi - lo == 0 || grp >= hi) return;
     } else {
-        a = g % nleaves;
-        chunk = g / nleaves;
+        grp = g % ng;
+        chunk = g / ng;
     }
     const int p = chunk * kThreads + (int)threadIdx.x;
     if (p >= P) return;
-    C s = d.Lc[(int64_t)d.leaf_cell[a] * P + p];
-    const int e0 = d.near_ptr[a], e1 = d.near_ptr[a + 1];
-    for (int e = e0; e < e1; ++e) {
-        const C v = d.W[(int64_t)d.near_idx[e] * P + p];
-        s.x -= v.x;
-        s.y -= v.y;
+    const int a0 = d.grp_first[grp], na = d.grp_first[grp + 1] - a0;
+    C s[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < na) s[c] = d.Lc[(int64_t)d.leaf_cell[a0 + c] * P + p];
+    const int e0 = d.uni_ptr[grp], e1 = d.uni_ptr[grp + 1];
+    // eight near rows in flight per step (entries past the end repeat the last with mask 0)
+    for (int e = e0; e < e1; e += 8) {
+        int b[8], m[8];
+        C v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = min(e + u, e1 - 1);
+            b[u] = __builtin_amdgcn_readfirstlane(d.uni_idx[k]);
+            m[u] = e + u < e1 ? __builtin_amdgcn_readfirstlane(d.uni_mask[k]) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.W[(int64_t)b[u] * P + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if ((m[u] >> c) & 1) {
+                    s[c].x -= v[u].x;
+                    s[c].y -= v[u].y;
+                }
     }
     const double f = d.wtab[p];
     const int row = p / H, h = p - row * H;
-    d.Lx[((int64_t)a * d.R + row) * HP + h] = C{(T)(f * s.x), (T)(f * s.y)};
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < na)
+            d.Lx[((int64_t)(a0 + c) * d.R + row) * HP + h] = C{(T)(f * s[c].x), (T)(f * s[c].y)};
 }
 
-// Disaggregation (L2P) + combine.  One wave per task (up to 64 target points of one
+// Disaggregation (L2P) + combine on the vector ALUs (the FP64 path).  One wave per task (up to 64 target points of one
 // leaf), one lane per target.  The lane keeps e^{+i xi_{H+h} x_d} for all h in registers
 // and walks the rows with an FP64 odometer recurrence for the other factors; the leaf's
 // L rows (padded to HMAX) are uniform across the wave and come through scalar loads.
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ void l2p_valu_body(const Desc<T> &d, T *__restrict__ u, int bid) {
     using C = typename cplx<T>::type;
     constexpr int DM = D > 1 ? D - 1 : 1;
     const int2 tk = d.tasks[bid];
@@ -499,6 +690,139 @@ __device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, in
     if (act) u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * acc;
 }
 
+// Disaggregation (L2P) + combine on the matrix cores (the FP32 path).  For the targets i of a workgroup
+// (NT of one 64-target task) and the leaf's local rows r:
+//   G[i][r] = sum_h E_i[h] L[r][h]   (E_i[h] = e^{+i xi_{H+h} x_id}),   a real product over
+//   K' = 2 HMAX with A'[i][2h] = Re E, A'[i][2h+1] = Im E, B_re = [Re L; -Im L], B_im = [Im L; Re L];
+//   u_i = u_near_i + 2 Re sum_r KV_i[r] G[i][r],  KV_i[r] = prod_{k<d-1} e^{+i xi_{m_k(r)} x_ik}.
+// The four waves split the row tiles; the phase tables of the NT targets are built once in
+// LDS (FP64 recurrences stored in T); per-target sums are reduced over the 16 lanes of a row
+// group and then over the waves in a fixed order.
+template <class T, int D, int HMAX>
+__device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, int bid, char *smem_raw) {
+    using C = typename cplx<T>::type;
+    using M = Mfma<T>;
+    using V = typename M::V;
+    constexpr int DM = D - 1;
+    constexpr int KS = HMAX / 2;                       // K steps of 4 over k' = 2 h + c
+    constexpr int NT = l2p_targets((int)sizeof(C), D, HMAX);
+    constexpr int IT = NT / 16, SPLIT = 64 / NT;
+    const int2 tk = d.tasks[bid / SPLIT];
+    const int a = tk.x;
+    const int tb = d.leaf_begin[a] + tk.y + (bid % SPLIT) * NT;
+    const int t1 = d.leaf_begin[a + 1];
+    const int nt = min(NT, t1 - tb);
+    if (nt <= 0) return;                               // the same for the whole workgroup
+    const int R = d.R, mn = d.mn;
+    const int64_t n = d.n;
+    C *E = reinterpret_cast<C *>(smem_raw);            // [NT][HMAX]
+    C *Tt = E + NT * HMAX;                             // [DM][NT][mn]
+    T *red = reinterpret_cast<T *>(Tt + DM * NT * mn); // [4][NT]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, hsel = lane >> 5, csel = (lane >> 4) & 1;
+    for (int job = tid; job < NT * (1 + DM); job += blockDim.x) {
+        const int i = job % NT, k = job / NT;
+        const int64_t ti = tb + min(i, nt - 1);
+        double sb, cb, ss, cs;
+        if (k == 0) {
+            const double x = (double)d.xs[(int64_t)(D - 1) * n + ti];
+            sincos(d.xiH * x, &sb, &cb);
+            sincos(d.dxi * x, &ss, &cs);
+        } else {
+            const double x = (double)d.xs[(int64_t)(k - 1) * n + ti];
+            sincos(d.xi0 * x, &sb, &cb);
+            sincos(d.dxi * x, &ss, &cs);
+        }
+        C *dst = k == 0 ? E + i * HMAX : Tt + ((k - 1) * NT + i) * mn;
+        const int len = k == 0 ? HMAX : mn;
+        double er = cb, ei = sb;
+        for (int m = 0; m < len; ++m) {
+            dst[m] = C{(T)er, (T)ei};
+            double nr = er * cs - ei * ss;
+            ei = er * ss + ei * cs;
+            er = nr;
+        }
+    }
+    __syncthreads();
+    T afr[IT][KS];
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const C e = E[(16 * it + lr) * HMAX + 2 * s + hsel];
+            afr[it][s] = csel ? e.y : e.x;
+        }
+    T acc[IT][4];
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[it][q] = 0;
+    const T *La = reinterpret_cast<const T *>(d.Lx + (int64_t)a * R * HMAX);
+    const int NR = (R + 15) / 16;
+    // B fragments of a row tile, loaded unconditionally from a clamped row and masked
+    auto load_b = [&](int rt, T (&br)[KS], T (&bi)[KS]) {
+        const int r = rt * 16 + lr;
+        const bool rv = r < R;
+        const T *q = La + ((int64_t)min(r, R - 1) * HMAX + hsel) * 2;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const T x = gld(q + 4 * s), y = gld(q + 4 * s + 1);
+            br[s] = rv ? (csel ? -y : x) : T(0);
+            bi[s] = rv ? (csel ? x : y) : T(0);
+        }
+    };
+    T br[KS], bi[KS];
+    if (wave < NR) load_b(wave, br, bi);
+    for (int rt = wave; rt < NR; rt += 4) {
+        T nr_[KS], ni_[KS];
+        load_b(min(rt + 4, NR - 1), nr_, ni_);         // next tile of this wave, one step ahead
+        const int r = rt * 16 + lr;
+        int md[DM];
+        row_digits<DM>((unsigned)min(r, R - 1), mn, d.mn_magic, md);
+        // 2 IT independent accumulation chains, interleaved
+        V gr[IT], gi[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) { gr[it] = V{0, 0, 0, 0}; gi[it] = V{0, 0, 0, 0}; }
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                gr[it] = M::mac(afr[it][s], br[s], gr[it]);
+                gi[it] = M::mac(afr[it][s], bi[s], gi[it]);
+            }
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * it + M::row(q, lane);
+                C kv = Tt[i * mn + md[0]];
+#pragma unroll
+                for (int k = 1; k < DM; ++k) kv = cmul(kv, Tt[(k * NT + i) * mn + md[k]]);
+                acc[it][q] = fma(kv.x, gr[it][q], acc[it][q]);
+                acc[it][q] = fma(-kv.y, gi[it][q], acc[it][q]);
+            }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) { br[s] = nr_[s]; bi[s] = ni_[s]; }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T v = acc[it][q];
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            v += __shfl_xor(v, 8, 64);
+            if (lr == 0) red[wave * NT + 16 * it + M::row(q, lane)] = v;
+        }
+    __syncthreads();
+    if (tid < nt) {
+        const T sum = ((red[tid] + red[NT + tid]) + red[2 * NT + tid]) + red[3 * NT + tid];
+        const int ti = tb + tid;
+        u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * sum;
+    }
+}
+
 // ---- kernels: single problem (descriptor by value) or batch (descriptor array) --------
 __device__ __forceinline__ int find_prob(const int *__restrict__ bstart, int nprob, int g) {
     int lo = 0, hi = nprob;   // largest q with bstart[q] <= g
@@ -553,11 +877,17 @@ template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) 
     const Desc<T> &d = resolve(w, lb);
     phase_dl_body<T, D, HMAX>(d, lb);
 }
+// FP64 runs the aggregation and disaggregation on the vector ALUs: on this chip the FP64
+// matrix rate equals the FP64 vector rate, and the VALU kernels measured as fast or faster.
+// FP32 uses the matrix cores (twice the vector rate without packed FP32).
+template <class T> constexpr bool kExpMfma = sizeof(T) == 4;
+
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_p2m(Work<T> w) {
     extern __shared__ char smem_raw[];
     int lb;
     const Desc<T> &d = resolve(w, lb);
-    p2m_body<T, D, HMAX>(d, lb, smem_raw);
+    if constexpr (kExpMfma<T>) p2m_body<T, D, HMAX>(d, lb, smem_raw);
+    else p2m_valu_body<T, D, HMAX>(d, lb, smem_raw);
 }
 template <class T> __global__ void __launch_bounds__(kThreads) k_m2m(Work<T> w) {
     int lb;
@@ -574,10 +904,12 @@ template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_leaf
     const Desc<T> &d = resolve<T, false>(w, lb);
     m2l_leaf_body<T, D>(d, lb);
 }
-template <class T, int D, int HMAX> __global__ void __launch_bounds__(kWave) k_l2p(Work<T> w) {
+template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_l2p(Work<T> w) {
+    extern __shared__ char smem_raw[];
     int lb;
     const Desc<T> &d = resolve(w, lb);
-    l2p_body<T, D, HMAX>(d, w.u, lb);
+    if constexpr (kExpMfma<T>) l2p_body<T, D, HMAX>(d, w.u, lb, smem_raw);
+    else l2p_valu_body<T, D, HMAX>(d, w.u, lb);
 }
 
 // ---- host side -----------------------------------------------------------------------
@@ -599,21 +931,22 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
     if (!d.far && phase != PH_GATHER && phase != PH_P2P && phase != PH_DIRECT) return 0;
     switch (phase) {
         case PH_GATHER: case PH_PHASE_DL: case PH_DIRECT: return nb_pts;
-        case PH_P2P: case PH_L2P: return d.ntasks;
+        case PH_P2P: return d.ntasks;
+        case PH_L2P:
+            if (!kExpMfma<T>) return d.ntasks;
+            return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
         case PH_P2M: return (int64_t)d.nleaves * d.wpl;
         case PH_M2M: case PH_M2L_AXIS: return d.ncells * nch;
         case PH_M2L_LEAF: {
             const int64_t nch_l = (d.P + kThreads - 1) / kThreads;
-            if (d.m2l_sched == 1) return 8 * nch_l * ((d.nleaves + 7) / 8);
-            return nch_l * d.nleaves;
+            if (d.m2l_sched == 1) return 8 * nch_l * ((d.ngroups + 7) / 8);
+            return nch_l * d.ngroups;
         }
     }
     return 0;
 }
 
-template <class T> size_t p2m_shmem(const Desc<T> &d, int D) {
-    return sizeof(typename cplx<T>::type) * (size_t)((D > 1 ? D - 1 : 1) * d.mn) * d.p2m_ch;
-}
+template <class T> size_t p2m_shmem(const Desc<T> &d, int) { return (size_t)d.p2m_lds; }
 
 // Launch one phase for a single problem or a batch (see Work).
 template <class T, int D, int HMAX>
@@ -631,11 +964,16 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
             else k_direct<T, D, RBF_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w);
             break;
         case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kThreads, 0, s>>>(w); break;
-        case PH_P2M: k_p2m<T, D, HMAX><<<g, (D > 2 ? kThreads : kWave), shmem, s>>>(w); break;
+        case PH_P2M: k_p2m<T, D, HMAX><<<g, (kExpMfma<T> || D > 2) ? kThreads : kWave, shmem, s>>>(w); break;
         case PH_M2M: k_m2m<T><<<g, kThreads, 0, s>>>(w); break;
         case PH_M2L_AXIS: k_m2l_axis<T, D><<<g, kThreads, 0, s>>>(w, axis); break;
         case PH_M2L_LEAF: k_m2l_leaf<T, D><<<g, kThreads, 0, s>>>(w); break;
-        case PH_L2P: k_l2p<T, D, HMAX><<<g, kWave, 0, s>>>(w); break;
+        case PH_L2P: {
+            constexpr int csz = (int)sizeof(typename cplx<T>::type);
+            constexpr size_t lds = kExpMfma<T> ? l2p_lds(csz, D, HMAX, l2p_targets(csz, D, HMAX)) : 0;
+            k_l2p<T, D, HMAX><<<g, kExpMfma<T> ? kThreads : kWave, lds, s>>>(w);
+            break;
+        }
     }
     RBF_HIP(hipGetLastError());
     return RBF_OK;
@@ -816,11 +1154,22 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->dl = (C *)p->dl;
     d->wtab = p->wtab;
     d->m2l_sched = p->m2l_sched;
-    const int bd = (p->d > 2) ? kThreads : kWave;
-    d->wpl = (int)((p->R + bd - 1) / bd);
-    const size_t per_point = sizeof(C) * (size_t)((p->d > 1 ? p->d - 1 : 1) * p->mn);
-    d->p2m_ch = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point));
+    // aggregation: rows per workgroup, and per point of a chunk the factors of the d-1
+    // leading dimensions (plus, on the matrix cores, the point's HP phases) in LDS
+    const int rows = kExpMfma<T> ? p2m_rows(p->d) : (p->d > 2 ? kThreads : kWave);
+    d->wpl = (int)((p->R + rows - 1) / rows);
+    const size_t per_point =
+        sizeof(C) * (size_t)((p->d > 1 ? p->d - 1 : 1) * p->mn + (kExpMfma<T> ? p->HP : 0));
+    d->p2m_ch = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point)) & ~1;
+    d->p2m_lds = (int)(per_point * d->p2m_ch);
     d->far = p->far;
+    d->dim = p->d;
+    d->ngroups = p->ngroups;
+    d->grp_first = p->grp_first;
+    d->uni_ptr = p->uni_ptr;
+    d->uni_idx = p->uni_idx;
+    d->uni_mask = p->uni_mask;
+    d->mn_magic = (unsigned)((1ull << 32) / (unsigned)p->mn + 1);
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);
 template void fill_desc<double>(const rbf_plan *, Desc<double> *);

@@ -40,6 +40,11 @@ template <class T> struct Desc {
     int far;                // 0: every kept pair is near (no far-field phases)
     const double *wtab;     // w(xi) C(xi) per stored node [P]
     int m2l_sched;          // block order of the leaf translation
+    int dim;                // spatial dimension d
+    int ngroups;            // sibling groups of the leaf translation
+    const int *grp_first, *uni_ptr, *uni_idx, *uni_mask;
+    int p2m_lds;            // dynamic LDS bytes of the aggregation kernel
+    unsigned mn_magic;      // floor(2^32 / mn) + 1: r / mn = (r * mn_magic) >> 32 for r < 2^22
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);

@@ -90,6 +90,14 @@ struct rbf_plan {
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
     int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    // sibling groups of the leaf translation: runs of at most 8 consecutive leaves with one
+    // parent; each group's near lists merged into one ascending list with member masks
+    int ngroups = 0;
+    int64_t nunion = 0;
+    int *grp_first = nullptr;        // first leaf of each group [ngroups + 1]
+    int *uni_ptr = nullptr;          // [ngroups + 1]
+    int *uni_idx = nullptr;          // near leaf of each entry [nunion]
+    int *uni_mask = nullptr;         // bit c set: member c of the group has the leaf as near [nunion]
     double *wtab = nullptr;          // quadrature weight times C(xi) per stored node [P]
     int m2l_sched = 0;               // block order of the leaf translation
     int ntasks = 0;

@@ -619,6 +619,55 @@ int tree_typed(rbf_plan *p, const void *points_v) {
         p->ntasks = (int)tk.size();
         RBF_TRY(ar.alloc((void **)&p->tasks, sizeof(int2) * tk.size()));
         RBF_HIP(hipMemcpyAsync(p->tasks, tk.data(), sizeof(int2) * tk.size(), hipMemcpyHostToDevice, s));
+        RBF_HIP(hipStreamSynchronize(s));   // tk is freed at the end of this scope
+    }
+    // sibling groups for the leaf translation
+    {
+        std::vector<int> hl(nleaves), np(nleaves + 1), ni((size_t)std::max(nnear, 1));
+        std::vector<uint64_t> pf(nleaves);
+        RBF_HIP(hipMemcpyAsync(hl.data(), p->leaf_level, sizeof(int) * nleaves, hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipMemcpyAsync(pf.data(), p->leaf_prefix, sizeof(uint64_t) * nleaves, hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipMemcpyAsync(np.data(), p->near_ptr, sizeof(int) * (nleaves + 1), hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipMemcpyAsync(ni.data(), p->near_idx, sizeof(int) * std::max(nnear, 1), hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipStreamSynchronize(s));
+        std::vector<int> gf, up, ui, um;
+        std::vector<std::pair<int, int>> ent;
+        up.push_back(0);
+        for (int a = 0; a < nleaves;) {
+            int b = a + 1;
+            while (b < nleaves && b - a < 8 && hl[b] == hl[a] && hl[a] > 0 &&
+                   (pf[b] >> p->d) == (pf[a] >> p->d))
+                ++b;
+            gf.push_back(a);
+            ent.clear();
+            for (int c = a; c < b; ++c)
+                for (int e = np[c]; e < np[c + 1]; ++e) ent.emplace_back(ni[e], 1 << (c - a));
+            std::sort(ent.begin(), ent.end());
+            for (size_t k = 0; k < ent.size();) {
+                int m = 0;
+                size_t k2 = k;
+                while (k2 < ent.size() && ent[k2].first == ent[k].first) m |= ent[k2++].second;
+                ui.push_back(ent[k].first);
+                um.push_back(m);
+                k = k2;
+            }
+            up.push_back((int)ui.size());
+            a = b;
+        }
+        gf.push_back(nleaves);
+        p->ngroups = (int)gf.size() - 1;
+        p->nunion = (int64_t)ui.size();
+        RBF_TRY(ar.alloc((void **)&p->grp_first, sizeof(int) * gf.size()));
+        RBF_TRY(ar.alloc((void **)&p->uni_ptr, sizeof(int) * up.size()));
+        RBF_TRY(ar.alloc((void **)&p->uni_idx, sizeof(int) * std::max<size_t>(ui.size(), 1)));
+        RBF_TRY(ar.alloc((void **)&p->uni_mask, sizeof(int) * std::max<size_t>(um.size(), 1)));
+        RBF_HIP(hipMemcpyAsync(p->grp_first, gf.data(), sizeof(int) * gf.size(), hipMemcpyHostToDevice, s));
+        RBF_HIP(hipMemcpyAsync(p->uni_ptr, up.data(), sizeof(int) * up.size(), hipMemcpyHostToDevice, s));
+        if (!ui.empty()) {
+            RBF_HIP(hipMemcpyAsync(p->uni_idx, ui.data(), sizeof(int) * ui.size(), hipMemcpyHostToDevice, s));
+            RBF_HIP(hipMemcpyAsync(p->uni_mask, um.data(), sizeof(int) * um.size(), hipMemcpyHostToDevice, s));
+        }
+        RBF_HIP(hipStreamSynchronize(s));
     }
     RBF_HIP(hipStreamSynchronize(s));
     RBF_HIP(hipFree(pacc));
