@@ -506,16 +506,37 @@ __device__ __forceinline__ void m2m_body(const Desc<T> &d, int bid) {
     if (p >= P) return;
     const int a0 = d.cell_begin[c], a1 = d.cell_begin[c + 1];
     C s{0, 0};
-    for (int a = a0; a < a1; ++a) {
-        C v = d.W[(int64_t)a * P + p];
-        s.x += v.x;
-        s.y += v.y;
+    // eight leaf rows in flight per step, added in leaf order
+    for (int a = a0; a < a1; a += 8) {
+        C v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.W[(int64_t)min(a + u, a1 - 1) * P + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (a + u < a1) {
+                s.x += v[u].x;
+                s.y += v[u].y;
+            }
     }
     d.Wc[c * P + p] = s;
 }
 
 // Coarse translation: box sum of radius r along one axis of the dense coarse grid.
 // Pass k reads the output of pass k-1 (the first reads Wc) and the last writes Lc.
+// Grids with at most kLineMax cells per side run one workgroup per (line along the axis,
+// 256-entry chunk): each thread holds the line's values in registers, so every cell is
+// read once per pass; larger grids run one workgroup per (cell, chunk).  Either way each
+// output adds its inputs in increasing order along the axis.
+constexpr int kLineMax = 16;
+
+__host__ __device__ constexpr bool axis_by_lines(int lc) { return lc >= 1 && (1 << lc) <= kLineMax; }
+
+template <int D> __device__ __forceinline__ int64_t axis_bits(int64_t v, int lc, int axis) {
+    int64_t ins = 0;
+    for (int b = 0; b < lc; ++b) ins |= ((v >> b) & 1) << (b * D + axis);
+    return ins;
+}
+
 template <class T, int D>
 __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bid) {
     using C = typename cplx<T>::type;
@@ -531,21 +552,52 @@ __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bi
     }
     const C *in = (axis == 0) ? d.Wc : ((axis % 2 == 1) ? d.Tmp : d.Wc);
     C *out = (axis == D - 1) ? d.Lc : ((axis % 2 == 0) ? d.Tmp : d.Wc);
-    int64_t cc = 0, mask = 0;
-    for (int b = 0; b < lc; ++b) {
-        cc |= ((c >> (b * D + axis)) & 1) << b;
-        mask |= (int64_t)1 << (b * D + axis);
-    }
+    int64_t mask = 0;
+    for (int b = 0; b < lc; ++b) mask |= (int64_t)1 << (b * D + axis);
     const int64_t side = (int64_t)1 << lc;
+    if (axis_by_lines(lc)) {
+        // c numbers the line: the other axes' bits of its cells, packed (the axis bits removed)
+        int64_t rest = 0;
+        {
+            int k = 0;
+            for (int b = 0; b < lc * D; ++b)
+                if (!((mask >> b) & 1)) rest |= ((c >> k++) & 1) << b;
+        }
+        C v[kLineMax];
+#pragma unroll
+        for (int k = 0; k < kLineMax; ++k)
+            if (k < side) v[k] = in[(rest | axis_bits<D>(k, lc, axis)) * P + p];
+        const int r = d.r;
+#pragma unroll
+        for (int k = 0; k < kLineMax; ++k) {
+            if (k >= side) break;
+            C acc{0, 0};
+#pragma unroll
+            for (int j = 0; j < kLineMax; ++j)
+                if (j < side && j >= k - r && j <= k + r) {
+                    acc.x += v[j].x;
+                    acc.y += v[j].y;
+                }
+            out[(rest | axis_bits<D>(k, lc, axis)) * P + p] = acc;
+        }
+        return;
+    }
+    int64_t cc = 0;
+    for (int b = 0; b < lc; ++b) cc |= ((c >> (b * D + axis)) & 1) << b;
     const int64_t lo = max((int64_t)0, cc - d.r), hi = min(side - 1, cc + d.r);
     const int64_t rest = c & ~mask;
     C s{0, 0};
-    for (int64_t v = lo; v <= hi; ++v) {
-        int64_t ins = 0;
-        for (int b = 0; b < lc; ++b) ins |= ((v >> b) & 1) << (b * D + axis);
-        C x = in[(rest | ins) * P + p];
-        s.x += x.x;
-        s.y += x.y;
+    // eight cells in flight per step, added in order along the axis
+    for (int64_t v0 = lo; v0 <= hi; v0 += 8) {
+        C x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = in[(rest | axis_bits<D>(min(v0 + u, hi), lc, axis)) * P + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (v0 + u <= hi) {
+                s.x += x[u].x;
+                s.y += x[u].y;
+            }
     }
     out[c * P + p] = s;
 }
@@ -936,7 +988,8 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
             if (!kExpMfma<T>) return d.ntasks;
             return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
         case PH_P2M: return (int64_t)d.nleaves * d.wpl;
-        case PH_M2M: case PH_M2L_AXIS: return d.ncells * nch;
+        case PH_M2M: return d.ncells * nch;
+        case PH_M2L_AXIS: return (axis_by_lines(d.lc) ? d.ncells >> d.lc : d.ncells) * nch;
         case PH_M2L_LEAF: {
             const int64_t nch_l = (d.P + kThreads - 1) / kThreads;
             if (d.m2l_sched == 1) return 8 * nch_l * ((d.ngroups + 7) / 8);
