@@ -246,6 +246,72 @@ def run_solve(args):
     print(json.dumps(result), flush=True)
 
 
+def run_c4(args):
+    """5-D: N = 2^18 uniform in [0,1]^5, Gaussian s = 0.2, float32 at tol 1e-5 (tensor-product
+    quadrature over all five dimensions).  The fast product (leaf capacity 512) is timed with
+    the device direct sum beside it; the oracle checks 2048 sampled targets."""
+    import torch
+
+    from paper_1606_07652_amd import FmmPlan
+    from workloads import c4
+
+    w = c4(n=args.n_c4)
+    n = w.points.shape[0]
+    X = torch.as_tensor(w.points, device="cuda:0")
+    lam = torch.as_tensor(w.lam, device="cuda:0")
+    t0 = time.perf_counter()
+    plan = FmmPlan(X, kernel="gaussian", shape=w.shape, tol=w.tol, n_max=512)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    log(f"[bench] 5-D plan {plan_ms:.0f} ms: nodes={info['nodes']} leaves={info['nleaves']} "
+        f"far={info['far_field']} near_pairs={info['near_pairs']}")
+    u = torch.empty_like(lam)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn(lam, u)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            fn(lam, u)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3 / steps
+
+    ms = timed(plan.matvec, args.steps, args.warmup)
+    u_fmm = u.double().cpu().numpy()
+    plan.set_profiling(True)
+    for _ in range(args.steps):
+        plan.matvec(lam, u)
+    torch.cuda.synchronize()
+    ph = plan.phase_times()
+    plan.set_profiling(False)
+    calls = max(ph.pop("calls"), 1)
+    ms_direct = timed(plan.direct, max(2, args.steps // 5), 1)
+    u_dir = u.double().cpu().numpy()
+    result = {"metric": "RBF-FMM matvec points/s @ rel-L2<=1e-5 (5-D)", "value": n / (ms * 1e-3),
+              "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+              "data": "synthetic",
+              "config": {"workload": "5d_uniform_gaussian_s0.2", "n": n, "tol": w.tol, "n_max": 512,
+                         "nodes": info["nodes"], "leaves": info["nleaves"], "half_nodes": info["half_nodes"]},
+              "plan_ms": plan_ms, "phase_ms": {k: v / calls for k, v in ph.items()},
+              "direct_ms_per_step": ms_direct, "direct_points_per_s": n / (ms_direct * 1e-3)}
+    if not args.no_cpu:
+        from oracle import direct
+        rng = np.random.default_rng(4)
+        idx = np.sort(rng.choice(n, 2048, replace=False))
+        xs = w.points.astype(np.float64)
+        t1 = time.perf_counter()
+        ref = direct.direct_sum(xs, w.lam.astype(np.float64), "gaussian", w.shape, targets=xs[idx])
+        tcpu = time.perf_counter() - t1
+        result["rel_l2_sampled"] = direct.rel_l2(u_fmm[idx], ref)
+        result["direct_rel_l2_sampled"] = direct.rel_l2(u_dir[idx], ref)
+        result["cpu_baseline"] = {"value": 2048 / tcpu, "unit": "points/s", "cores": direct.threads(),
+                                  "kind": "oracle", "sample": f"2048 seeded targets x all {n} sources ({tcpu:.1f} s)"}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,7 +325,8 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4"])
+    ap.add_argument("--n-c4", type=int, default=1 << 18)
     ap.add_argument("--n-solve", type=int, default=1 << 21)
     ap.add_argument("--solve-iters", type=int, default=300)
     ap.add_argument("--nprob", type=int, default=512)
@@ -275,6 +342,8 @@ def main():
         return run_batched(args)
     if args.workload == "solve":
         return run_solve(args)
+    if args.workload == "c4":
+        return run_c4(args)
 
     import torch
 
