@@ -166,8 +166,10 @@ int rbf_fmm_phase_times(const rbf_plan *plan, double *ms, int64_t *calls);
 
 /* ---- measuring autotuner ------------------------------------------------------------
  * Plans each candidate configuration for the given points (leaf capacity 64, 128, 256,
- * 512 on top of *base, and a near-only tree: uniform at the deepest level whose cells are
- * at least the pruning radius wide, so that every kept pair is a near pair), times `reps`
+ * 512 on top of *base; a near-only tree: uniform at the deepest level whose cells are at
+ * least the pruning radius wide, so that every kept pair is a near pair; and, when the
+ * pruning radius is at least half the extent and n <= 2^19, a single leaf holding every
+ * point, which is the direct sum), times `reps`
  * products of each with HIP events on `stream`, and writes the fastest configuration to
  * *best (host) and its time per product to *best_ms (host, may be NULL).  Arguments as in
  * rbf_fmm_plan; base may be NULL.  Synchronous; allocates and frees temporary plans. */

@@ -8,9 +8,10 @@
 // batch's own stream and replayed on every call; the graph is captured again only when
 // the caller passes different vector pointers.
 //
-// The autotuner plans each candidate configuration (leaf capacity 64..512, and a
-// near-only tree whose cells are at least the pruning radius wide), times a few products
-// with HIP events and keeps the fastest.
+// The autotuner plans each candidate configuration (leaf capacity 64..512, a near-only
+// tree whose cells are at least the pruning radius wide, and -- when nothing can be pruned
+// -- a single leaf, i.e. the direct sum), times a few products with HIP events and keeps
+// the fastest.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -73,6 +74,18 @@ std::vector<rbf_opts> candidates(const rbf_opts *base, int64_t n, int d, double 
         c.coarse_radius = 1;
         c.min_level = lstar;
         c.max_level = lstar;
+        c.nodes = 4;
+        c.n_max = 1 << 30;
+        out.push_back(c);
+    }
+    // one leaf holding every point (the direct sum through the near-field kernel) when no
+    // pair can be pruned and the sum stays small enough to time
+    if (rcut >= 0.5 * ext && n <= (1 << 19)) {
+        rbf_opts c = o;
+        c.coarse_level = 0;
+        c.coarse_radius = 0;
+        c.min_level = 0;
+        c.max_level = 0;
         c.nodes = 4;
         c.n_max = 1 << 30;
         out.push_back(c);

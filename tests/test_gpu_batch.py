@@ -131,3 +131,25 @@ def test_autotune_single_problem():
     ref = direct.direct_sum(x.astype(np.float32).astype(np.float64), lam.astype(np.float32).astype(np.float64),
                             "gaussian", 0.03)
     assert direct.rel_l2(u, ref) <= 1e-4
+
+
+def test_single_leaf_plan_is_the_direct_sum():
+    """A tree of one leaf (the autotuner's candidate when nothing can be pruned) evaluates
+    every pair in the near field: it equals the device direct sum and the oracle."""
+    from paper_1606_07652_amd import FmmPlan, autotune
+    x = uniform_points(3000, 5, 41)
+    lam = normal_weights(3000, 42)
+    X = dev(x, torch.float64)
+    kw = dict(n_max=1 << 30, max_level=0, min_level=0, coarse_level=0, coarse_radius=0, nodes=4)
+    p = FmmPlan(X, kernel="gaussian", shape=0.2, tol=1e-6, **kw)
+    inf = p.info()
+    assert inf["nleaves"] == 1 and inf["far_field"] == 0 and inf["near_pairs"] == 3000 * 3000
+    L = dev(lam, torch.float64)
+    u = p.matvec(L).cpu().numpy()
+    ud = p.direct(L).cpu().numpy()
+    assert np.max(np.abs(u - ud)) <= 1e-12 * np.max(np.abs(ud))
+    assert direct.rel_l2(u, direct.direct_sum(x, lam, "gaussian", 0.2)) <= 1e-13
+    opts, ms = autotune(X, kernel="gaussian", shape=0.2, tol=1e-6, reps=2)
+    print(f"[autotune 5-D] {opts} {ms:.3f} ms", flush=True)
+    q = FmmPlan(X, kernel="gaussian", shape=0.2, tol=1e-6, **opts)
+    assert direct.rel_l2(q.matvec(L).cpu().numpy(), direct.direct_sum(x, lam, "gaussian", 0.2)) <= 1e-6
