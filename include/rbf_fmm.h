@@ -39,7 +39,9 @@ enum { RBF_OK = 0, RBF_ENOCONV = 1, RBF_EINVAL = -1, RBF_EUNSUPPORTED = -2, RBF_
 enum { RBF_F32 = 0, RBF_F64 = 1 };
 /* Kernels of the paper's table "Global functions" (section 2.2).  The Gaussian is used in
  * the shape form exp(-r^2 / (2 s^2)) (shape = s > 0); the multiquadric is sqrt(r^2 + c^2)
- * (shape = c > 0). */
+ * (shape = c > 0).  This build has no band-limited far field for the multiquadric: its plans
+ * hold a single leaf and the product is the exact O(N^2) sum through the tiled near-field
+ * kernel (tol and the tree options are ignored). */
 enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
 
@@ -69,7 +71,7 @@ typedef struct rbf_plan rbf_plan;
  *   stream  a hipStream_t (NULL = default stream); all later work of the plan runs on it.
  *   out     host; receives the plan.  The plan owns its device memory until
  *           rbf_fmm_destroy.
- * Errors: RBF_EINVAL (bad sizes or parameters), RBF_EUNSUPPORTED (kernel, dimension or a
+ * Errors: RBF_EINVAL (bad sizes or parameters), RBF_EUNSUPPORTED (dimension or a
  * quadrature grid too large for the stated tolerance), RBF_ENOMEM, RBF_EHIP.
  * This call synchronises the stream (the tree build reads counts back). */
 int rbf_fmm_plan(const void *points, int64_t n, int d, int dtype, int kernel, double shape,

@@ -53,7 +53,33 @@ double band_t(double tol) {
     return hi;
 }
 
+// Multiquadric: this build has no band-limited far field for it (a kernel that does not
+// decay cannot be pruned, and one frequency grid for all levels would have to resolve the
+// finest near-zone width over the whole domain).  Every pair is a near pair of a single
+// leaf: the product is the exact sum, evaluated by the tiled near-field kernel.
+void multiquadric_params(rbf_plan *p) {
+    p->sigma = 1.0;
+    p->rcut = p->rfar = p->ext;
+    p->lc = 0;
+    p->r = 0;
+    p->n_max = 1 << 30;
+    p->max_level = 0;
+    p->min_level = 0;
+    p->nodes_needed = 4;
+    p->mn = 4;
+    p->H = 2;
+    p->HP = 4;
+    p->R = 1;
+    for (int k = 0; k < p->d - 1; ++k) p->R *= p->mn;
+    p->P = p->R * p->H;
+    p->L = 2.0 * M_PI / (2.0 * p->sigma / (p->mn - 1));
+}
+
 int choose_params(rbf_plan *p, const rbf_opts *o) {
+    if (p->kernel == RBF_MULTIQUADRIC) {
+        multiquadric_params(p);
+        return RBF_OK;
+    }
     const double s = p->shape, tol = p->tol;
     const int d = p->d;
     p->sigma = (o && o->band > 0) ? o->band : band_t(tol) / s;
@@ -142,10 +168,6 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (kernel != RBF_GAUSSIAN && kernel != RBF_MULTIQUADRIC) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
     if (!(shape > 0) || !std::isfinite(shape)) { set_error("rbf_fmm_plan: shape must be positive"); return RBF_EINVAL; }
     if (!(tol > 0 && tol < 1)) { set_error("rbf_fmm_plan: tol must lie in (0, 1)"); return RBF_EINVAL; }
-    if (kernel == RBF_MULTIQUADRIC) {
-        set_error("rbf_fmm_plan: the multiquadric far field is not available in this build");
-        return RBF_EUNSUPPORTED;
-    }
     rbf_plan *p = new (std::nothrow) rbf_plan();
     if (!p) { set_error("rbf_fmm_plan: out of host memory"); return RBF_ENOMEM; }
     p->n = n; p->d = d; p->dtype = dtype; p->kernel = kernel; p->shape = shape; p->tol = tol;

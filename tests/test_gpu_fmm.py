@@ -210,3 +210,30 @@ def test_full_size_mixed_sampled_targets():
         assert err <= tol
         p.close()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,bound", [(torch.float64, 1e-13), (torch.float32, 1e-5)])
+def test_multiquadric_plan_is_the_exact_sum(dtype, bound):
+    """Multiquadric plans hold one leaf: the product is the exact sum (no far field)."""
+    from paper_1606_07652_amd import FmmPlan
+    from workloads import mixed_points
+    x = mixed_points(3000, 3, 71)
+    lam = normal_weights(3000, 72)
+    X = torch.as_tensor(x, dtype=dtype, device="cuda")
+    L = torch.as_tensor(lam, dtype=dtype, device="cuda")
+    p = FmmPlan(X, kernel="multiquadric", shape=0.02, tol=1e-6, n_max=64)
+    inf = p.info()
+    assert inf["nleaves"] == 1 and inf["far_field"] == 0
+    u = p.matvec(L).double().cpu().numpy()
+    xo = X.double().cpu().numpy()
+    ref = direct.direct_sum(xo, L.double().cpu().numpy(), "multiquadric", 0.02)
+    assert direct.rel_l2(u, ref) <= bound
+    # the solve runs on it and reports the true residual of the product (checked in FP64,
+    # where the returned iterate is the one the residual was computed for)
+    ft = torch.as_tensor(np.sin(2 * np.pi * xo[:, 0]) * np.cos(2 * np.pi * xo[:, 1]), dtype=dtype, device="cuda")
+    lam2, info = p.solve(ft, rtol=1e-6, restart=30, max_iters=60)
+    assert np.isfinite(info["true_res"]) and info["iters"] > 0
+    if dtype == torch.float64:
+        fh = ft.cpu().numpy()
+        r = fh - p.matvec(lam2).cpu().numpy()
+        assert abs(np.linalg.norm(r) / np.linalg.norm(fh) - info["true_res"]) <= 1e-6 * info["true_res"] + 1e-12
