@@ -210,6 +210,20 @@ typedef struct rbf_batch_info {
 int rbf_fmm_batch_info(const rbf_batch *batch, rbf_batch_info *info, int32_t *n_max, int32_t *nodes);
 int rbf_fmm_batch_destroy(rbf_batch *batch);
 
+/* Solve A_p lambda_p = f_p for every problem of a batch with restarted GMRES (section 1),
+ * all problems together: each Arnoldi step is one batched product, the projections (CGS2,
+ * FP64) are segmented per problem, and every problem keeps its own Hessenberg matrix, Givens
+ * rotations and stopping test (true residual ||f_p - A_p lambda_p|| / ||f_p|| <= rtol,
+ * recomputed at every restart; a problem that stops early takes zero directions).
+ *   f, lambda  device, concatenated like the points, batch dtype; lambda is the initial
+ *              guess (unless opts->zero_init) and the solution.
+ *   opts       as for rbf_interp_solve; precond must be RBF_PC_NONE (else RBF_EUNSUPPORTED).
+ *   info       host array of nprob rbf_solve_info (may be NULL).
+ * Work is ordered on the batch's stream argument.  Returns RBF_OK if every problem
+ * converged, RBF_ENOCONV otherwise.  Synchronous. */
+int rbf_interp_solve_batch(rbf_batch *batch, const void *f, void *lambda, double rtol,
+                           const rbf_solve_opts *opts, rbf_solve_info *info);
+
 /* ---- right preconditioners of the solve ----------------------------------------------
  * Neither preconditioner is part of the paper (which names GMRES and says nothing about
  * preconditioning); rbf_interp_solve applies them as right preconditioners of flexible

@@ -94,6 +94,7 @@ SIGNATURES = {
     "rbf_fmm_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfBatchInfo), ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "rbf_fmm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rbf_interp_solve_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(RbfSolveOpts), _P]),
     "rbf_pc_block_jacobi": (ctypes.c_int, [_P, ctypes.c_double]),
     "rbf_pc_learned_features": (ctypes.c_int, [_P, ctypes.c_double]),
     "rbf_pc_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),

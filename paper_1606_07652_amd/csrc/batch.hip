@@ -18,32 +18,7 @@
 #include <cstring>
 #include <vector>
 
-#include "fmm_desc.h"
-#include "internal.h"
-
-struct rbf_batch {
-    int nprob = 0, d = 0, dtype = 0, kernel = 0;
-    hipStream_t user_stream = nullptr, stream = nullptr;
-    std::vector<rbf_plan *> plans;
-    std::vector<int64_t> offsets;
-    std::vector<int> n_max, nodes, far;
-    struct Group {
-        int HP = 0, nprob = 0;
-        void *descs = nullptr;
-        int *bstart[rbf::PH_COUNT] = {};
-        int64_t nblocks[rbf::PH_COUNT] = {};
-        size_t p2m_sh = 0;
-    };
-    std::vector<Group> groups;
-    rbf::Arena arena;
-    int use_graph = 1;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    const void *g_lam = nullptr;
-    void *g_u = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    double plan_seconds = 0;
-};
+#include "batch.h"
 
 namespace rbf {
 namespace {
@@ -330,9 +305,7 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
     return RBF_OK;
 }
 
-extern "C" int rbf_fmm_matvec_batch(rbf_batch *b, const void *lambda, void *u) {
-    if (!b || !lambda || !u) { set_error("rbf_fmm_matvec_batch: null argument"); return RBF_EINVAL; }
-    if (lambda == u) { set_error("rbf_fmm_matvec_batch: lambda and u must not alias"); return RBF_EINVAL; }
+int rbf::batch_product(rbf_batch *b, const void *lambda, void *u) {
     RBF_HIP(hipEventRecord(b->ev_in, b->user_stream));
     RBF_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     if (b->use_graph) {
@@ -357,6 +330,12 @@ extern "C" int rbf_fmm_matvec_batch(rbf_batch *b, const void *lambda, void *u) {
     RBF_HIP(hipEventRecord(b->ev_out, b->stream));
     RBF_HIP(hipStreamWaitEvent(b->user_stream, b->ev_out, 0));
     return RBF_OK;
+}
+
+extern "C" int rbf_fmm_matvec_batch(rbf_batch *b, const void *lambda, void *u) {
+    if (!b || !lambda || !u) { set_error("rbf_fmm_matvec_batch: null argument"); return RBF_EINVAL; }
+    if (lambda == u) { set_error("rbf_fmm_matvec_batch: lambda and u must not alias"); return RBF_EINVAL; }
+    return batch_product(b, lambda, u);
 }
 
 extern "C" int rbf_fmm_batch_set_graph(rbf_batch *b, int on) {

@@ -88,6 +88,22 @@ class BatchPlan:
         L.check(L.load().rbf_fmm_matvec_batch(self._h, _ptr(lam), _ptr(out)))
         return out
 
+    def solve(self, f: torch.Tensor, lam: Optional[torch.Tensor] = None, rtol: float = 1e-8, restart: int = 50,
+              max_iters: int = 1000, time_limit_s: float = 0.0):
+        """Restarted GMRES for every problem (rbf_interp_solve_batch); returns (lambda, [info per problem])."""
+        if f.shape != (self.n,) or f.dtype != self.dtype:
+            raise ValueError("f must be the concatenated right-hand side of all problems")
+        zero = lam is None
+        if lam is None:
+            lam = torch.zeros_like(f)
+        o = L.RbfSolveOpts(restart, max_iters, L.RBF_PC_NONE, 1 if zero else 0, 1, float(time_limit_s))
+        infos = (L.RbfSolveInfo * self.nprob)()
+        code = L.load().rbf_interp_solve_batch(self._h, _ptr(f), _ptr(lam), float(rtol), ctypes.byref(o), infos)
+        L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
+        out = [{"iters": i.iters, "restarts": i.restarts, "converged": bool(i.converged), "true_res": i.true_res,
+                "seconds": i.seconds, "history": list(i.history[:i.nhistory])} for i in infos]
+        return lam, out
+
     def set_graph(self, on: bool):
         L.check(L.load().rbf_fmm_batch_set_graph(self._h, 1 if on else 0))
 

@@ -153,3 +153,41 @@ def test_single_leaf_plan_is_the_direct_sum():
     print(f"[autotune 5-D] {opts} {ms:.3f} ms", flush=True)
     q = FmmPlan(X, kernel="gaussian", shape=0.2, tol=1e-6, **opts)
     assert direct.rel_l2(q.matvec(L).cpu().numpy(), direct.direct_sum(x, lam, "gaussian", 0.2)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype,rtol", [(torch.float64, 1e-9), (torch.float32, 1e-5)])
+def test_batched_solve_matches_single_solves(dtype, rtol):
+    """GMRES on all problems of a batch at once equals one solve per problem: the operators
+    are identical and only the blocking of the FP64 reductions differs.  One problem has a
+    zero right-hand side (converged at once, zero solution)."""
+    from paper_1606_07652_amd import BatchPlan, FmmPlan
+    from workloads import fourier_modes_rhs, jittered_grid
+    sides = [20, 28, 35, 24, 40, 30]
+    pts = [jittered_grid(sd, 2, 300 + k) for k, sd in enumerate(sides)]
+    ss = np.array([0.5 / sd for sd in sides])
+    fs = [fourier_modes_rhs(x, 400 + k) for k, x in enumerate(pts)]
+    fs[3] = np.zeros_like(fs[3])
+    off = np.concatenate([[0], np.cumsum([x.shape[0] for x in pts])]).astype(np.int64)
+    X = dev(np.concatenate(pts), dtype)
+    F = dev(np.concatenate(fs), dtype)
+    tol = 1e-8 if dtype == torch.float64 else 1e-4
+    b = BatchPlan(X, off, ss, kernel="gaussian", tol=tol)
+    lam, infos = b.solve(F, rtol=rtol, restart=30, max_iters=300)
+    lam = lam.double().cpu().numpy()
+    for q in range(len(sides)):
+        sl = slice(off[q], off[q + 1])
+        iq = infos[q]
+        print(f"[batch solve {dtype}] problem {q}: iters={iq['iters']} res={iq['true_res']:.2e}", flush=True)
+        assert iq["converged"] and iq["true_res"] <= rtol
+        if q == 3:
+            assert iq["iters"] == 0 and np.all(lam[sl] == 0)
+            continue
+        p = FmmPlan(X[sl].contiguous(), kernel="gaussian", shape=float(ss[q]), tol=tol)
+        l1, i1 = p.solve(F[sl].contiguous(), rtol=rtol, restart=30, max_iters=300)
+        assert i1["converged"] and abs(i1["iters"] - iq["iters"]) <= 2
+        assert np.linalg.norm(lam[sl] - l1.double().cpu().numpy()) <= 1e3 * rtol * np.linalg.norm(lam[sl])
+        # the batched solution's residual under the problem's own operator
+        u = p.matvec(dev(lam[sl], dtype)).double().cpu().numpy()
+        fq = F[sl].double().cpu().numpy()
+        assert np.linalg.norm(fq - u) / np.linalg.norm(fq) <= 10 * rtol
+    b.close()
