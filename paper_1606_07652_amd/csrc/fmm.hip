@@ -68,12 +68,6 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int q, int lane) { return 4 * (lane >> 4) + q; }
 };
 
-// Load through a global-address-space pointer (a plain pointer read becomes a flat load,
-// which also counts against the LDS wait counter and serialises with LDS traffic).
-template <class X> __device__ __forceinline__ X gld(const X *p) {
-    return *(const __attribute__((address_space(1))) X *)p;
-}
-
 // Row digits (m_0 .. m_{d-2}, fastest last) of an expansion row r < 2^22, dividing by mn
 // with a multiply-high (exact in that range for every mn up to 128).
 template <int DM>
@@ -668,81 +662,7 @@ __device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
             d.Lx[((int64_t)(a0 + c) * d.R + row) * HP + h] = C{(T)(f * s[c].x), (T)(f * s[c].y)};
 }
 
-// Disaggregation (L2P) + combine on the vector ALUs (the FP64 path).  One wave per task (up to 64 target points of one
-// leaf), one lane per target.  The lane keeps e^{+i xi_{H+h} x_d} for all h in registers
-// and walks the rows with an FP64 odometer recurrence for the other factors; the leaf's
-// L rows (padded to HMAX) are uniform across the wave and come through scalar loads.
-template <class T, int D, int HMAX>
-__device__ __forceinline__ void l2p_valu_body(const Desc<T> &d, T *__restrict__ u, int bid) {
-    using C = typename cplx<T>::type;
-    constexpr int DM = D > 1 ? D - 1 : 1;
-    const int2 tk = d.tasks[bid];
-    const int a = tk.x;
-    const int t1 = d.leaf_begin[a + 1];
-    const int ti = d.leaf_begin[a] + tk.y + threadIdx.x;
-    const bool act = ti < t1;
-    const int tj = act ? ti : t1 - 1;
-    const int R = d.R, mn = d.mn;
-    const CView<T> La = as_const<T>(d.Lx + (int64_t)a * R * HMAX);
-    double x[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = (double)d.xs[k * d.n + tj];
-    C e[HMAX];
-    {
-        double sb, cb, ss, cs;
-        sincos(d.xiH * x[D - 1], &sb, &cb);
-        sincos(d.dxi * x[D - 1], &ss, &cs);
-        double er = cb, ei = sb;
-#pragma unroll
-        for (int h = 0; h < HMAX; ++h) {
-            e[h] = C{(T)er, (T)ei};
-            double nr = er * cs - ei * ss;
-            ei = er * ss + ei * cs;
-            er = nr;
-        }
-    }
-    double br[DM], bi[DM], sr[DM], si[DM], cr[DM], ci[DM];
-    int dig[DM];
-#pragma unroll
-    for (int k = 0; k < D - 1; ++k) {
-        sincos(d.xi0 * x[k], &bi[k], &br[k]);
-        sincos(d.dxi * x[k], &si[k], &sr[k]);
-        cr[k] = br[k];
-        ci[k] = bi[k];
-        dig[k] = 0;
-    }
-    T acc = 0;
-    for (int row = 0; row < R; ++row) {
-        const CView<T> lr = La + (int64_t)row * HMAX;
-        C g{0, 0};
-#pragma unroll
-        for (int h = 0; h < HMAX; ++h) cmac(g, lr[h], e[h]);
-        double kr = cr[0], ki = ci[0];
-#pragma unroll
-        for (int k = 1; k < D - 1; ++k) {
-            double t = kr * cr[k] - ki * ci[k];
-            ki = kr * ci[k] + ki * cr[k];
-            kr = t;
-        }
-        acc = fma((T)kr, g.x, acc);
-        acc = fma(-(T)ki, g.y, acc);
-        // odometer: advance the fastest digit (k = d-2), carry towards k = 0
-        for (int k = D - 2; k >= 0; --k) {
-            if (++dig[k] < mn) {
-                double t = cr[k] * sr[k] - ci[k] * si[k];
-                ci[k] = cr[k] * si[k] + ci[k] * sr[k];
-                cr[k] = t;
-                break;
-            }
-            dig[k] = 0;
-            cr[k] = br[k];
-            ci[k] = bi[k];
-        }
-    }
-    if (act) u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * acc;
-}
-
-// Disaggregation (L2P) + combine on the matrix cores (the FP32 path).  For the targets i of a workgroup
+// Disaggregation (L2P) + combine on the matrix cores.  For the targets i of a workgroup
 // (NT of one 64-target task) and the leaf's local rows r:
 //   G[i][r] = sum_h E_i[h] L[r][h]   (E_i[h] = e^{+i xi_{H+h} x_id}),   a real product over
 //   K' = 2 HMAX with A'[i][2h] = Re E, A'[i][2h+1] = Im E, B_re = [Re L; -Im L], B_im = [Im L; Re L];
@@ -809,52 +729,44 @@ __device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, in
     for (int it = 0; it < IT; ++it)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[it][q] = 0;
-    const T *La = reinterpret_cast<const T *>(d.Lx + (int64_t)a * R * HMAX);
+    const C *La = d.Lx + (int64_t)a * R * HMAX;
     const int NR = (R + 15) / 16;
-    // B fragments of a row tile, loaded unconditionally from a clamped row and masked
-    auto load_b = [&](int rt, T (&br)[KS], T (&bi)[KS]) {
+    for (int rt = wave; rt < NR; rt += 4) {
         const int r = rt * 16 + lr;
         const bool rv = r < R;
-        const T *q = La + ((int64_t)min(r, R - 1) * HMAX + hsel) * 2;
+        // B fragments of the row tile (a row past the end reads as zero), then per target tile
+        // the MFMA chain and the stage-2 sums of its rows
+        T br[KS], bi[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const T x = gld(q + 4 * s), y = gld(q + 4 * s + 1);
-            br[s] = rv ? (csel ? -y : x) : T(0);
-            bi[s] = rv ? (csel ? x : y) : T(0);
+            const C l = rv ? La[(int64_t)r * HMAX + 2 * s + hsel] : C{0, 0};
+            br[s] = csel ? -l.y : l.x;
+            bi[s] = csel ? l.x : l.y;
         }
-    };
-    T br[KS], bi[KS];
-    if (wave < NR) load_b(wave, br, bi);
-    for (int rt = wave; rt < NR; rt += 4) {
-        T nr_[KS], ni_[KS];
-        load_b(min(rt + 4, NR - 1), nr_, ni_);         // next tile of this wave, one step ahead
-        const int r = rt * 16 + lr;
         int md[DM];
-        row_digits<DM>((unsigned)min(r, R - 1), mn, d.mn_magic, md);
-        // 2 IT independent accumulation chains, interleaved
-        V gr[IT], gi[IT];
+        {
+            int rr = rv ? r : 0;
 #pragma unroll
-        for (int it = 0; it < IT; ++it) { gr[it] = V{0, 0, 0, 0}; gi[it] = V{0, 0, 0, 0}; }
+            for (int k = DM - 1; k >= 0; --k) { md[k] = rr % mn; rr /= mn; }
+        }
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int it = 0; it < IT; ++it) {
+            V gr = V{0, 0, 0, 0}, gi = V{0, 0, 0, 0};
 #pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                gr[it] = M::mac(afr[it][s], br[s], gr[it]);
-                gi[it] = M::mac(afr[it][s], bi[s], gi[it]);
+            for (int s = 0; s < KS; ++s) {
+                gr = M::mac(afr[it][s], br[s], gr);
+                gi = M::mac(afr[it][s], bi[s], gi);
             }
-#pragma unroll
-        for (int it = 0; it < IT; ++it)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = 16 * it + M::row(q, lane);
                 C kv = Tt[i * mn + md[0]];
 #pragma unroll
                 for (int k = 1; k < DM; ++k) kv = cmul(kv, Tt[(k * NT + i) * mn + md[k]]);
-                acc[it][q] = fma(kv.x, gr[it][q], acc[it][q]);
-                acc[it][q] = fma(-kv.y, gi[it][q], acc[it][q]);
+                acc[it][q] = fma(kv.x, gr[q], acc[it][q]);
+                acc[it][q] = fma(-kv.y, gi[q], acc[it][q]);
             }
-#pragma unroll
-        for (int s = 0; s < KS; ++s) { br[s] = nr_[s]; bi[s] = ni_[s]; }
+        }
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
@@ -929,9 +841,9 @@ template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) 
     const Desc<T> &d = resolve(w, lb);
     phase_dl_body<T, D, HMAX>(d, lb);
 }
-// FP64 runs the aggregation and disaggregation on the vector ALUs: on this chip the FP64
-// matrix rate equals the FP64 vector rate, and the VALU kernels measured as fast or faster.
-// FP32 uses the matrix cores (twice the vector rate without packed FP32).
+// The FP64 aggregation runs on the vector ALUs: on this chip the FP64 matrix rate equals the
+// FP64 vector rate, and its VALU kernel measured faster than the MFMA one.  FP32 aggregation
+// and the disaggregation in both precisions use the matrix cores.
 template <class T> constexpr bool kExpMfma = sizeof(T) == 4;
 
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_p2m(Work<T> w) {
@@ -960,8 +872,7 @@ template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) 
     extern __shared__ char smem_raw[];
     int lb;
     const Desc<T> &d = resolve(w, lb);
-    if constexpr (kExpMfma<T>) l2p_body<T, D, HMAX>(d, w.u, lb, smem_raw);
-    else l2p_valu_body<T, D, HMAX>(d, w.u, lb);
+    l2p_body<T, D, HMAX>(d, w.u, lb, smem_raw);
 }
 
 // ---- host side -----------------------------------------------------------------------
@@ -985,7 +896,6 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
         case PH_GATHER: case PH_PHASE_DL: case PH_DIRECT: return nb_pts;
         case PH_P2P: return d.ntasks;
         case PH_L2P:
-            if (!kExpMfma<T>) return d.ntasks;
             return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
         case PH_P2M: return (int64_t)d.nleaves * d.wpl;
         case PH_M2M: return d.ncells * nch;
@@ -1023,8 +933,8 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
         case PH_M2L_LEAF: k_m2l_leaf<T, D><<<g, kThreads, 0, s>>>(w); break;
         case PH_L2P: {
             constexpr int csz = (int)sizeof(typename cplx<T>::type);
-            constexpr size_t lds = kExpMfma<T> ? l2p_lds(csz, D, HMAX, l2p_targets(csz, D, HMAX)) : 0;
-            k_l2p<T, D, HMAX><<<g, kExpMfma<T> ? kThreads : kWave, lds, s>>>(w);
+            constexpr size_t lds = l2p_lds(csz, D, HMAX, l2p_targets(csz, D, HMAX));
+            k_l2p<T, D, HMAX><<<g, kThreads, lds, s>>>(w);
             break;
         }
     }
