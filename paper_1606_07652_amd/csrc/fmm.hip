@@ -431,50 +431,32 @@ __device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_r
             }
         }
         __syncthreads();
-        // B fragments of K step j0 (points j0, j0 + 1): the point's phases for h = 16 u + lr,
-        // read from LDS at a clamped index and masked, one step ahead
-        auto load_b = [&](int j0, T (&vr)[HT], T (&vi)[HT]) {
+        // K step j0 covers points j0 and j0 + 1; a point past the end of the chunk is clamped
+        // and its B entries are zero
+        for (int j0 = 0; j0 < cn; j0 += 2) {
             const int jl = j0 + jsel;
             const int jc = min(jl, cn - 1);
+            T bre[HT], bim[HT];
 #pragma unroll
             for (int u = 0; u < HT; ++u) {
-                const int h = min(16 * u + lr, HMAX - 1);
-                const C v = dls[jc * HMAX + h];
-                const bool ok = jl < cn && 16 * u + lr < HMAX;
-                vr[u] = ok ? (csel ? -v.y : v.x) : T(0);
-                vi[u] = ok ? (csel ? v.x : v.y) : T(0);
+                const int h = 16 * u + lr;
+                const C v = (jl < cn && h < HMAX) ? dls[jc * HMAX + h] : C{0, 0};
+                bre[u] = csel ? -v.y : v.x;
+                bim[u] = csel ? v.x : v.y;
             }
-        };
-        // A fragments of K step j0: one entry of KV_j[r] per row tile (a point past the end
-        // of the leaf is clamped; its B entries are zero)
-        auto load_a = [&](int j0, T (&av)[NRT]) {
-            const C *pt = tab + min(j0 + jsel, cn - 1) * ST;
+            const C *pt = tab + jc * ST;
 #pragma unroll
             for (int t = 0; t < NRT; ++t) {
                 C kv = pt[md[t][0]];
 #pragma unroll
                 for (int k = 1; k < DM; ++k) kv = cmul(kv, pt[k * mn + md[t][k]]);
-                av[t] = csel ? kv.y : kv.x;
-            }
-        };
-        T bre[HT], bim[HT], av[NRT];
-        load_b(0, bre, bim);
-        load_a(0, av);
-        for (int j0 = 0; j0 < cn; j0 += 2) {
-            T nre[HT], nim[HT], nav[NRT];
-            load_b(j0 + 2, nre, nim);                 // next step (clamped past the end)
-            load_a(j0 + 2, nav);
-#pragma unroll
-            for (int t = 0; t < NRT; ++t)
+                const T av = csel ? kv.y : kv.x;
 #pragma unroll
                 for (int u = 0; u < HT; ++u) {
-                    wr[t][u] = M::mac(av[t], bre[u], wr[t][u]);
-                    wi[t][u] = M::mac(av[t], bim[u], wi[t][u]);
+                    wr[t][u] = M::mac(av, bre[u], wr[t][u]);
+                    wi[t][u] = M::mac(av, bim[u], wi[t][u]);
                 }
-#pragma unroll
-            for (int u = 0; u < HT; ++u) { bre[u] = nre[u]; bim[u] = nim[u]; }
-#pragma unroll
-            for (int t = 0; t < NRT; ++t) av[t] = nav[t];
+            }
         }
     }
     C *out = d.W + (int64_t)a * R * H;
