@@ -41,7 +41,10 @@ def phase_model(info, dtype_bytes, n):
     pairs = info["near_pairs"]
     return {
         # (kind, amount): flops for ALU-bound phases, bytes for memory-bound ones
-        "p2p": ("alu", pairs * (3 * d + 3)),
+        # per near pair: d differences, d multiply-adds for r^2, one scaling and one
+        # multiply-add into the sum (3d + 3 flops), plus the FP64 exponential, which has no
+        # hardware instruction: counted as the 22 flops of its degree-11 polynomial
+        "p2p": ("alu", pairs * (3 * d + 3 + 22)),
         "p2m": ("alu", 8.0 * n * P),
         "l2p": ("alu", 8.0 * n * P),
         "m2m": ("hbm", (nl + nc) * P * cb),
