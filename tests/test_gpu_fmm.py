@@ -237,3 +237,32 @@ def test_multiquadric_plan_is_the_exact_sum(dtype, bound):
         fh = ft.cpu().numpy()
         r = fh - p.matvec(lam2).cpu().numpy()
         assert abs(np.linalg.norm(r) / np.linalg.norm(fh) - info["true_res"]) <= 1e-6 * info["true_res"] + 1e-12
+
+
+@pytest.mark.parametrize("d,n,s,tol", [(2, 6000, 0.01, 1e-4), (5, 4000, 0.3, 1e-4)])
+def test_fp32_matrix_core_path_meets_tolerance(d, n, s, tol):
+    """FP32 aggregation/disaggregation on the matrix cores in 2-D (up to two 16-wide node
+    tiles) and 5-D, against the FP64 direct sum of the same (float-rounded) inputs."""
+    from paper_1606_07652_amd import FmmPlan
+    x = uniform_points(n, d, 80 + d).astype(np.float32)
+    lam = normal_weights(n, 90 + d).astype(np.float32)
+    p = FmmPlan(torch.as_tensor(x, device="cuda"), kernel="gaussian", shape=s, tol=tol, n_max=64)
+    inf = p.info()
+    print(f"[fp32 d={d}] nodes={inf['nodes']} leaves={inf['nleaves']} far={inf['far_field']}", flush=True)
+    assert inf["far_field"] == 1
+    u = p.matvec(torch.as_tensor(lam, device="cuda")).double().cpu().numpy()
+    ref = direct.direct_sum(x.astype(np.float64), lam.astype(np.float64), "gaussian", s)
+    assert direct.rel_l2(u, ref) <= tol
+
+
+def test_fp64_many_nodes_uses_the_small_target_tiles():
+    """56 nodes per dimension in 3-D FP64: the disaggregation's phase tables for 32 targets
+    would exceed 64 KiB of LDS, so it runs 16 targets per workgroup."""
+    from paper_1606_07652_amd import FmmPlan
+    x = uniform_points(5000, 3, 95)
+    lam = normal_weights(5000, 96)
+    p = FmmPlan(dev(x), kernel="gaussian", shape=0.03, tol=1e-6, n_max=64, nodes=56)
+    inf = p.info()
+    assert inf["nodes"] == 56 and inf["far_field"] == 1
+    u = p.matvec(dev(lam)).cpu().numpy()
+    assert direct.rel_l2(u, direct.direct_sum(x, lam, "gaussian", 0.03)) <= 1e-6
