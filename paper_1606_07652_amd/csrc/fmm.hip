@@ -157,11 +157,22 @@ template <class T> __device__ __forceinline__ CView<T> as_const(const typename c
     return CView<T>{(cptr<T>)(const T *)(((uint64_t)hi << 32) | lo)};
 }
 
+// A wave-uniform read-only int array, read with scalar loads.
+__device__ __forceinline__ cptr<int> uconst(const int *q) {
+    const uint64_t a = (uint64_t)q;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (cptr<int>)(const int *)(((uint64_t)hi << 32) | lo);
+}
+
+// A per-problem descriptor read through the constant address space (see resolve()).
+template <class T> using DescC = const __attribute__((address_space(4))) Desc<T>;
+
 // ---- bodies --------------------------------------------------------------------------
 
 // permutation of the coefficients into Morton order
 template <class T>
-__device__ __forceinline__ void gather_body(const Desc<T> &d, const T *__restrict__ lam, int bid) {
+__device__ __forceinline__ void gather_body(DescC<T> &d, const T *__restrict__ lam, int bid) {
     int64_t i = bid * (int64_t)kThreads + threadIdx.x;
     if (i < d.n) d.lam_s[i] = lam[d.off + d.perm[i]];
 }
@@ -170,7 +181,7 @@ __device__ __forceinline__ void gather_body(const Desc<T> &d, const T *__restric
 // merged point ranges of the leaf's near list, staged through LDS in tiles of kTile
 // points (x_1..x_d, lam).
 template <class T, int D, int KER>
-__device__ __forceinline__ void p2p_body(const Desc<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     __shared__ int rb[kTile], roff[kTile + 1];
@@ -236,7 +247,7 @@ __device__ __forceinline__ void p2p_body(const Desc<T> &d, T *__restrict__ u, in
 
 // Exact product over all pairs (rows of targets per workgroup, all sources tiled).
 template <class T, int D, int KER>
-__device__ __forceinline__ void direct_body(const Desc<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int bid) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     const T *__restrict__ xs = d.xs;
@@ -273,7 +284,7 @@ __device__ __forceinline__ void direct_body(const Desc<T> &d, T *__restrict__ u,
 // Last-dimension phases, weighted by lambda: dl[i][h] = lam_i e^{-i xi_{H+h} x_{i,d}} for
 // h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void phase_dl_body(const Desc<T> &d, int bid) {
+__device__ __forceinline__ void phase_dl_body(DescC<T> &d, int bid) {
     using C = typename cplx<T>::type;
     const int64_t i = bid * (int64_t)kThreads + threadIdx.x;
     if (i >= d.n) return;
@@ -298,7 +309,7 @@ __device__ __forceinline__ void phase_dl_body(const Desc<T> &d, int bid) {
 // last-dimension phases of a point are uniform across the block and come through scalar
 // loads.
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void p2m_valu_body(const Desc<T> &d, int bid, char *smem_raw) {
+__device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_raw) {
     using C = typename cplx<T>::type;
     C *tab = reinterpret_cast<C *>(smem_raw);
     constexpr int DM = D > 1 ? D - 1 : 1;
@@ -385,7 +396,7 @@ __device__ __forceinline__ void p2m_valu_body(const Desc<T> &d, int bid, char *s
 // (FP64 recurrences stored in T); the A fragment of a lane is one complex product of
 // those, the B fragment one entry of the point's lambda-weighted phases.
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_raw) {
+__device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
     using C = typename cplx<T>::type;
     using M = Mfma<T>;
     using V = typename M::V;
@@ -473,7 +484,7 @@ __device__ __forceinline__ void p2m_body(const Desc<T> &d, int bid, char *smem_r
 
 // Upward pass: coarse cell = sum of its leaves.  Blocks (cell, 256-node chunk).
 template <class T>
-__device__ __forceinline__ void m2m_body(const Desc<T> &d, int bid) {
+__device__ __forceinline__ void m2m_body(DescC<T> &d, int bid) {
     using C = typename cplx<T>::type;
     const int64_t P = d.P;
     const int nch = (int)((P + kThreads - 1) / kThreads);
@@ -514,7 +525,7 @@ template <int D> __device__ __forceinline__ int64_t axis_bits(int64_t v, int lc,
 }
 
 template <class T, int D>
-__device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bid) {
+__device__ __forceinline__ void m2l_axis_body(DescC<T> &d, int axis, int bid) {
     using C = typename cplx<T>::type;
     const int64_t P = d.P;
     const int nch = (int)((P + kThreads - 1) / kThreads);
@@ -526,8 +537,9 @@ __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bi
         if (axis == 0) d.Lc[c * P + p] = d.Wc[c * P + p];
         return;
     }
-    const C *in = (axis == 0) ? d.Wc : ((axis % 2 == 1) ? d.Tmp : d.Wc);
-    C *out = (axis == D - 1) ? d.Lc : ((axis % 2 == 0) ? d.Tmp : d.Wc);
+    C *const Wc = d.Wc, *const Tmp = d.Tmp, *const Lc = d.Lc;   // values, not field addresses
+    const C *in = (axis == 0) ? Wc : ((axis % 2 == 1) ? Tmp : Wc);
+    C *out = (axis == D - 1) ? Lc : ((axis % 2 == 0) ? Tmp : Wc);
     int64_t mask = 0;
     for (int b = 0; b < lc; ++b) mask |= (int64_t)1 << (b * D + axis);
     const int64_t side = (int64_t)1 << lc;
@@ -581,7 +593,7 @@ __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bi
 // Leaf translation + downward pass.  Blocks (sibling group, 256-entry chunk of the
 // expansion): the group's members (at most 8 consecutive leaves with one parent) share one
 // ascending list of the leaves near any of them, with a mask of the members each entry is
-// near to; every near row is loaded once for the whole group and subtracted from the
+// near to (padded to whole steps of 8 with entries of no member); every near row is loaded once for the whole group and subtracted from the
 // members' copies of their coarse cell's local expansion (the same sequence of operations
 // per member as a per-leaf walk of its own near list).  The quadrature weight w(xi) C(xi)
 // is applied on output.  Output rows are padded to HP entries; the padding was zeroed at
@@ -590,7 +602,7 @@ __device__ __forceinline__ void m2l_axis_body(const Desc<T> &d, int axis, int bi
 // into 8 contiguous group ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
 // the near rows a range re-reads stay in one XCD's L2.  Batches use 0.
 template <class T, int D>
-__device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
+__device__ __forceinline__ void m2l_leaf_body(DescC<T> &d, int g) {
     using C = typename cplx<T>::type;
     const int ng = d.ngroups, H = d.H, HP = d.HP;
     const int P = (int)d.P;
@@ -607,41 +619,66 @@ __device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
         grp = g % ng;
         chunk = g / ng;
     }
-    const int p = chunk * kThreads + (int)threadIdx.x;
-    if (p >= P) return;
-    const int a0 = d.grp_first[grp], na = d.grp_first[grp + 1] - a0;
+    // lanes past the end of the expansion read its last entry and store nothing, so that the
+    // loop below stays in wave-uniform control flow (its indices and masks are scalar loads)
+    const int pl = chunk * kThreads + (int)threadIdx.x;
+    const bool live = pl < P;
+    const int p = live ? pl : P - 1;
+    const cptr<int> gfirst = uconst(d.grp_first), uptr = uconst(d.uni_ptr);
+    const cptr<int> uidx = uconst(d.uni_idx), umask = uconst(d.uni_mask), lcell = uconst(d.leaf_cell);
+    const C *const W = d.W, *const Lc = d.Lc;
+    const int a0 = gfirst[grp], na = gfirst[grp + 1] - a0;
     C s[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        if (c < na) s[c] = d.Lc[(int64_t)d.leaf_cell[a0 + c] * P + p];
-    const int e0 = d.uni_ptr[grp], e1 = d.uni_ptr[grp + 1];
-    // eight near rows in flight per step (entries past the end repeat the last with mask 0)
+        if (c < na) s[c] = Lc[(int64_t)lcell[a0 + c] * P + p];
+    // The list holds whole steps of 8 (padding entries have no members) and one readable
+    // step past its end: the next step's indices and masks are fetched while this step's
+    // near rows load.
+    const int e0 = uptr[grp], e1 = uptr[grp + 1];
+    int bn[8], mn[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        bn[u] = uidx[e0 + u];
+        mn[u] = umask[e0 + u];
+    }
     for (int e = e0; e < e1; e += 8) {
         int b[8], m[8];
-        C v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int k = min(e + u, e1 - 1);
-            b[u] = __builtin_amdgcn_readfirstlane(d.uni_idx[k]);
-            m[u] = e + u < e1 ? __builtin_amdgcn_readfirstlane(d.uni_mask[k]) : 0;
+            b[u] = bn[u];
+            m[u] = mn[u];
         }
+        C v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = d.W[(int64_t)b[u] * P + p];
+        for (int u = 0; u < 8; ++u) v[u] = W[(int64_t)b[u] * P + p];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 8; ++u) {
+            bn[u] = uidx[e + 8 + u];
+            mn[u] = umask[e + 8 + u];
+        }
+        // keep all eight row loads ahead of the sums (the scheduler would otherwise interleave
+        // them with the arithmetic to save registers, leaving one or two loads in flight)
+        __builtin_amdgcn_sched_barrier(0);
+        // member c takes s - v (an fma with the scalar 1), a non-member s + 0 (fma with 0):
+        // two FMAs per pair instead of a subtract and a select of each half
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if ((m[u] >> c) & 1) {
-                    s[c].x -= v[u].x;
-                    s[c].y -= v[u].y;
+        for (int c = 0; c < 8; ++c)
+            if (c < na)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const T k = ((m[u] >> c) & 1) ? T(-1) : T(0);
+                    s[c].x = fma(k, v[u].x, s[c].x);
+                    s[c].y = fma(k, v[u].y, s[c].y);
                 }
     }
+    if (!live) return;
     const double f = d.wtab[p];
     const int row = p / H, h = p - row * H;
+    C *const Lx = d.Lx;
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        if (c < na)
-            d.Lx[((int64_t)(a0 + c) * d.R + row) * HP + h] = C{(T)(f * s[c].x), (T)(f * s[c].y)};
+        if (c < na) Lx[((int64_t)(a0 + c) * d.R + row) * HP + h] = C{(T)(f * s[c].x), (T)(f * s[c].y)};
 }
 
 // Disaggregation (L2P) + combine on the matrix cores.  For the targets i of a workgroup
@@ -653,7 +690,7 @@ __device__ __forceinline__ void m2l_leaf_body(const Desc<T> &d, int g) {
 // LDS (FP64 recurrences stored in T); per-target sums are reduced over the 16 lanes of a row
 // group and then over the waves in a fixed order.
 template <class T, int D, int HMAX>
-__device__ __forceinline__ void l2p_body(const Desc<T> &d, T *__restrict__ u, int bid, char *smem_raw) {
+__device__ __forceinline__ void l2p_body(DescC<T> &d, T *__restrict__ u, int bid, char *smem_raw) {
     using C = typename cplx<T>::type;
     using M = Mfma<T>;
     using V = typename M::V;
@@ -790,37 +827,41 @@ template <class T> struct Work {
     T *u;
 };
 
-// Resolves the calling block to (descriptor, problem-local block id).
+// Resolves the calling block to (descriptor, problem-local block id).  The descriptor is
+// returned as a constant-address-space pointer: its fields are then read with scalar loads
+// and stay wave-uniform (a read through a generic pointer would be a flat load, whose result
+// the compiler must treat as per-lane), and the device pointers read from it are known to
+// be global.
 template <class T, bool SWIZZLE = true>
-__device__ __forceinline__ const Desc<T> &resolve(const Work<T> &w, int &lb) {
+__device__ __forceinline__ cptr<Desc<T>> resolve(const Work<T> &w, int &lb) {
     const int g = SWIZZLE ? xcd_swizzle(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (w.nprob == 0) {
         lb = g;
-        return w.one;
+        return (cptr<Desc<T>>)&w.one;
     }
     const int q = find_prob(w.bstart, w.nprob, g);
     lb = g - w.bstart[q];
-    return w.many[q];
+    return (cptr<Desc<T>>)(w.many + q);
 }
 
 template <class T> __global__ void __launch_bounds__(kThreads) k_gather(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     gather_body<T>(d, w.lam, lb);
 }
 template <class T, int D, int KER> __global__ void __launch_bounds__(kWave) k_p2p(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     p2p_body<T, D, KER>(d, w.u, lb);
 }
 template <class T, int D, int KER> __global__ void __launch_bounds__(kThreads) k_direct(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     direct_body<T, D, KER>(d, w.u, lb);
 }
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_phase_dl(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     phase_dl_body<T, D, HMAX>(d, lb);
 }
 // The FP64 aggregation runs on the vector ALUs: on this chip the FP64 matrix rate equals the
@@ -831,29 +872,29 @@ template <class T> constexpr bool kExpMfma = sizeof(T) == 4;
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_p2m(Work<T> w) {
     extern __shared__ char smem_raw[];
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     if constexpr (kExpMfma<T>) p2m_body<T, D, HMAX>(d, lb, smem_raw);
     else p2m_valu_body<T, D, HMAX>(d, lb, smem_raw);
 }
 template <class T> __global__ void __launch_bounds__(kThreads) k_m2m(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     m2m_body<T>(d, lb);
 }
 template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_axis(Work<T> w, int axis) {
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     m2l_axis_body<T, D>(d, axis, lb);
 }
 template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_leaf(Work<T> w) {
     int lb;
-    const Desc<T> &d = resolve<T, false>(w, lb);
+    DescC<T> &d = *resolve<T, false>(w, lb);
     m2l_leaf_body<T, D>(d, lb);
 }
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_l2p(Work<T> w) {
     extern __shared__ char smem_raw[];
     int lb;
-    const Desc<T> &d = resolve(w, lb);
+    DescC<T> &d = *resolve(w, lb);
     l2p_body<T, D, HMAX>(d, w.u, lb, smem_raw);
 }
 

@@ -96,8 +96,8 @@ struct rbf_plan {
     int64_t nunion = 0;
     int *grp_first = nullptr;        // first leaf of each group [ngroups + 1]
     int *uni_ptr = nullptr;          // [ngroups + 1]
-    int *uni_idx = nullptr;          // near leaf of each entry [nunion]
-    int *uni_mask = nullptr;         // bit c set: member c of the group has the leaf as near [nunion]
+    int *uni_idx = nullptr;          // near leaf of each entry [nunion + 8]
+    int *uni_mask = nullptr;         // bit c set: member c of the group has the leaf as near [nunion + 8]
     double *wtab = nullptr;          // quadrature weight times C(xi) per stored node [P]
     int m2l_sched = 0;               // block order of the leaf translation
     int ntasks = 0;

@@ -643,6 +643,7 @@ int tree_typed(rbf_plan *p, const void *points_v) {
             for (int c = a; c < b; ++c)
                 for (int e = np[c]; e < np[c + 1]; ++e) ent.emplace_back(ni[e], 1 << (c - a));
             std::sort(ent.begin(), ent.end());
+            const size_t u0 = ui.size();
             for (size_t k = 0; k < ent.size();) {
                 int m = 0;
                 size_t k2 = k;
@@ -651,22 +652,31 @@ int tree_typed(rbf_plan *p, const void *points_v) {
                 um.push_back(m);
                 k = k2;
             }
+            // pad the group's list to a multiple of 8 entries (a repeat of its first leaf with
+            // no members), so the kernel reads whole aligned steps of 8
+            while ((ui.size() - u0) % 8 != 0) {
+                ui.push_back(ui[u0]);
+                um.push_back(0);
+            }
             up.push_back((int)ui.size());
             a = b;
         }
+        // one more step of 8 past the end: the kernel reads the step after its last one
+        for (int k = 0; k < 8; ++k) {
+            ui.push_back(0);
+            um.push_back(0);
+        }
         gf.push_back(nleaves);
         p->ngroups = (int)gf.size() - 1;
-        p->nunion = (int64_t)ui.size();
+        p->nunion = (int64_t)ui.size() - 8;
         RBF_TRY(ar.alloc((void **)&p->grp_first, sizeof(int) * gf.size()));
         RBF_TRY(ar.alloc((void **)&p->uni_ptr, sizeof(int) * up.size()));
-        RBF_TRY(ar.alloc((void **)&p->uni_idx, sizeof(int) * std::max<size_t>(ui.size(), 1)));
-        RBF_TRY(ar.alloc((void **)&p->uni_mask, sizeof(int) * std::max<size_t>(um.size(), 1)));
+        RBF_TRY(ar.alloc((void **)&p->uni_idx, sizeof(int) * ui.size()));
+        RBF_TRY(ar.alloc((void **)&p->uni_mask, sizeof(int) * um.size()));
         RBF_HIP(hipMemcpyAsync(p->grp_first, gf.data(), sizeof(int) * gf.size(), hipMemcpyHostToDevice, s));
         RBF_HIP(hipMemcpyAsync(p->uni_ptr, up.data(), sizeof(int) * up.size(), hipMemcpyHostToDevice, s));
-        if (!ui.empty()) {
-            RBF_HIP(hipMemcpyAsync(p->uni_idx, ui.data(), sizeof(int) * ui.size(), hipMemcpyHostToDevice, s));
-            RBF_HIP(hipMemcpyAsync(p->uni_mask, um.data(), sizeof(int) * um.size(), hipMemcpyHostToDevice, s));
-        }
+        RBF_HIP(hipMemcpyAsync(p->uni_idx, ui.data(), sizeof(int) * ui.size(), hipMemcpyHostToDevice, s));
+        RBF_HIP(hipMemcpyAsync(p->uni_mask, um.data(), sizeof(int) * um.size(), hipMemcpyHostToDevice, s));
         RBF_HIP(hipStreamSynchronize(s));
     }
     RBF_HIP(hipStreamSynchronize(s));
