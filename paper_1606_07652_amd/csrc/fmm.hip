@@ -177,66 +177,66 @@ __device__ __forceinline__ void gather_body(DescC<T> &d, const T *__restrict__ l
     if (i < d.n) d.lam_s[i] = lam[d.off + d.perm[i]];
 }
 
-// Near field (P2P): one wave per task (up to 64 targets of one leaf); sources are the
-// merged point ranges of the leaf's near list, staged through LDS in tiles of kTile
-// points (x_1..x_d, lam).
+// Near field (P2P): one wave per task (up to 64 targets of one leaf, one per lane).  The
+// sources are the merged point ranges of the leaf's near list, walked in order in steps of
+// kP2pStep points read with scalar loads: every source coordinate and weight is an SGPR
+// operand shared by the 64 lanes, so there is no LDS staging and no barrier.  A range's
+// last partial step repeats its last point with weight 0.
+template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
+
+template <class T, int D, int KER>
+__device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef) {
+    T r2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T t = y[k] - x[k];
+        r2 = fma(t, t, r2);
+    }
+    return (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
+}
+
 template <class T, int D, int KER>
 __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
-    constexpr int DP = Pad<D>::v;
-    __shared__ T sdat[kTile * DP];
-    __shared__ int rb[kTile], roff[kTile + 1];
-    const T *__restrict__ xs = d.xs;
+    constexpr int S = kP2pStep<T>;
     const int64_t n = d.n;
-    const int2 tk = d.tasks[bid];
-    const int a = tk.x;
-    const int t1 = d.leaf_begin[a + 1];
-    const int ti = d.leaf_begin[a] + tk.y + threadIdx.x;
+    const cptr<int> tasks = uconst((const int *)d.tasks), lb = uconst(d.leaf_begin);
+    const cptr<int> sp = uconst(d.src_ptr), rng = uconst((const int *)d.src_rng);
+    const cptr<T> X = (cptr<T>)d.xs, L = (cptr<T>)d.lam_s;
+    const int a = tasks[2 * bid], t0 = tasks[2 * bid + 1];
+    const int t1 = lb[a + 1];
+    const int ti = lb[a] + t0 + (int)threadIdx.x;
     const bool act = ti < t1;
-    const int r0 = d.src_ptr[a], r1 = d.src_ptr[a + 1];
     const T coef = d.coef;
     T y[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
+    for (int k = 0; k < D; ++k) y[k] = act ? d.xs[k * n + ti] : T(0);
     T acc = 0;
-    for (int rbase = r0; rbase < r1; rbase += kTile) {
-        const int nr = min(kTile, r1 - rbase);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int o = 0;
-            for (int q = 0; q < nr; ++q) {
-                int2 g = d.src_rng[rbase + q];
-                rb[q] = g.x;
-                roff[q] = o;
-                o += g.y - g.x;
-            }
-            roff[nr] = o;
+    const int r0 = sp[a], r1 = sp[a + 1];
+    for (int q = r0; q < r1; ++q) {
+        const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
+        int j = j0;
+        for (; j + S <= j1; j += S) {
+            T x[S][D], w[S];
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+#pragma unroll
+                for (int v = 0; v < S; ++v) x[v][k] = X[k * n + j + v];
+#pragma unroll
+            for (int v = 0; v < S; ++v) w[v] = L[j + v];
+#pragma unroll
+            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
         }
-        __syncthreads();
-        const int tot = __builtin_amdgcn_readfirstlane(roff[nr]);
-        for (int base = 0; base < tot; base += kTile) {
-            const int cnt = min(kTile, tot - base);
-            __syncthreads();
-            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                int g = base + e;
-                int q = 0;
-                while (roff[q + 1] <= g) ++q;
-                int j = rb[q] + (g - roff[q]);
+        if (j < j1) {
+            T x[S][D], w[S];
 #pragma unroll
-                for (int k = 0; k < D; ++k) sdat[e * DP + k] = xs[k * n + j];
-                sdat[e * DP + D] = d.lam_s[j];
-            }
-            __syncthreads();
-#pragma unroll 4
-            for (int e = 0; e < cnt; ++e) {
-                T r2 = 0;
+            for (int v = 0; v < S; ++v) {
+                const int jj = min(j + v, j1 - 1);
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    T t = y[k] - sdat[e * DP + k];
-                    r2 = fma(t, t, r2);
-                }
-                T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
-                acc = fma(sdat[e * DP + D], ph, acc);
+                for (int k = 0; k < D; ++k) x[v][k] = X[k * n + jj];
+                w[v] = j + v < j1 ? L[jj] : T(0);
             }
+#pragma unroll
+            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
         }
     }
     if (act) {
@@ -328,8 +328,20 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
     C acc[HMAX];
 #pragma unroll
     for (int h = 0; h < HMAX; ++h) acc[h] = C{0, 0};
+    // The chunk's point phases d.dl are read below with scalar loads, one point per step, and
+    // every such load that goes to HBM stalls the whole workgroup.  Coalesced vector loads of
+    // the chunk's rows, issued before its tables are built, bring them into L2 first.  Their
+    // bits feed a value tested once at the end (never true), which keeps the loads alive.
+    constexpr int kPre = 4;
+    uint32_t sink = 0;
     for (int c0 = t0; c0 < t1; c0 += CH) {
         const int cn = min(CH, t1 - c0);
+        uint32_t pre[kPre];
+#pragma unroll
+        for (int v = 0; v < kPre; ++v) {
+            const int e = (int)threadIdx.x + v * (int)blockDim.x;
+            pre[v] = e < cn * HMAX ? (uint32_t)__double_as_longlong((double)d.dl[(int64_t)c0 * HMAX + e].x) : 0u;
+        }
         __syncthreads();
         for (int t = threadIdx.x; t < cn * DM; t += blockDim.x) {
             const int j = t / DM, k = t % DM;
@@ -346,6 +358,8 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
                 er = nr;
             }
         }
+#pragma unroll
+        for (int v = 0; v < kPre; ++v) sink |= pre[v];
         __syncthreads();
         if constexpr (sizeof(T) == 4) {
             // prefetch the next point's uniform operands while the current one is used
@@ -385,6 +399,7 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
         for (int h = 0; h < HMAX; ++h)
             if (h < H) out[h] = acc[h];
     }
+    if (sink == 1u && n < 0) d.W[0] = C{0, 0};   // n >= 0: never taken
 }
 
 // Aggregation (P2M) on the matrix cores (the FP32 path): per leaf, W[r][h] = sum_j KV_j[r] DL_j[h] with
