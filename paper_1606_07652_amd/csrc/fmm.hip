@@ -83,13 +83,17 @@ __device__ __forceinline__ void row_digits(unsigned r, int mn, unsigned magic, i
 // Aggregation geometry: row tiles of 16 per wave and rows per workgroup of four waves.
 __host__ __device__ constexpr int p2m_rtiles(int dim) { return dim > 2 ? 4 : 1; }
 __host__ __device__ constexpr int p2m_rows(int dim) { return 4 * 16 * p2m_rtiles(dim); }
-// Disaggregation: targets per workgroup (32, or 16 where the phase tables of 32 targets
-// would exceed 64 KiB of LDS); a 64-target task is split over 64 / NT workgroups.
+// Disaggregation: targets per workgroup; a 64-target task is split over 64 / NT workgroups.
+// FP32 takes whole tasks (64) where their phase tables fit in 96 KiB of LDS: each loaded row
+// tile then feeds four target tiles.  FP64 takes 32 (its A fragments for 64 targets would
+// leave two waves per SIMD), or 16 where the tables of 32 targets exceed 64 KiB.
 __host__ __device__ constexpr size_t l2p_lds(int csize, int dim, int hmax, int nt) {
     return (size_t)csize * nt * (hmax + (dim - 1) * 2 * hmax) + (size_t)(csize / 2) * 4 * nt;
 }
 __host__ __device__ constexpr int l2p_targets(int csize, int dim, int hmax) {
-    return l2p_lds(csize, dim, hmax, 32) <= 65536 ? 32 : 16;
+    return (csize == 8 && l2p_lds(csize, dim, hmax, 64) <= 98304) ? 64
+           : l2p_lds(csize, dim, hmax, 32) <= 65536               ? 32
+                                                                   : 16;
 }
 
 template <class T> struct KFun;
@@ -605,17 +609,20 @@ __device__ __forceinline__ void m2l_axis_body(DescC<T> &d, int axis, int bid) {
     out[c * P + p] = s;
 }
 
-// Leaf translation + downward pass.  Blocks (sibling group, 256-entry chunk of the
+// Leaf translation + downward pass.  Blocks (sibling group, kLeafThreads-entry chunk of the
 // expansion): the group's members (at most 8 consecutive leaves with one parent) share one
 // ascending list of the leaves near any of them, with a mask of the members each entry is
-// near to (padded to whole steps of 8 with entries of no member); every near row is loaded once for the whole group and subtracted from the
-// members' copies of their coarse cell's local expansion (the same sequence of operations
+// near to (padded to whole steps of 8 with entries of no member); every near row is loaded
+// once for the whole group and subtracted from the members' copies of their coarse cell's
+// local expansion (the same sequence of operations
 // per member as a per-leaf walk of its own near list).  The quadrature weight w(xi) C(xi)
 // is applied on output.  Output rows are padded to HP entries; the padding was zeroed at
 // plan time and is not written.
 // Block order (d.m2l_sched): 0 = group fastest, chunk slowest; 1 = the same order split
 // into 8 contiguous group ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
 // the near rows a range re-reads stay in one XCD's L2.  Batches use 0.
+constexpr int kLeafThreads = 256;   // expansion entries per leaf-translation workgroup
+
 template <class T, int D>
 __device__ __forceinline__ void m2l_leaf_body(DescC<T> &d, int g) {
     using C = typename cplx<T>::type;
@@ -636,7 +643,7 @@ __device__ __forceinline__ void m2l_leaf_body(DescC<T> &d, int g) {
     }
     // lanes past the end of the expansion read its last entry and store nothing, so that the
     // loop below stays in wave-uniform control flow (its indices and masks are scalar loads)
-    const int pl = chunk * kThreads + (int)threadIdx.x;
+    const int pl = chunk * kLeafThreads + (int)threadIdx.x;
     const bool live = pl < P;
     const int p = live ? pl : P - 1;
     const cptr<int> gfirst = uconst(d.grp_first), uptr = uconst(d.uni_ptr);
@@ -901,7 +908,7 @@ template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_axis
     DescC<T> &d = *resolve(w, lb);
     m2l_axis_body<T, D>(d, axis, lb);
 }
-template <class T, int D> __global__ void __launch_bounds__(kThreads) k_m2l_leaf(Work<T> w) {
+template <class T, int D> __global__ void __launch_bounds__(kLeafThreads) k_m2l_leaf(Work<T> w) {
     int lb;
     DescC<T> &d = *resolve<T, false>(w, lb);
     m2l_leaf_body<T, D>(d, lb);
@@ -939,7 +946,7 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
         case PH_M2M: return d.ncells * nch;
         case PH_M2L_AXIS: return (axis_by_lines(d.lc) ? d.ncells >> d.lc : d.ncells) * nch;
         case PH_M2L_LEAF: {
-            const int64_t nch_l = (d.P + kThreads - 1) / kThreads;
+            const int64_t nch_l = (d.P + kLeafThreads - 1) / kLeafThreads;
             if (d.m2l_sched == 1) return 8 * nch_l * ((d.ngroups + 7) / 8);
             return nch_l * d.ngroups;
         }
@@ -968,7 +975,7 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
         case PH_P2M: k_p2m<T, D, HMAX><<<g, (kExpMfma<T> || D > 2) ? kThreads : kWave, shmem, s>>>(w); break;
         case PH_M2M: k_m2m<T><<<g, kThreads, 0, s>>>(w); break;
         case PH_M2L_AXIS: k_m2l_axis<T, D><<<g, kThreads, 0, s>>>(w, axis); break;
-        case PH_M2L_LEAF: k_m2l_leaf<T, D><<<g, kThreads, 0, s>>>(w); break;
+        case PH_M2L_LEAF: k_m2l_leaf<T, D><<<g, kLeafThreads, 0, s>>>(w); break;
         case PH_L2P: {
             constexpr int csz = (int)sizeof(typename cplx<T>::type);
             constexpr size_t lds = l2p_lds(csz, D, HMAX, l2p_targets(csz, D, HMAX));
