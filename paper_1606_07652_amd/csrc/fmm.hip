@@ -181,11 +181,17 @@ __device__ __forceinline__ void gather_body(DescC<T> &d, const T *__restrict__ l
     if (i < d.n) d.lam_s[i] = lam[d.off + d.perm[i]];
 }
 
-// Near field (P2P): one wave per task (up to 64 targets of one leaf, one per lane).  The
-// sources are the merged point ranges of the leaf's near list, walked in order in steps of
-// kP2pStep points read with scalar loads: every source coordinate and weight is an SGPR
-// operand shared by the 64 lanes, so there is no LDS staging and no barrier.  A range's
-// last partial step repeats its last point with weight 0.
+// Near field (P2P): one wave per task, a chunk of up to 64 targets of one leaf.  The
+// sources are the merged point ranges of the leaf's near list.
+//  * G = 1 (one target per lane): the wave walks the ranges in order in steps of kP2pStep
+//    points read with scalar loads, so every source coordinate and weight is an SGPR operand
+//    shared by the 64 lanes (no LDS staging, no barrier); a range's last partial step
+//    repeats its last point with weight 0.
+//  * G = 2, 4, 8 (a leaf's last chunk of at most 64 / G targets): the lanes form G groups of
+//    64 / G, one target per lane of a group; group g takes the sources j with j - j0 = g mod G
+//    of each range [j0, j1), read with per-lane vector loads, and the G partial sums of a
+//    target are added over the groups at the end.  A leaf of 80 points then costs one full
+//    wave and a quarter wave of source steps instead of two full waves.
 template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 
 template <class T, int D, int KER>
@@ -200,22 +206,13 @@ __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef) 
 }
 
 template <class T, int D, int KER>
-__device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int r1) {
     constexpr int S = kP2pStep<T>;
     const int64_t n = d.n;
-    const cptr<int> tasks = uconst((const int *)d.tasks), lb = uconst(d.leaf_begin);
-    const cptr<int> sp = uconst(d.src_ptr), rng = uconst((const int *)d.src_rng);
+    const cptr<int> rng = uconst((const int *)d.src_rng);
     const cptr<T> X = (cptr<T>)d.xs, L = (cptr<T>)d.lam_s;
-    const int a = tasks[2 * bid], t0 = tasks[2 * bid + 1];
-    const int t1 = lb[a + 1];
-    const int ti = lb[a] + t0 + (int)threadIdx.x;
-    const bool act = ti < t1;
     const T coef = d.coef;
-    T y[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) y[k] = act ? d.xs[k * n + ti] : T(0);
     T acc = 0;
-    const int r0 = sp[a], r1 = sp[a + 1];
     for (int q = r0; q < r1; ++q) {
         const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
         int j = j0;
@@ -243,7 +240,66 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
             for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
         }
     }
-    if (act) {
+    return acc;
+}
+
+// Lane group g = lane / (64 / G) sums the sources j0 + g + G m of every range; two sources
+// per lane per step, a source past the range end repeats the last one with weight 0.  The
+// result is the group sums added over the groups (in every lane of the target).
+template <class T, int D, int KER, int G>
+__device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int r1) {
+    constexpr int TP = kWave / G, U = 2;
+    const int64_t n = d.n;
+    const cptr<int> rng = uconst((const int *)d.src_rng);
+    const T *__restrict__ X = d.xs;
+    const T *__restrict__ L = d.lam_s;
+    const int g = (int)threadIdx.x / TP;
+    const T coef = d.coef;
+    T acc = 0;
+    for (int q = r0; q < r1; ++q) {
+        const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
+        for (int jb = j0; jb < j1; jb += G * U) {
+            T x[U][D], w[U];
+#pragma unroll
+            for (int v = 0; v < U; ++v) {
+                const int j = jb + g + G * v;
+                const int jj = min(j, j1 - 1);
+#pragma unroll
+                for (int k = 0; k < D; ++k) x[v][k] = X[k * n + jj];
+                w[v] = j < j1 ? L[jj] : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < U; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
+        }
+    }
+#pragma unroll
+    for (int o = TP; o < kWave; o *= 2) acc += __shfl_xor(acc, o, kWave);
+    return acc;
+}
+
+template <class T, int D, int KER>
+__device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
+    const int64_t n = d.n;
+    const cptr<int> tasks = uconst((const int *)d.ptasks), lb = uconst(d.leaf_begin);
+    const cptr<int> sp = uconst(d.src_ptr);
+    const int a = tasks[2 * bid], code = tasks[2 * bid + 1];
+    const int t0 = (code & 0x0fffffff) * kWave, gl = code >> 28;
+    const int TP = kWave >> gl;
+    const int t1 = lb[a + 1];
+    const int ti = lb[a] + t0 + (int)threadIdx.x % TP;
+    const bool act = ti < t1;
+    T y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[k] = act ? d.xs[k * n + ti] : T(0);
+    const int r0 = sp[a], r1 = sp[a + 1];
+    T acc;
+    switch (gl) {
+        case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1); break;
+        case 1: acc = p2p_split<T, D, KER, 2>(d, y, r0, r1); break;
+        case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1); break;
+        default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1); break;
+    }
+    if (act && (int)threadIdx.x < TP) {
         if (d.far) d.u_s[ti] = acc;
         else u[d.off + d.perm[ti]] = acc;   // near-only plan: this is the result
     }
@@ -939,7 +995,7 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
     if (!d.far && phase != PH_GATHER && phase != PH_P2P && phase != PH_DIRECT) return 0;
     switch (phase) {
         case PH_GATHER: case PH_PHASE_DL: case PH_DIRECT: return nb_pts;
-        case PH_P2P: return d.ntasks;
+        case PH_P2P: return d.nptasks;
         case PH_L2P:
             return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
         case PH_P2M: return (int64_t)d.nleaves * d.wpl;
@@ -1133,6 +1189,8 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->cell_begin = p->cell_leaf_begin;
     d->src_rng = p->src_rng;
     d->tasks = p->tasks;
+    d->ptasks = p->ptasks;
+    d->nptasks = p->nptasks;
     d->nleaves = p->nleaves;
     d->ntasks = p->ntasks;
     d->ncells = p->ncells;

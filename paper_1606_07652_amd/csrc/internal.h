@@ -90,6 +90,11 @@ struct rbf_plan {
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
     int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    // near-field tasks: (leaf, first point offset / 64 | log2(G) << 28): a leaf's last chunk
+    // of m points runs on G lane groups of 64 / G lanes that split its sources, G the largest
+    // power of two <= 8 with m <= 64 / G; full chunks have G = 1 [nptasks]
+    int2 *ptasks = nullptr;
+    int nptasks = 0;
     // sibling groups of the leaf translation: runs of at most 8 consecutive leaves with one
     // parent; each group's near lists merged into one ascending list with member masks
     int ngroups = 0;

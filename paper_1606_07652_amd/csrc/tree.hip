@@ -619,7 +619,23 @@ int tree_typed(rbf_plan *p, const void *points_v) {
         p->ntasks = (int)tk.size();
         RBF_TRY(ar.alloc((void **)&p->tasks, sizeof(int2) * tk.size()));
         RBF_HIP(hipMemcpyAsync(p->tasks, tk.data(), sizeof(int2) * tk.size(), hipMemcpyHostToDevice, s));
-        RBF_HIP(hipStreamSynchronize(s));   // tk is freed at the end of this scope
+        // near-field tasks: a leaf's last chunk of m points, m <= 64 / (2 G), runs on G lane
+        // groups of 64 / G lanes that split the sources (G <= 8)
+        std::vector<int2> pk;
+        pk.reserve(tk.size());
+        for (int a = 0; a < nleaves; ++a) {
+            const int na = hb[a + 1] - hb[a];
+            for (int o = 0; o < na; o += kWave) {
+                const int m = std::min(kWave, na - o);
+                int gl = 0;
+                while (gl < 3 && m <= (kWave >> (gl + 1))) ++gl;   // 64 / 2^gl lanes hold m targets
+                pk.push_back(make_int2(a, (o / kWave) | (gl << 28)));
+            }
+        }
+        p->nptasks = (int)pk.size();
+        RBF_TRY(ar.alloc((void **)&p->ptasks, sizeof(int2) * pk.size()));
+        RBF_HIP(hipMemcpyAsync(p->ptasks, pk.data(), sizeof(int2) * pk.size(), hipMemcpyHostToDevice, s));
+        RBF_HIP(hipStreamSynchronize(s));   // tk and pk are freed at the end of this scope
     }
     // sibling groups for the leaf translation
     {
