@@ -87,6 +87,31 @@ int rbf_fmm_matvec(rbf_plan *plan, const void *lambda, void *u);
  * rbf_fmm_matvec; the reference the fast product is measured against. */
 int rbf_direct_matvec(rbf_plan *plan, const void *lambda, void *u);
 
+/* Evaluation at separate targets: the sum of eq. 1 taken at points y_t that are not the
+ * centres x_j (section 1 names the two roles; evaluating an interpolant is this sum),
+ *   u_t = sum_j lambda_j Phi(y_t - x_j),  t = 1..m.
+ * rbf_fmm_plan_eval plans for the n sources and the m targets together:
+ *   sources  device, (n, d) row-major, dtype, n >= 1;
+ *   targets  device, (m, d) row-major, dtype, m >= 0 (may be NULL when m = 0);
+ *   the other arguments as for rbf_fmm_plan.  Both sets are copied, so the caller may free
+ *   them after the call.  The targets take part as points of weight zero: tree, near lists,
+ *   tolerance rule and kernels are those of rbf_fmm_plan over the n + m points, a target
+ *   outside the sources' bounding box included, and the cost of an evaluation is that of a
+ *   product over n + m points.  Such a plan is used with rbf_fmm_eval and rbf_direct_eval
+ *   only; rbf_fmm_matvec, rbf_direct_matvec, rbf_interp_solve and the preconditioner calls
+ *   return RBF_EINVAL on it, and rbf_fmm_eval returns RBF_EINVAL on a plan from
+ *   rbf_fmm_plan.  Synchronises the stream.  Errors as rbf_fmm_plan.
+ * rbf_fmm_eval: lambda device, length n, plan dtype, the sources' order; u device, length
+ *   m, plan dtype, the targets' order, overwritten (nothing is written when m = 0); must not
+ *   alias lambda.  Asynchronous on the plan's stream; relative 2-norm error over the
+ *   targets within the plan's tolerance.
+ * rbf_direct_eval: the same sum over all pairs, exactly (O((n + m) n) on the device). */
+int rbf_fmm_plan_eval(const void *sources, int64_t n, const void *targets, int64_t m, int d,
+                      int dtype, int kernel, double shape, double tol, const rbf_opts *opts,
+                      void *stream, rbf_plan **out);
+int rbf_fmm_eval(rbf_plan *plan, const void *lambda, void *u);
+int rbf_direct_eval(rbf_plan *plan, const void *lambda, void *u);
+
 typedef struct rbf_solve_opts {
     int    restart;      /* Krylov subspace size m of GMRES(m) (default 50) */
     int    max_iters;    /* total inner-iteration cap (default 1000) */

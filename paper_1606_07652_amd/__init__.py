@@ -6,11 +6,11 @@ load the library; the first plan does, and fails loudly if the library is missin
 """
 from ._lib import RbfError, load  # noqa: F401
 
-__all__ = ["FmmPlan", "BatchPlan", "autotune", "RbfError", "load"]
+__all__ = ["FmmPlan", "EvalPlan", "BatchPlan", "autotune", "RbfError", "load"]
 
 
 def __getattr__(name):
-    if name in ("FmmPlan", "BatchPlan", "autotune"):
+    if name in ("FmmPlan", "EvalPlan", "BatchPlan", "autotune"):
         from . import fmm
         return getattr(fmm, name)
     raise AttributeError(name)

@@ -74,6 +74,11 @@ SIGNATURES = {
                                     ctypes.POINTER(ctypes.c_void_p)]),
     "rbf_fmm_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rbf_direct_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_fmm_plan_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(RbfOpts), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_fmm_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_direct_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rbf_interp_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                         ctypes.POINTER(RbfSolveOpts), ctypes.POINTER(RbfSolveInfo)]),
     "rbf_fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -275,6 +275,57 @@ int plan_create(const void *points, int64_t n, int d, int dtype, int kernel, dou
     return plan_impl(points, n, d, dtype, kernel, shape, tol, opts, stream, out);
 }
 
+int reject_eval_plan(const rbf_plan *p, const char *fn) {
+    if (p && p->n_src > 0) {
+        set_error("%s: the plan was made for separate targets (rbf_fmm_plan_eval); use rbf_fmm_eval", fn);
+        return RBF_EINVAL;
+    }
+    return RBF_OK;
+}
+
+namespace {
+
+constexpr int kEvalThreads = 256;
+
+// Weights of a plan for separate targets: the sources' weights, then zeros at the targets.
+template <class T>
+__global__ void __launch_bounds__(kEvalThreads) k_eval_pack(const T *__restrict__ lam, int64_t n_src, int64_t n, T *out) {
+    const int64_t i = blockIdx.x * (int64_t)kEvalThreads + threadIdx.x;
+    if (i < n) out[i] = i < n_src ? lam[i] : T(0);
+}
+// The product at the targets: entries [n_src, n) of the product over all points.
+template <class T>
+__global__ void __launch_bounds__(kEvalThreads) k_eval_unpack(const T *__restrict__ all, int64_t n_src, int64_t m, T *u) {
+    const int64_t t = blockIdx.x * (int64_t)kEvalThreads + threadIdx.x;
+    if (t < m) u[t] = all[n_src + t];
+}
+
+template <class T>
+int eval_t(rbf_plan *p, const void *lambda, void *u, bool direct) {
+    const int64_t n = p->n, m = n - p->n_src;
+    hipStream_t s = p->stream;
+    k_eval_pack<T><<<(unsigned)((n + kEvalThreads - 1) / kEvalThreads), kEvalThreads, 0, s>>>((const T *)lambda, p->n_src, n,
+                                                                                   (T *)p->ev_lam);
+    RBF_HIP(hipGetLastError());
+    RBF_TRY(direct ? launch_direct(p, p->ev_lam, p->ev_u) : launch_matvec(p, p->ev_lam, p->ev_u));
+    if (m > 0) {
+        k_eval_unpack<T><<<(unsigned)((m + kEvalThreads - 1) / kEvalThreads), kEvalThreads, 0, s>>>((const T *)p->ev_u, p->n_src,
+                                                                                        m, (T *)u);
+        RBF_HIP(hipGetLastError());
+    }
+    return RBF_OK;
+}
+
+int eval_impl(rbf_plan *p, const void *lambda, void *u, bool direct, const char *fn) {
+    if (!p || !lambda) { set_error("%s: null argument", fn); return RBF_EINVAL; }
+    if (p->n_src > 0 && !u && p->n > p->n_src) { set_error("%s: null u with targets to write", fn); return RBF_EINVAL; }
+    if (p->n_src <= 0) { set_error("%s: the plan has no separate targets (make it with rbf_fmm_plan_eval)", fn); return RBF_EINVAL; }
+    if (lambda == u) { set_error("%s: lambda and u must not alias", fn); return RBF_EINVAL; }
+    return p->dtype == RBF_F32 ? eval_t<float>(p, lambda, u, direct) : eval_t<double>(p, lambda, u, direct);
+}
+
+}  // namespace
+
 }  // namespace rbf
 
 using namespace rbf;
@@ -292,13 +343,66 @@ int rbf_fmm_plan(const void *points, int64_t n, int d, int dtype, int kernel, do
 int rbf_fmm_matvec(rbf_plan *plan, const void *lambda, void *u) {
     if (!plan || !lambda || !u) { set_error("rbf_fmm_matvec: null argument"); return RBF_EINVAL; }
     if (lambda == u) { set_error("rbf_fmm_matvec: lambda and u must not alias"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_fmm_matvec"));
     return launch_matvec(plan, lambda, u);
 }
 
 int rbf_direct_matvec(rbf_plan *plan, const void *lambda, void *u) {
     if (!plan || !lambda || !u) { set_error("rbf_direct_matvec: null argument"); return RBF_EINVAL; }
     if (lambda == u) { set_error("rbf_direct_matvec: lambda and u must not alias"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_direct_matvec"));
     return launch_direct(plan, lambda, u);
+}
+
+int rbf_fmm_plan_eval(const void *sources, int64_t n, const void *targets, int64_t m, int d, int dtype, int kernel,
+                      double shape, double tol, const rbf_opts *opts, void *stream, rbf_plan **out) {
+    g_err[0] = 0;
+    if (!sources || !out || (m > 0 && !targets)) { set_error("rbf_fmm_plan_eval: null pointer argument"); return RBF_EINVAL; }
+    if (n < 1 || m < 0 || n + m > (int64_t)0x3fffffff) {
+        set_error("rbf_fmm_plan_eval: n=%lld, m=%lld out of range", (long long)n, (long long)m);
+        return RBF_EINVAL;
+    }
+    if (d < 1 || d > kMaxDim || (dtype != RBF_F32 && dtype != RBF_F64)) {
+        set_error("rbf_fmm_plan_eval: bad d=%d or dtype=%d", d, dtype);
+        return RBF_EINVAL;
+    }
+    // one point set: the sources, then the targets (the plan copies it and sorts its copy)
+    const size_t tsz = dtype == RBF_F32 ? 4 : 8;
+    hipStream_t s = (hipStream_t)stream;
+    void *all = nullptr;
+    if (hipMalloc(&all, tsz * (size_t)d * (size_t)(n + m)) != hipSuccess) {
+        set_error("rbf_fmm_plan_eval: hipMalloc of the joined point set failed");
+        return RBF_ENOMEM;
+    }
+    int rc = RBF_OK;
+    if (hipMemcpyAsync(all, sources, tsz * d * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        (m > 0 && hipMemcpyAsync((char *)all + tsz * d * n, targets, tsz * d * m, hipMemcpyDeviceToDevice, s) !=
+                      hipSuccess)) {
+        set_error("rbf_fmm_plan_eval: copying the points failed");
+        rc = RBF_EHIP;
+    }
+    rbf_plan *p = nullptr;
+    if (rc == RBF_OK) rc = plan_impl(all, n + m, d, dtype, kernel, shape, tol, opts, stream, &p);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(all);
+    if (rc != RBF_OK) return rc;
+    p->n_src = n;
+    rc = p->arena.alloc(&p->ev_lam, tsz * (size_t)(n + m));
+    if (rc == RBF_OK) rc = p->arena.alloc(&p->ev_u, tsz * (size_t)(n + m));
+    if (rc != RBF_OK) {
+        rbf_fmm_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return RBF_OK;
+}
+
+int rbf_fmm_eval(rbf_plan *plan, const void *lambda, void *u) {
+    return eval_impl(plan, lambda, u, false, "rbf_fmm_eval");
+}
+
+int rbf_direct_eval(rbf_plan *plan, const void *lambda, void *u) {
+    return eval_impl(plan, lambda, u, true, "rbf_direct_eval");
 }
 
 int rbf_fmm_destroy(rbf_plan *plan) {

@@ -90,6 +90,11 @@ struct rbf_plan {
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
     int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    // a plan for separate targets (rbf_fmm_plan_eval): caller points [0, n_src) are the sources,
+    // [n_src, n) the targets, which take part with weight 0; 0 for an ordinary plan
+    int64_t n_src = 0;
+    void *ev_lam = nullptr;          // [n] the sources' weights followed by zeros
+    void *ev_u = nullptr;            // [n] the product over all n points
     // near-field tasks: (leaf, first point offset / 64 | log2(G) << 28): a leaf's last chunk
     // of m points runs on G lane groups of 64 / G lanes that split its sources, G the largest
     // power of two <= 8 with m <= 64 / G; full chunks have G = 1 [nptasks]
@@ -154,6 +159,8 @@ int plan_create(const void *points, int64_t n, int d, int dtype, int kernel, dou
 int build_tree(rbf_plan *p, const void *points);
 int build_near_lists(rbf_plan *p);
 int launch_matvec(rbf_plan *p, const void *lambda, void *u);
+// RBF_EINVAL (with a message naming fn) when p is a plan for separate targets
+int reject_eval_plan(const rbf_plan *p, const char *fn);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);
 int pc_ready(rbf_plan *p, int kind);                                 // pc.hip
 int pc_apply(rbf_plan *p, int kind, const double *v, double *z);     // pc.hip

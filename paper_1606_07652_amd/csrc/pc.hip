@@ -331,18 +331,21 @@ using namespace rbf;
 
 extern "C" int rbf_pc_block_jacobi(rbf_plan *plan, double reg) {
     if (!plan) { set_error("rbf_pc_block_jacobi: null plan"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_block_jacobi"));
     if (!std::isfinite(reg)) { set_error("rbf_pc_block_jacobi: reg must be finite"); return RBF_EINVAL; }
     return build_bj(plan, reg < 0 ? kDefaultBjReg : reg);
 }
 
 extern "C" int rbf_pc_learned_features(rbf_plan *plan, double reg) {
     if (!plan) { set_error("rbf_pc_learned_features: null plan"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_learned_features"));
     if (!std::isfinite(reg)) { set_error("rbf_pc_learned_features: reg must be finite"); return RBF_EINVAL; }
     return build_lp(plan, reg < 0 ? kDefaultLpReg : reg);
 }
 
 extern "C" int rbf_pc_apply(rbf_plan *plan, int kind, const double *v, double *z) {
     if (!plan || !v || !z) { set_error("rbf_pc_apply: null argument"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_apply"));
     if (kind != RBF_PC_BLOCK_JACOBI && kind != RBF_PC_LEARNED) {
         set_error("rbf_pc_apply: kind must be RBF_PC_BLOCK_JACOBI or RBF_PC_LEARNED");
         return RBF_EINVAL;
@@ -359,6 +362,7 @@ extern "C" int rbf_pc_set_learned(rbf_plan *plan, rbf_mlp *mlp) {
 
 extern "C" int rbf_pc_pairs(rbf_plan *plan, const double *r, const double *e, float *x, float *t, float *w) {
     if (!plan || !r || !e || !x || !t || !w) { set_error("rbf_pc_pairs: null argument"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_pairs"));
     if (plan->lp_reg < 0) RBF_TRY(build_lp(plan, kDefaultLpReg));
     hipStream_t s = plan->stream;
     k_dot_self<<<1, kT, 0, s>>>(e, plan->n, plan->pc_scal);
@@ -374,6 +378,7 @@ extern "C" int rbf_pc_harvest(rbf_plan *plan, const void *f, double rtol, int ma
         set_error("rbf_pc_harvest: bad arguments");
         return RBF_EINVAL;
     }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_harvest"));
     if (precond != RBF_PC_NONE && precond != RBF_PC_BLOCK_JACOBI) {
         set_error("rbf_pc_harvest: the harvesting solves run without a preconditioner or with block-Jacobi");
         return RBF_EINVAL;

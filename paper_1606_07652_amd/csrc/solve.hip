@@ -316,6 +316,7 @@ extern "C" int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, dou
                                 rbf_solve_info *info) {
     using namespace rbf;
     if (!plan || !f || !lambda) { set_error("rbf_interp_solve: null argument"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_interp_solve"));
     if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve: rtol must lie in (0, 1)"); return RBF_EINVAL; }
     if (opts && (opts->restart < 0 || opts->restart > 1000)) { set_error("rbf_interp_solve: restart out of range"); return RBF_EINVAL; }
     if (opts && (opts->precond < RBF_PC_NONE || opts->precond > RBF_PC_LEARNED)) {

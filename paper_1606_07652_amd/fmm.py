@@ -230,3 +230,54 @@ class FmmPlan:
             self.close()
         except Exception:
             pass
+
+
+class EvalPlan(FmmPlan):
+    """Plan for u_t = sum_j lambda_j Phi(y_t - x_j) at targets y other than the sources x
+    (rbf_fmm_plan_eval); the plan's points are the sources followed by the targets."""
+
+    def __init__(self, sources: torch.Tensor, targets: torch.Tensor, kernel: str = "gaussian",
+                 shape: float = 0.05, tol: float = 1e-6, n_max: int = 0, max_level: int = 0,
+                 min_level: int = 0, coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0,
+                 band: float = 0.0, m2l_schedule: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        lib = L.load()
+        if sources.dim() != 2 or targets.dim() != 2 or targets.shape[1] != sources.shape[1]:
+            raise ValueError("sources (n, d) and targets (m, d) must share d")
+        if targets.dtype != sources.dtype or targets.device != sources.device:
+            raise ValueError("sources and targets must share dtype and device")
+        self.n_src, self.d = sources.shape
+        self.m = targets.shape[0]
+        self.n = self.n_src + self.m
+        self.dtype = sources.dtype
+        self.device = sources.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(sources.device)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
+        h = ctypes.c_void_p()
+        tp = _ptr(targets) if self.m > 0 else None
+        L.check(lib.rbf_fmm_plan_eval(_ptr(sources), self.n_src, tp, self.m, self.d, _dtype_code(sources),
+                                      _KERNELS[kernel], float(shape), float(tol), ctypes.byref(opts),
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.kernel, self.shape, self.tol = kernel, shape, tol
+
+    def _check(self, v: torch.Tensor, k: int):
+        if v.shape != (k,) or v.dtype != self.dtype or v.device != self.device:
+            raise ValueError(f"expected a ({k},) {self.dtype} vector on {self.device}")
+
+    def eval(self, lam: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """u at the targets for weights lam at the sources (rbf_fmm_eval)."""
+        self._check(lam, self.n_src)
+        if out is None:
+            out = torch.empty(self.m, dtype=self.dtype, device=self.device)
+        self._check(out, self.m)
+        L.check(L.load().rbf_fmm_eval(self._h, _ptr(lam), out.data_ptr() if self.m > 0 else None))
+        return out
+
+    def direct(self, lam: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The exact sum at the targets (rbf_direct_eval)."""
+        self._check(lam, self.n_src)
+        if out is None:
+            out = torch.empty(self.m, dtype=self.dtype, device=self.device)
+        self._check(out, self.m)
+        L.check(L.load().rbf_direct_eval(self._h, _ptr(lam), out.data_ptr() if self.m > 0 else None))
+        return out

@@ -59,3 +59,29 @@ def test_single_point_and_targets():
     full = direct.direct_sum(xs, lam, "gaussian", 0.05)
     sub = direct.direct_sum(xs, lam, "gaussian", 0.05, targets=xs[50:60])
     assert np.array_equal(sub, full[50:60])
+
+
+@pytest.mark.parametrize("kernel,shape", [("gaussian", 0.05), ("multiquadric", 0.02)])
+def test_separate_targets_against_dense_matrix(kernel, shape):
+    """Targets that are not sources (inside and outside the sources' box): the rectangular
+    matrix Phi(|y_t - x_j|) from cdist, applied to lambda."""
+    x = uniform_points(500, 3, 21)
+    lam = normal_weights(500, 22)
+    y = uniform_points(300, 3, 23) * 1.6 - 0.3
+    r = cdist(y, x)
+    a = np.exp(-r ** 2 / (2 * shape ** 2)) if kernel == "gaussian" else np.sqrt(r ** 2 + shape ** 2)
+    ref = a @ lam
+    u = direct.direct_sum(x, lam, kernel, shape, targets=y)
+    assert np.max(np.abs(u - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    un = direct.direct_sum_numpy(x, lam, kernel, shape, targets=y)
+    assert np.max(np.abs(u - un)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_one_source_at_separate_targets():
+    """One source of weight w at x0: u(y) = w exp(-|y - x0|^2 / (2 s^2)), by the closed form."""
+    x0 = np.array([[0.25, 0.5, 0.75]])
+    y = np.array([[0.25, 0.5, 0.75], [0.35, 0.5, 0.75], [1.25, -0.5, 0.0]])
+    u = direct.direct_sum(x0, np.array([-1.5]), "gaussian", 0.1, targets=y)
+    r2 = np.array([0.0, 0.01, 1.0 + 1.0 + 0.5625])
+    # the third exponent is -128: one rounding of 2 s^2 moves the value by ~1e-14 relative
+    assert np.allclose(u, -1.5 * np.exp(-r2 / (2 * 0.1 ** 2)), rtol=1e-13, atol=0)
