@@ -394,6 +394,76 @@ def run_c2mq(args):
     print(json.dumps(result), flush=True)
 
 
+def run_eval(args):
+    """Evaluation at separate targets: the default workload's 2^20 mixed sources and weights,
+    2^20 targets uniform over the unit cube (seed 7), FP64 at tol 1e-6 and FP32 at 1e-4.
+    value = targets / time of one evaluation; the oracle checks 2048 seeded targets."""
+    import torch
+
+    from paper_1606_07652_amd import EvalPlan
+    from workloads import c2, uniform_points
+
+    w = c2("gaussian", n=args.n)
+    n = w.points.shape[0]
+    y = uniform_points(args.n_targets, 3, 7)
+    m = y.shape[0]
+    rng = np.random.default_rng(124)
+    idx = np.sort(rng.choice(m, min(2048, m), replace=False))
+    ref = None
+    if not args.no_cpu:
+        from oracle import direct
+        t1 = time.perf_counter()
+        ref = direct.direct_sum(w.points.astype(np.float64), w.lam.astype(np.float64), "gaussian", w.shape,
+                                targets=y[idx])
+        tcpu = time.perf_counter() - t1
+    out = {}
+    for name, dt, tol in (("f64", torch.float64, 1e-6), ("f32", torch.float32, 1e-4)):
+        X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
+        Y = torch.as_tensor(y, dtype=dt, device="cuda:0")
+        lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
+        t0 = time.perf_counter()
+        plan = EvalPlan(X, Y, kernel="gaussian", shape=w.shape, tol=tol, n_max=args.n_max)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        u = torch.empty(m, dtype=dt, device="cuda:0")
+        for _ in range(args.warmup):
+            plan.eval(lam, u)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.eval(lam, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ph = plan.phase_times()
+        plan.set_profiling(False)
+        calls = max(ph.pop("calls"), 1)
+        inf = plan.info()
+        out[name] = {"ms_per_step": ms, "targets_per_s": m / (ms * 1e-3), "plan_ms": plan_ms,
+                     "phase_ms": {k: v / calls for k, v in ph.items()}, "nodes": inf["nodes"],
+                     "leaves": inf["nleaves"]}
+        if ref is not None:
+            out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
+        log(f"[bench] eval {name}: {ms:.2f} ms for {m} targets ({n} sources)")
+        plan.close()
+        del X, Y, lam, u
+        torch.cuda.empty_cache()
+    f = out["f64"]
+    dom = max(f["phase_ms"], key=lambda k: f["phase_ms"][k])
+    result = {"metric": "RBF-FMM evaluation targets/s @ rel-L2<=1e-6", "value": f["targets_per_s"],
+              "unit": "targets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+              "config": {"workload": "3d_mixed_sources_uniform_targets_gaussian_s0.03", "n_sources": n,
+                         "n_targets": m, "kernel": "gaussian", "shape": w.shape, "tol": 1e-6,
+                         "n_max": args.n_max},
+              "dominant_phase": dom, "paths": out}
+    if ref is not None:
+        result["cpu_baseline"] = {"value": len(idx) / tcpu, "unit": "targets/s", "cores": direct.threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{len(idx)} seeded targets x all {n} sources ({tcpu:.1f} s)"}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,7 +477,8 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq", "eval"])
+    ap.add_argument("--n-targets", type=int, default=1 << 20)
     ap.add_argument("--n-c4", type=int, default=1 << 18)
     ap.add_argument("--n-solve", type=int, default=1 << 21)
     ap.add_argument("--solve-iters", type=int, default=300)
@@ -430,6 +501,8 @@ def main():
         return run_c4(args)
     if args.workload == "c2mq":
         return run_c2mq(args)
+    if args.workload == "eval":
+        return run_eval(args)
 
     import torch
 
