@@ -158,8 +158,9 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
     return RBF_OK;
 }
 
+// n_src > 0: a plan for separate targets, points [0, n_src) the sources and the rest targets
 int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
-              const rbf_opts *opts, void *stream, rbf_plan **out) {
+              const rbf_opts *opts, void *stream, rbf_plan **out, int64_t n_src = 0) {
     if (!points || !out) { set_error("rbf_fmm_plan: null pointer argument"); return RBF_EINVAL; }
     if (n < 1 || n > (int64_t)0x3fffffff) { set_error("rbf_fmm_plan: n=%lld out of range", (long long)n); return RBF_EINVAL; }
     if (d < 1 || d > kMaxDim) { set_error("rbf_fmm_plan: d=%d out of range [1,5]", d); return RBF_EINVAL; }
@@ -171,6 +172,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     rbf_plan *p = new (std::nothrow) rbf_plan();
     if (!p) { set_error("rbf_fmm_plan: out of host memory"); return RBF_ENOMEM; }
     p->n = n; p->d = d; p->dtype = dtype; p->kernel = kernel; p->shape = shape; p->tol = tol;
+    p->n_src = n_src;
     p->stream = (hipStream_t)stream;
     p->n_max = (opts && opts->n_max > 0) ? opts->n_max : 128;
     // leaf translation block order: XCD leaf ranges unless the caller asks for leaf-major
@@ -382,11 +384,10 @@ int rbf_fmm_plan_eval(const void *sources, int64_t n, const void *targets, int64
         rc = RBF_EHIP;
     }
     rbf_plan *p = nullptr;
-    if (rc == RBF_OK) rc = plan_impl(all, n + m, d, dtype, kernel, shape, tol, opts, stream, &p);
+    if (rc == RBF_OK) rc = plan_impl(all, n + m, d, dtype, kernel, shape, tol, opts, stream, &p, n);
     (void)hipStreamSynchronize(s);
     (void)hipFree(all);
     if (rc != RBF_OK) return rc;
-    p->n_src = n;
     rc = p->arena.alloc(&p->ev_lam, tsz * (size_t)(n + m));
     if (rc == RBF_OK) rc = p->arena.alloc(&p->ev_u, tsz * (size_t)(n + m));
     if (rc != RBF_OK) {

@@ -282,11 +282,13 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
     const int64_t n = d.n;
     const cptr<int> tasks = uconst((const int *)d.ptasks), lb = uconst(d.leaf_begin);
     const cptr<int> sp = uconst(d.src_ptr);
-    const int a = tasks[2 * bid], code = tasks[2 * bid + 1];
-    const int t0 = (code & 0x0fffffff) * kWave, gl = code >> 28;
+    const int a = tasks[2 * bid], t0 = tasks[2 * bid + 1];   // leaf, first target
+    const int t1 = min(t0 + kWave, lb[a + 1]);
+    // lane groups: the largest G <= 8 with the chunk's m targets fitting 64 / G lanes
+    const int m = t1 - t0;
+    const int gl = m <= kWave / 8 ? 3 : m <= kWave / 4 ? 2 : m <= kWave / 2 ? 1 : 0;
     const int TP = kWave >> gl;
-    const int t1 = lb[a + 1];
-    const int ti = lb[a] + t0 + (int)threadIdx.x % TP;
+    const int ti = t0 + (int)threadIdx.x % TP;
     const bool act = ti < t1;
     T y[D];
 #pragma unroll
@@ -376,7 +378,7 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
     const int mn = d.mn, R = d.R, CH = d.p2m_ch;
     const int ST = DM * mn;
     const int a = bid / d.wpl, part = bid % d.wpl;
-    const int t0 = d.leaf_begin[a], t1 = d.leaf_begin[a + 1];
+    const int t0 = d.leaf_begin[a], t1 = d.src_end[a];   // the leaf's sources
     const int row = part * blockDim.x + threadIdx.x;
     const bool act = row < R;
     const int64_t n = d.n;
@@ -483,7 +485,7 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
     const int mn = d.mn, R = d.R, CH = d.p2m_ch, H = d.H;
     const int ST = DM * mn;
     const int a = bid / d.wpl, part = bid % d.wpl;
-    const int t0 = d.leaf_begin[a], t1 = d.leaf_begin[a + 1];
+    const int t0 = d.leaf_begin[a], t1 = d.src_end[a];   // the leaf's sources
     const int64_t n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, jsel = lane >> 5, csel = (lane >> 4) & 1;
@@ -1182,6 +1184,7 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->off = 0;
     d->perm = p->perm;
     d->leaf_begin = p->leaf_begin;
+    d->src_end = p->src_end ? p->src_end : p->leaf_begin + 1;
     d->leaf_cell = p->leaf_cell;
     d->near_ptr = p->near_ptr;
     d->near_idx = p->near_idx;

@@ -24,6 +24,7 @@ template <class T> struct Desc {
     int64_t n;
     int64_t off;            // offset of this problem in the caller's (concatenated) vectors
     const int *perm, *leaf_begin, *leaf_cell, *near_ptr, *near_idx, *src_ptr, *cell_begin;
+    const int *src_end;     // end of each leaf's sources (leaf_begin + 1 unless targets are separate)
     const int2 *src_rng, *tasks, *ptasks;
     int nleaves, ntasks, nptasks;
     int64_t ncells;

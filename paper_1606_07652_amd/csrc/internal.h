@@ -89,15 +89,16 @@ struct rbf_plan {
     int *src_ptr = nullptr;          // merged source point ranges of the near field [nleaves + 1]
     int2 *src_rng = nullptr;         // [nranges] (begin, end)
     int *cell_leaf_begin = nullptr;  // [ncells + 1]
-    int2 *tasks = nullptr;           // (leaf, first point offset) per 64-point task [ntasks]
+    int2 *tasks = nullptr;           // (leaf, first target's offset in the leaf) per 64-target task [ntasks]
     // a plan for separate targets (rbf_fmm_plan_eval): caller points [0, n_src) are the sources,
     // [n_src, n) the targets, which take part with weight 0; 0 for an ordinary plan
     int64_t n_src = 0;
+    int *src_end = nullptr;          // such a plan orders each leaf's sources before its targets:
+                                     // sources [leaf_begin[a], src_end[a]), targets the rest [nleaves]
     void *ev_lam = nullptr;          // [n] the sources' weights followed by zeros
     void *ev_u = nullptr;            // [n] the product over all n points
-    // near-field tasks: (leaf, first point offset / 64 | log2(G) << 28): a leaf's last chunk
-    // of m points runs on G lane groups of 64 / G lanes that split its sources, G the largest
-    // power of two <= 8 with m <= 64 / G; full chunks have G = 1 [nptasks]
+    // near-field tasks: (leaf, first target), one per chunk of at most 64 targets of a leaf
+    // [nptasks]
     int2 *ptasks = nullptr;
     int nptasks = 0;
     // sibling groups of the leaf translation: runs of at most 8 consecutive leaves with one

@@ -395,26 +395,28 @@ __global__ void k_near(int nleaves, const uint64_t *keys, int n, int B, const in
 }
 
 // Merge consecutive near leaves into point ranges for the near-field kernel.
+// A leaf's sources are [leaf_begin[b], src_end[b]); near leaves b, b + 1 merge into one range
+// when b has no points after its sources.
 template <bool FILL>
 __global__ void k_ranges(int nleaves, const int *near_ptr, const int *near_idx, const int *leaf_begin,
-                         const int *rptr, int *rcnt, int2 *rng, int *npairs_part) {
+                         const int *src_end, const int *rptr, int *rcnt, int2 *rng, int *npairs_part) {
     int a = blockIdx.x * kThreads + threadIdx.x;
     if (a >= nleaves) return;
     int c = 0, total = 0;
     int b0 = -1, b1 = -1;
     for (int e = near_ptr[a]; e < near_ptr[a + 1]; ++e) {
         int b = near_idx[e];
-        if (b0 >= 0 && b == b1 + 1) { b1 = b; continue; }
+        if (b0 >= 0 && b == b1 + 1 && src_end[b1] == leaf_begin[b]) { b1 = b; continue; }
         if (b0 >= 0) {
-            if (FILL) rng[rptr[a] + c] = make_int2(leaf_begin[b0], leaf_begin[b1 + 1]);
-            total += leaf_begin[b1 + 1] - leaf_begin[b0];
+            if (FILL) rng[rptr[a] + c] = make_int2(leaf_begin[b0], src_end[b1]);
+            total += src_end[b1] - leaf_begin[b0];
             ++c;
         }
         b0 = b1 = b;
     }
     if (b0 >= 0) {
-        if (FILL) rng[rptr[a] + c] = make_int2(leaf_begin[b0], leaf_begin[b1 + 1]);
-        total += leaf_begin[b1 + 1] - leaf_begin[b0];
+        if (FILL) rng[rptr[a] + c] = make_int2(leaf_begin[b0], src_end[b1]);
+        total += src_end[b1] - leaf_begin[b0];
         ++c;
     }
     if (!FILL) {
@@ -423,10 +425,12 @@ __global__ void k_ranges(int nleaves, const int *near_ptr, const int *near_idx, 
     }
 }
 
-__global__ void k_pairs(int nleaves, const int *leaf_begin, const int *src_total, unsigned long long *acc) {
+// targets of leaf a: [tgt_begin[a], leaf_begin[a + 1])
+__global__ void k_pairs(int nleaves, const int *leaf_begin, const int *tgt_begin, const int *src_total,
+                        unsigned long long *acc) {
     int a = blockIdx.x * kThreads + threadIdx.x;
     if (a >= nleaves) return;
-    unsigned long long v = (unsigned long long)(leaf_begin[a + 1] - leaf_begin[a]) * (unsigned long long)src_total[a];
+    unsigned long long v = (unsigned long long)(leaf_begin[a + 1] - tgt_begin[a]) * (unsigned long long)src_total[a];
     atomicAdd(acc, v);
 }
 
@@ -581,16 +585,44 @@ int tree_typed(rbf_plan *p, const void *points_v) {
 #undef NEAR_LAUNCH
     RBF_HIP(hipGetLastError());
 
+    // A plan for separate targets orders each leaf's points sources first, targets after (each
+    // part keeps its Morton order), and records where the sources end.  The tree and the near
+    // lists do not depend on the order inside a leaf.
+    std::vector<int> hse;   // host copy of src_end (separate targets only)
+    if (p->n_src > 0) {
+        std::vector<int> hperm(n), hlb(nleaves + 1), np(n);
+        RBF_HIP(hipMemcpyAsync(hperm.data(), p->perm, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipMemcpyAsync(hlb.data(), p->leaf_begin, sizeof(int) * (nleaves + 1), hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipStreamSynchronize(s));
+        hse.resize(nleaves);
+        for (int a = 0; a < nleaves; ++a) {
+            int o = hlb[a];
+            for (int i = hlb[a]; i < hlb[a + 1]; ++i)
+                if (hperm[i] < p->n_src) np[o++] = hperm[i];
+            hse[a] = o;
+            for (int i = hlb[a]; i < hlb[a + 1]; ++i)
+                if (hperm[i] >= p->n_src) np[o++] = hperm[i];
+        }
+        RBF_TRY(ar.alloc((void **)&p->src_end, sizeof(int) * nleaves));
+        RBF_HIP(hipMemcpyAsync(p->src_end, hse.data(), sizeof(int) * nleaves, hipMemcpyHostToDevice, s));
+        RBF_HIP(hipMemcpyAsync(p->perm, np.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        k_gather_points<T><<<nbl, kThreads, 0, s>>>(pts, p->perm, n, d, (T *)p->xs);
+        RBF_HIP(hipGetLastError());
+        RBF_HIP(hipStreamSynchronize(s));   // np is freed at the end of this scope
+    }
+    const int *src_end = p->src_end ? p->src_end : p->leaf_begin + 1;
+    const int *tgt_begin = p->src_end ? p->src_end : p->leaf_begin;
+
     // merged source ranges for the near field
     int *rcnt = leaflev;   // reuse
     int *ptot = leafflag;  // reuse
-    k_ranges<false><<<nlb, kThreads, 0, s>>>(nleaves, p->near_ptr, p->near_idx, p->leaf_begin, nullptr, rcnt,
-                                             nullptr, ptot);
+    k_ranges<false><<<nlb, kThreads, 0, s>>>(nleaves, p->near_ptr, p->near_idx, p->leaf_begin, src_end, nullptr,
+                                             rcnt, nullptr, ptot);
     RBF_HIP(hipGetLastError());
     unsigned long long *pacc = nullptr;
     RBF_HIP(hipMalloc(&pacc, sizeof(unsigned long long)));
     RBF_HIP(hipMemsetAsync(pacc, 0, sizeof(unsigned long long), s));
-    k_pairs<<<nlb, kThreads, 0, s>>>(nleaves, p->leaf_begin, ptot, pacc);
+    k_pairs<<<nlb, kThreads, 0, s>>>(nleaves, p->leaf_begin, tgt_begin, ptot, pacc);
     RBF_HIP(hipGetLastError());
     unsigned long long npairs = 0;
     RBF_HIP(hipMemcpyAsync(&npairs, pacc, sizeof(npairs), hipMemcpyDeviceToHost, s));
@@ -601,10 +633,11 @@ int tree_typed(rbf_plan *p, const void *points_v) {
     p->nranges = nr;
     p->near_pairs = (int64_t)npairs;
     RBF_TRY(ar.alloc((void **)&p->src_rng, sizeof(int2) * std::max(nr, 1)));
-    k_ranges<true><<<nlb, kThreads, 0, s>>>(nleaves, p->near_ptr, p->near_idx, p->leaf_begin, p->src_ptr, nullptr,
-                                            p->src_rng, nullptr);
+    k_ranges<true><<<nlb, kThreads, 0, s>>>(nleaves, p->near_ptr, p->near_idx, p->leaf_begin, src_end, p->src_ptr,
+                                            nullptr, p->src_rng, nullptr);
     RBF_HIP(hipGetLastError());
-    // wave tasks: (leaf, offset) for every 64 consecutive points of a leaf
+    // wave tasks: (leaf, offset in the leaf) for every 64 consecutive targets of a leaf (all its
+    // points, or with separate targets the part after src_end)
     {
         std::vector<int> hb(nleaves + 1), hl(nleaves);
         RBF_HIP(hipMemcpyAsync(hb.data(), p->leaf_begin, sizeof(int) * (nleaves + 1), hipMemcpyDeviceToHost, s));
@@ -612,26 +645,19 @@ int tree_typed(rbf_plan *p, const void *points_v) {
         RBF_HIP(hipStreamSynchronize(s));
         p->min_leaf_level = *std::min_element(hl.begin(), hl.end());
         p->max_leaf_level = *std::max_element(hl.begin(), hl.end());
-        std::vector<int2> tk;
+        std::vector<int2> tk, pk;   // disaggregation tasks (offset in the leaf), near-field tasks
         tk.reserve(nleaves + n / kWave + 1);
-        for (int a = 0; a < nleaves; ++a)
-            for (int o = 0; o < hb[a + 1] - hb[a]; o += kWave) tk.push_back(make_int2(a, o));
+        pk.reserve(nleaves + n / kWave + 1);
+        for (int a = 0; a < nleaves; ++a) {
+            const int t0 = p->n_src > 0 ? hse[a] : hb[a];
+            for (int t = t0; t < hb[a + 1]; t += kWave) {
+                tk.push_back(make_int2(a, t - hb[a]));
+                pk.push_back(make_int2(a, t));
+            }
+        }
         p->ntasks = (int)tk.size();
         RBF_TRY(ar.alloc((void **)&p->tasks, sizeof(int2) * tk.size()));
         RBF_HIP(hipMemcpyAsync(p->tasks, tk.data(), sizeof(int2) * tk.size(), hipMemcpyHostToDevice, s));
-        // near-field tasks: a leaf's last chunk of m points, m <= 64 / (2 G), runs on G lane
-        // groups of 64 / G lanes that split the sources (G <= 8)
-        std::vector<int2> pk;
-        pk.reserve(tk.size());
-        for (int a = 0; a < nleaves; ++a) {
-            const int na = hb[a + 1] - hb[a];
-            for (int o = 0; o < na; o += kWave) {
-                const int m = std::min(kWave, na - o);
-                int gl = 0;
-                while (gl < 3 && m <= (kWave >> (gl + 1))) ++gl;   // 64 / 2^gl lanes hold m targets
-                pk.push_back(make_int2(a, (o / kWave) | (gl << 28)));
-            }
-        }
         p->nptasks = (int)pk.size();
         RBF_TRY(ar.alloc((void **)&p->ptasks, sizeof(int2) * pk.size()));
         RBF_HIP(hipMemcpyAsync(p->ptasks, pk.data(), sizeof(int2) * pk.size(), hipMemcpyHostToDevice, s));
