@@ -198,13 +198,15 @@ __global__ void k_boxes(const int *head, const int *ex, int n, int *box_start, i
     if (head[i]) box_start[b] = i;
 }
 
+// A box splits while it holds more than nmax points; with separate targets (src_pre: prefix
+// counts of sources in sorted order, else null) only its sources count.
 __global__ void k_box_status(int nboxes, const int *box_start, int lev, int maxlev, int minlev, int nmax,
-                             const int *bop_prev, const unsigned char *split_prev, unsigned char *split,
-                             int *leafflag, int *leaflev, int *any_split) {
+                             const int *src_pre, const int *bop_prev, const unsigned char *split_prev,
+                             unsigned char *split, int *leafflag, int *leaflev, int *any_split) {
     int b = blockIdx.x * kThreads + threadIdx.x;
     if (b >= nboxes) return;
     int s = box_start[b];
-    int cnt = box_start[b + 1] - s;
+    int cnt = src_pre ? src_pre[box_start[b + 1]] - src_pre[s] : box_start[b + 1] - s;
     int exists = (lev == 0) ? 1 : (int)split_prev[bop_prev[s]];
     int sp = exists && lev < maxlev && (lev < minlev || cnt > nmax);
     split[b] = (unsigned char)sp;
@@ -213,6 +215,11 @@ __global__ void k_box_status(int nboxes, const int *box_start, int lev, int maxl
         leaflev[s] = lev;
     }
     if (sp) atomicOr(any_split, 1);
+}
+
+__global__ void k_src_flag(const int *perm, int n, int64_t n_src, int *flag) {
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) flag[i] = perm[i] < n_src;
 }
 
 __global__ void k_leaves(const int *flag, const int *ex, const int *lev, const uint64_t *keys, int n, int d,
@@ -513,6 +520,16 @@ int tree_typed(rbf_plan *p, const void *points_v) {
     RBF_HIP(hipMalloc(&leaflev, sizeof(int) * n));
     RBF_HIP(hipMalloc(&anysplit, sizeof(int)));
     RBF_HIP(hipMemsetAsync(leafflag, 0, sizeof(int) * n, s));
+    int *srcpre = nullptr;   // separate targets: prefix counts of sources in sorted order [n + 1]
+    if (p->n_src > 0) {
+        RBF_HIP(hipMalloc(&srcpre, sizeof(int) * (n + 1)));
+        k_src_flag<<<nbl, kThreads, 0, s>>>(p->perm, n, p->n_src, head);
+        RBF_HIP(hipGetLastError());
+        int ns = 0;
+        RBF_TRY(exclusive_scan_i32(head, srcpre, n, &ns, s));
+        RBF_HIP(hipMemcpyAsync(srcpre + n, &ns, sizeof(int), hipMemcpyHostToDevice, s));
+        RBF_HIP(hipStreamSynchronize(s));   // ns is read by the copy
+    }
     const int maxlev = std::min(p->max_level, B);
     int cur = 0, lev = 0, nlev = 0;
     for (lev = 0; lev <= maxlev; ++lev) {
@@ -525,8 +542,8 @@ int tree_typed(rbf_plan *p, const void *points_v) {
         RBF_HIP(hipMemcpyAsync(bstart + nboxes, &n, sizeof(int), hipMemcpyHostToDevice, s));
         RBF_HIP(hipMemsetAsync(anysplit, 0, sizeof(int), s));
         k_box_status<<<(nboxes + kThreads - 1) / kThreads, kThreads, 0, s>>>(
-            nboxes, bstart, lev, maxlev, p->min_level, p->n_max, bop[cur ^ 1], spl[cur ^ 1], spl[cur], leafflag,
-            leaflev, anysplit);
+            nboxes, bstart, lev, maxlev, p->min_level, p->n_max, srcpre, bop[cur ^ 1], spl[cur ^ 1], spl[cur],
+            leafflag, leaflev, anysplit);
         RBF_HIP(hipGetLastError());
         int hs = 0;
         RBF_HIP(hipMemcpyAsync(&hs, anysplit, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -733,6 +750,7 @@ int tree_typed(rbf_plan *p, const void *points_v) {
     RBF_HIP(hipFree(leafflag));
     RBF_HIP(hipFree(leaflev));
     RBF_HIP(hipFree(anysplit));
+    if (srcpre) RBF_HIP(hipFree(srcpre));
     return RBF_OK;
 }
 
