@@ -43,7 +43,8 @@ def phase_model(info, dtype_bytes, n):
         # (kind, amount): flops for ALU-bound phases, bytes for memory-bound ones
         # per near pair: d differences, d multiply-adds for r^2, one scaling and one
         # multiply-add into the sum (3d + 3 flops), plus the FP64 exponential, which has no
-        # hardware instruction: counted as the 22 flops of its degree-11 polynomial
+        # hardware instruction: counted as a fixed 22 flops (its degree-11 Taylor evaluation),
+        # whatever method the kernel uses, so that faster exponentials show as a higher fraction
         "p2p": ("alu", pairs * (3 * d + 3 + 22)),
         "p2m": ("alu", 8.0 * n * P),
         "l2p": ("alu", 8.0 * n * P),

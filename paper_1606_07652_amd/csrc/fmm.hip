@@ -128,6 +128,29 @@ __device__ __forceinline__ double exp2_fp64(double t) {
     return ldexp(p, (int)k);   // the conversion saturates, so k below the int range gives 0
 }
 
+// 2^t in FP64 by the table-driven reduction of P. T. P. Tang (ACM TOMS 15(2), 1989), for the
+// near field: with s = 64 t rounded to the integer q = 64 k + j (0 <= j < 64) and u = s - q
+// (exact, |u| <= 1/2), 2^t = 2^k 2^(j/64) 2^(u/64); tab holds 2^(j/64) and 2^(u/64) comes from
+// its degree-5 Taylor polynomial, coefficients (ln 2 / 64)^n / n! (truncation below 4e-17
+// relative).  The argument is s = 64 t; very negative s underflows to 0 in the scaling.
+constexpr double exp2_64_taylor(int n) {
+    double c = 1.0;
+    for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / 64.0 / k;
+    return c;
+}
+__device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
+    const double qd = rint(s);
+    const double u = s - qd;
+    const int q = (int)qd;   // saturates; a saturated q gives 2^(huge negative) = 0
+    double p = exp2_64_taylor(5);
+    p = fma(p, u, exp2_64_taylor(4));
+    p = fma(p, u, exp2_64_taylor(3));
+    p = fma(p, u, exp2_64_taylor(2));
+    p = fma(p, u, exp2_64_taylor(1));
+    p = fma(p, u, 1.0);
+    return ldexp(p * tab[q & 63], q >> 6);   // q >> 6 = floor(q / 64)
+}
+
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32,
 // exp2_fp64 in FP64.  Multiquadric sqrt(r^2 + c^2): coef = c^2.
 template <> struct KFun<float> {
@@ -194,24 +217,28 @@ __device__ __forceinline__ void gather_body(DescC<T> &d, const T *__restrict__ l
 //    wave and a quarter wave of source steps instead of two full waves.
 template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 
+// The FP64 Gaussian of the near field goes through exp2_tab64 (coef then carries the factor 64
+// and tab the 64 table entries in LDS); other kernels and FP32 through KFun.
+template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
+
 template <class T, int D, int KER>
-__device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef) {
+__device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, const double *tab) {
     T r2 = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const T t = y[k] - x[k];
         r2 = fma(t, t, r2);
     }
-    return (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
+    if constexpr (kTabExp<T, KER>) return exp2_tab64(r2 * coef, tab);
+    else return (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
 }
 
 template <class T, int D, int KER>
-__device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int r1) {
+__device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, const double *tab) {
     constexpr int S = kP2pStep<T>;
     const int64_t n = d.n;
     const cptr<int> rng = uconst((const int *)d.src_rng);
     const cptr<T> X = (cptr<T>)d.xs, L = (cptr<T>)d.lam_s;
-    const T coef = d.coef;
     T acc = 0;
     for (int q = r0; q < r1; ++q) {
         const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
@@ -225,7 +252,7 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
 #pragma unroll
             for (int v = 0; v < S; ++v) w[v] = L[j + v];
 #pragma unroll
-            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
+            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
         }
         if (j < j1) {
             T x[S][D], w[S];
@@ -237,7 +264,7 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
                 w[v] = j + v < j1 ? L[jj] : T(0);
             }
 #pragma unroll
-            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
+            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
         }
     }
     return acc;
@@ -247,14 +274,13 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
 // per lane per step, a source past the range end repeats the last one with weight 0.  The
 // result is the group sums added over the groups (in every lane of the target).
 template <class T, int D, int KER, int G>
-__device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int r1) {
+__device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, const double *tab) {
     constexpr int TP = kWave / G, U = 2;
     const int64_t n = d.n;
     const cptr<int> rng = uconst((const int *)d.src_rng);
     const T *__restrict__ X = d.xs;
     const T *__restrict__ L = d.lam_s;
     const int g = (int)threadIdx.x / TP;
-    const T coef = d.coef;
     T acc = 0;
     for (int q = r0; q < r1; ++q) {
         const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
@@ -269,7 +295,7 @@ __device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int
                 w[v] = j < j1 ? L[jj] : T(0);
             }
 #pragma unroll
-            for (int v = 0; v < U; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef), acc);
+            for (int v = 0; v < U; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
         }
     }
 #pragma unroll
@@ -294,12 +320,19 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = act ? d.xs[k * n + ti] : T(0);
     const int r0 = sp[a], r1 = sp[a + 1];
+    __shared__ double tab[kWave];   // 2^(j/64), FP64 Gaussian only
+    T coef = d.coef;
+    if constexpr (kTabExp<T, KER>) {
+        tab[threadIdx.x] = exp2((double)threadIdx.x / kWave);
+        __syncthreads();
+        coef *= 64;   // exact
+    }
     T acc;
     switch (gl) {
-        case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1); break;
-        case 1: acc = p2p_split<T, D, KER, 2>(d, y, r0, r1); break;
-        case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1); break;
-        default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1); break;
+        case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1, coef, tab); break;
+        case 1: acc = p2p_split<T, D, KER, 2>(d, y, r0, r1, coef, tab); break;
+        case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1, coef, tab); break;
+        default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1, coef, tab); break;
     }
     if (act && (int)threadIdx.x < TP) {
         if (d.far) d.u_s[ti] = acc;
