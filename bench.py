@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VEC_TFLOPS = 78.6
+FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix-core peak (equal to the vector rate on this chip)
 FP32_VEC_TFLOPS = 157.3
 
 
@@ -40,14 +41,16 @@ def phase_model(info, dtype_bytes, n):
     cb = 2 * dtype_bytes
     pairs = info["near_pairs"]
     return {
-        # (kind, amount): flops for ALU-bound phases, bytes for memory-bound ones
+        # (kind, amount): flops for phases bound by the vector ALUs ("alu") or the matrix cores
+        # ("mfma"), bytes for memory-bound ones ("hbm"); the FP64 aggregation runs on the vector
+        # ALUs and the disaggregation on the matrix cores
         # per near pair: d differences, d multiply-adds for r^2, one scaling and one
         # multiply-add into the sum (3d + 3 flops), plus the FP64 exponential, which has no
         # hardware instruction: counted as a fixed 22 flops (its degree-11 Taylor evaluation),
         # whatever method the kernel uses, so that faster exponentials show as a higher fraction
         "p2p": ("alu", pairs * (3 * d + 3 + 22)),
         "p2m": ("alu", 8.0 * n * P),
-        "l2p": ("alu", 8.0 * n * P),
+        "l2p": ("mfma", 8.0 * n * P),
         "m2m": ("hbm", (nl + nc) * P * cb),
         "m2l_coarse": ("hbm", 2.0 * d * nc * P * cb),
         # compulsory bytes: every leaf expansion read once, every coarse local expansion
@@ -72,10 +75,12 @@ def measured_traffic(phase):
     return tab.get("bytes_per_launch", {}).get(phase)
 
 
-def roofline_of(kind, amount, ms, fp_peak):
+def roofline_of(kind, amount, ms, fp_peak, mfma_peak=FP64_MFMA_TFLOPS):
     secs = ms * 1e-3
     if kind == "hbm":
         r = {"bound": "hbm", "achieved": amount / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif kind == "mfma":
+        r = {"bound": "mfma", "achieved": amount / secs / 1e12, "peak": mfma_peak, "unit": "TFLOP/s"}
     else:
         r = {"bound": "alu", "achieved": amount / secs / 1e12, "peak": fp_peak, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
