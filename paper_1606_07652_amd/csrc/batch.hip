@@ -166,7 +166,8 @@ template <class T> int build_groups(rbf_batch *b) {
             std::memset(&d, 0, sizeof(d));
             fill_desc<T>(b->plans[q], &d);
             d.off = b->offsets[q];
-            d.m2l_sched = 0;   // block ids are problem-local here, so the XCD split does not apply
+            // the XCD-range order of the leaf translation (m2l_sched 1) gives every problem a
+            // multiple of 8 blocks, so problem-local block ids keep their XCD (id % 8)
             ds.push_back(d);
             g.p2m_sh = std::max(g.p2m_sh, (size_t)d.p2m_lds);
         }

@@ -711,7 +711,8 @@ __device__ __forceinline__ void m2l_axis_body(DescC<T> &d, int axis, int bid) {
 // plan time and is not written.
 // Block order (d.m2l_sched): 0 = group fastest, chunk slowest; 1 = the same order split
 // into 8 contiguous group ranges, one per XCD (dispatch puts block g on XCD g % 8), so that
-// the near rows a range re-reads stay in one XCD's L2.  Batches use 0.
+// the near rows a range re-reads stay in one XCD's L2.  In a batch every problem then has a
+// multiple of 8 blocks, so its problem-local block ids keep their XCD.
 constexpr int kLeafThreads = 256;   // expansion entries per leaf-translation workgroup
 
 template <class T, int D>
