@@ -94,13 +94,15 @@ int rbf_direct_matvec(rbf_plan *plan, const void *lambda, void *u);
  *   sources  device, (n, d) row-major, dtype, n >= 1;
  *   targets  device, (m, d) row-major, dtype, m >= 0 (may be NULL when m = 0);
  *   the other arguments as for rbf_fmm_plan.  Both sets are copied, so the caller may free
- *   them after the call.  The targets take part as points of weight zero: tree, near lists,
- *   tolerance rule and kernels are those of rbf_fmm_plan over the n + m points, a target
- *   outside the sources' bounding box included, and the cost of an evaluation is that of a
- *   product over n + m points.  Such a plan is used with rbf_fmm_eval and rbf_direct_eval
- *   only; rbf_fmm_matvec, rbf_direct_matvec, rbf_interp_solve and the preconditioner calls
- *   return RBF_EINVAL on it, and rbf_fmm_eval returns RBF_EINVAL on a plan from
- *   rbf_fmm_plan.  Synchronises the stream.  Errors as rbf_fmm_plan.
+ *   them after the call.  One tree covers both sets (a target outside the sources' bounding
+ *   box included); its boxes split on their source counts, and inside each leaf the sources
+ *   are aggregated and the targets evaluated, the near field pairing targets with sources.
+ *   The tolerance rule is that of rbf_fmm_plan over the n + m points.  An evaluation costs
+ *   about one product over the sources plus the targets' near field and disaggregation.
+ *   Such a plan is used with rbf_fmm_eval and rbf_direct_eval only; rbf_fmm_matvec,
+ *   rbf_direct_matvec, rbf_interp_solve and the preconditioner calls return RBF_EINVAL on
+ *   it, and rbf_fmm_eval returns RBF_EINVAL on a plan from rbf_fmm_plan.  Synchronises the
+ *   stream.  Errors as rbf_fmm_plan.
  * rbf_fmm_eval: lambda device, length n, plan dtype, the sources' order; u device, length
  *   m, plan dtype, the targets' order, overwritten (nothing is written when m = 0); must not
  *   alias lambda.  Asynchronous on the plan's stream; relative 2-norm error over the
