@@ -203,7 +203,7 @@ def test_full_size_mixed_sampled_targets():
     ls = w.lam.astype(np.float64)
     ref = direct.direct_sum(xs, ls, "gaussian", w.shape, targets=xs[idx])
     for dtype, tol in ((torch.float64, 1e-6), (torch.float32, 1e-4)):
-        p = plan(dev(w.points, dtype), kernel="gaussian", shape=w.shape, tol=tol, n_max=128)
+        p = plan(dev(w.points, dtype), kernel="gaussian", shape=w.shape, tol=tol, n_max=256)   # bench.py's
         u = p.matvec(dev(w.lam, dtype)).double().cpu().numpy()
         err = direct.rel_l2(u[idx], ref)
         print(f"[c2 {dtype}] sampled rel-L2 = {err:.3e} info={p.info()}", flush=True)
