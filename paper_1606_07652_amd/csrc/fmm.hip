@@ -109,7 +109,8 @@ constexpr double exp2_taylor(int n) {
 // 2^t in FP64: t = k + f with k = rint(t) and |f| <= 1/2 (t - k is exact), 2^f from its
 // degree-11 Taylor polynomial (truncation error below 7e-15 relative), scaled by 2^k.  Very
 // negative t underflows to 0 in the scaling.  Used for the Gaussian with
-// t = -r^2 log2(e) / (2 s^2) <= 0.
+// t = -r^2 log2(e) / (2 s^2) <= 0 where no LDS table is set up (the device direct sum); the
+// near field uses exp2_tab64 below.
 __device__ __forceinline__ double exp2_fp64(double t) {
     const double k = rint(t);
     const double f = t - k;
@@ -152,7 +153,8 @@ __device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
 }
 
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32,
-// exp2_fp64 in FP64.  Multiquadric sqrt(r^2 + c^2): coef = c^2.
+// exp2_fp64 in FP64 (the near field's FP64 Gaussian goes through exp2_tab64 instead).
+// Multiquadric sqrt(r^2 + c^2): coef = c^2.
 template <> struct KFun<float> {
     static __device__ __forceinline__ float gauss(float r2, float coef) { return __builtin_amdgcn_exp2f(r2 * coef); }
     static __device__ __forceinline__ float mq(float r2, float c2) { return __builtin_amdgcn_sqrtf(r2 + c2); }
