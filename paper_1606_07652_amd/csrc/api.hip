@@ -260,8 +260,17 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
         for (int k = 0; k < 2 * RBF_NPHASES && rc == RBF_OK; ++k)
             if (hipEventCreate(&p->ev[k]) != hipSuccess) { set_error("hipEventCreate failed"); rc = RBF_EHIP; }
     }
+    if (rc == RBF_OK && (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+                         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)) {
+        set_error("creating the near-field stream or its events failed");
+        rc = RBF_EHIP;
+    }
     if (rc != RBF_OK) {
         for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+        if (p->side) (void)hipStreamDestroy(p->side);
         p->arena.release();
         delete p;
         return rc;
@@ -410,6 +419,10 @@ int rbf_fmm_destroy(rbf_plan *plan) {
     if (!plan) return RBF_OK;
     (void)hipStreamSynchronize(plan->stream);
     for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (plan->ev[k]) (void)hipEventDestroy(plan->ev[k]);
+    if (plan->side) (void)hipStreamSynchronize(plan->side);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     plan->solver_arena.release();
     plan->pc_arena.release();
     plan->arena.release();

@@ -1015,15 +1015,24 @@ template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) 
 }
 
 // ---- host side -----------------------------------------------------------------------
-struct PhaseTimer {
+// Per-product launch context: phase timing (HIP events, when the plan profiles) and the
+// optional side stream of the near field with its fork and join events (single problems).
+struct ProductRun {
     rbf_plan *p;   // null: no timing
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int ph = -1;
-    explicit PhaseTimer(rbf_plan *pp) : p(pp && pp->profiling ? pp : nullptr) {}
-    hipError_t begin(int k) {
+    hipStream_t st = nullptr;
+    ProductRun(rbf_plan *pp, bool overlap)
+        : p(pp && pp->profiling ? pp : nullptr), side(overlap && pp ? pp->side : nullptr),
+          fork(overlap && pp ? pp->ev_fork : nullptr), join(overlap && pp ? pp->ev_join : nullptr) {}
+    // timing events go on stream s (the stream the phase runs on)
+    hipError_t begin(int k, hipStream_t s) {
         ph = k;
-        return p ? hipEventRecord(p->ev[2 * k], p->stream) : hipSuccess;
+        st = s;
+        return p ? hipEventRecord(p->ev[2 * k], s) : hipSuccess;
     }
-    hipError_t end() { return p ? hipEventRecord(p->ev[2 * ph + 1], p->stream) : hipSuccess; }
+    hipError_t end() { return p ? hipEventRecord(p->ev[2 * ph + 1], st) : hipSuccess; }
 };
 
 // Per-phase block counts of one problem (the grid of a single-problem launch).
@@ -1085,39 +1094,50 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
 // bstarts[phase] holds the per-problem block prefix of each phase (batch only).
 template <class T, int D, int HMAX>
 int product_d(const Work<T> &w0, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh, int kernel,
-              hipStream_t s, PhaseTimer &pt) {
+              hipStream_t s, ProductRun &pt) {
     Work<T> w = w0;
     auto bs = [&](int ph) {
         if (w0.nprob) w.bstart = bstarts[ph];
     };
-    RBF_HIP(pt.begin(0));
+    RBF_HIP(pt.begin(0, s));
     bs(PH_GATHER);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_GATHER, nblocks[PH_GATHER], s, 0, 0, kernel)));
     RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(1));
-    bs(PH_P2P);
-    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2P, nblocks[PH_P2P], s, 0, 0, kernel)));
-    RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(2));
+    RBF_HIP(pt.begin(2, s));
     bs(PH_PHASE_DL);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_PHASE_DL, nblocks[PH_PHASE_DL], s, 0, 0, kernel)));
     bs(PH_P2M);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2M, nblocks[PH_P2M], s, 0, p2m_sh, kernel)));
     RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(3));
+    // near field: on the side stream when there is one, forked after the aggregation so that it
+    // runs beside the memory-bound upward pass and translations rather than beside the
+    // aggregation's arithmetic
+    hipStream_t sn = s;
+    if (pt.side) {
+        RBF_HIP(hipEventRecord(pt.fork, s));
+        RBF_HIP(hipStreamWaitEvent(pt.side, pt.fork, 0));
+        sn = pt.side;
+    }
+    RBF_HIP(pt.begin(1, sn));
+    bs(PH_P2P);
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2P, nblocks[PH_P2P], sn, 0, 0, kernel)));
+    RBF_HIP(pt.end());
+    if (pt.side) RBF_HIP(hipEventRecord(pt.join, sn));
+    RBF_HIP(pt.begin(3, s));
     bs(PH_M2M);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2M, nblocks[PH_M2M], s, 0, 0, kernel)));
     RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(4));
+    RBF_HIP(pt.begin(4, s));
     bs(PH_M2L_AXIS);
     for (int ax = 0; ax < D; ++ax)
         RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_AXIS, nblocks[PH_M2L_AXIS], s, ax, 0, kernel)));
     RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(5));
+    RBF_HIP(pt.begin(5, s));
     bs(PH_M2L_LEAF);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_LEAF, nblocks[PH_M2L_LEAF], s, 0, 0, kernel)));
     RBF_HIP(pt.end());
-    RBF_HIP(pt.begin(6));
+    if (pt.side) RBF_HIP(hipStreamWaitEvent(s, pt.join, 0));   // the disaggregation reads u_s
+    RBF_HIP(pt.begin(6, s));
     bs(PH_L2P);
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_L2P, nblocks[PH_L2P], s, 0, 0, kernel)));
     RBF_HIP(pt.end());
@@ -1126,7 +1146,7 @@ int product_d(const Work<T> &w0, int64_t const *nblocks, const int *const *bstar
 
 template <class T, int D>
 int product_dispatch(int HP, const Work<T> &w, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh,
-                     int kernel, hipStream_t s, PhaseTimer &pt) {
+                     int kernel, hipStream_t s, ProductRun &pt) {
 #define CASE_H(V) \
     case V: return product_d<T, D, V>(w, nblocks, bstarts, p2m_sh, kernel, s, pt);
     switch (HP) {
@@ -1155,7 +1175,7 @@ int product_dispatch(int HP, const Work<T> &w, int64_t const *nblocks, const int
 
 template <class T>
 int product_t(int d, int HP, const Work<T> &w, int64_t const *nblocks, const int *const *bstarts, size_t p2m_sh,
-              int kernel, hipStream_t s, PhaseTimer &pt) {
+              int kernel, hipStream_t s, ProductRun &pt) {
     switch (d) {
         case 2: return product_dispatch<T, 2>(HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
         case 3: return product_dispatch<T, 3>(HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
@@ -1174,7 +1194,7 @@ int matvec_t(rbf_plan *p, const void *lam, void *u) {
     w.u = (T *)u;
     int64_t nb[PH_COUNT];
     for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
-    PhaseTimer pt(p);
+    ProductRun pt(p, true);
     RBF_TRY(product_t<T>(p->d, p->HP, w, nb, nullptr, p2m_shmem<T>(w.one, p->d), p->kernel, p->stream, pt));
     if (p->profiling) {
         RBF_HIP(hipEventSynchronize(p->ev[2 * RBF_NPHASES - 1]));
@@ -1293,7 +1313,7 @@ int launch_batch_group(int d, int HP, int kernel, const Desc<T> *descs, int npro
     w.nprob = nprob;
     w.lam = lam;
     w.u = u;
-    PhaseTimer pt(nullptr);
+    ProductRun pt(nullptr, false);
     return product_t<T>(d, HP, w, nblocks, bstarts, p2m_sh, kernel, s, pt);
 }
 template int launch_batch_group<float>(int, int, int, const Desc<float> *, int, const int *const *, const int64_t *,

@@ -123,6 +123,11 @@ struct rbf_plan {
     void *Lc = nullptr;              // coarse local expansions [ncells][P]
     void *Tmp = nullptr;             // stencil pass buffer [ncells][P]
 
+    // the near field of a product runs on a second stream of default priority, forked after the
+    // permutation and joined before the disaggregation (it reads nothing the far-field chain
+    // writes, and only the disaggregation reads its result)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // profiling
     int profiling = 0;
     hipEvent_t ev[2 * RBF_NPHASES] = {};
