@@ -351,7 +351,7 @@ def run_c4(args):
 
 def run_c2mq(args):
     """3-D mixed points (as the default workload), multiquadric c = 0.02: the plan holds one
-    leaf and the product is the exact sum through the tiled near-field kernel (no band-limited
+    leaf and the product is the exact sum through the tiled direct kernel (no band-limited
     far field for this kernel in this build).  FP64 and FP32; the oracle checks 2048 targets."""
     import torch
 

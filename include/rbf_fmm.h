@@ -40,8 +40,9 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
 /* Kernels of the paper's table "Global functions" (section 2.2).  The Gaussian is used in
  * the shape form exp(-r^2 / (2 s^2)) (shape = s > 0); the multiquadric is sqrt(r^2 + c^2)
  * (shape = c > 0).  This build has no band-limited far field for the multiquadric: its plans
- * hold a single leaf and the product is the exact O(N^2) sum through the tiled near-field
- * kernel (tol and the tree options are ignored). */
+ * hold a single leaf and the product is the exact O(N^2) sum through the tiled direct kernel
+ * (tol and the tree options are ignored).  Any plan of one leaf without a far field computes
+ * its product that way. */
 enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
 

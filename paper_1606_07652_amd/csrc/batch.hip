@@ -90,13 +90,16 @@ int bbox_ext(const void *points, int64_t n, int d, int dtype, hipStream_t s, dou
     return RBF_OK;
 }
 
-int time_plan(rbf_plan *p, void *lam, void *u, int reps, double *ms) {
+// Times reps products of the plan; for_batch: through the per-phase kernels, as a batch runs them
+// (a single plan of one leaf would otherwise take the direct kernel).
+int time_plan(rbf_plan *p, void *lam, void *u, int reps, bool for_batch, double *ms) {
+    auto run = [&]() { return for_batch ? launch_matvec_phases(p, lam, u) : launch_matvec(p, lam, u); };
     hipEvent_t a, b;
     RBF_HIP(hipEventCreate(&a));
     RBF_HIP(hipEventCreate(&b));
-    int rc = launch_matvec(p, lam, u);   // warm-up
+    int rc = run();   // warm-up
     if (rc == RBF_OK) rc = (hipEventRecord(a, p->stream) == hipSuccess) ? RBF_OK : RBF_EHIP;
-    for (int r = 0; r < reps && rc == RBF_OK; ++r) rc = launch_matvec(p, lam, u);
+    for (int r = 0; r < reps && rc == RBF_OK; ++r) rc = run();
     if (rc == RBF_OK) rc = (hipEventRecord(b, p->stream) == hipSuccess) ? RBF_OK : RBF_EHIP;
     if (rc == RBF_OK) rc = (hipEventSynchronize(b) == hipSuccess) ? RBF_OK : RBF_EHIP;
     float t = 0;
@@ -115,7 +118,7 @@ __global__ void k_fill_one(void *v, int64_t n, int dtype) {
 }
 
 int autotune_impl(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
-                  const rbf_opts *base, int reps, hipStream_t s, rbf_opts *best, double *best_ms) {
+                  const rbf_opts *base, int reps, hipStream_t s, bool for_batch, rbf_opts *best, double *best_ms) {
     double ext = 1.0;
     RBF_TRY(bbox_ext(points, n, d, dtype, s, &ext));
     auto cands = candidates(base, n, d, shape, tol, ext);
@@ -130,7 +133,7 @@ int autotune_impl(const void *points, int64_t n, int d, int dtype, int kernel, d
         rbf_plan *p = nullptr;
         if (plan_create(points, n, d, dtype, kernel, shape, tol, &c, s, &p) != RBF_OK) continue;
         double ms = INFINITY;
-        int rc = time_plan(p, lam, u, reps, &ms);
+        int rc = time_plan(p, lam, u, reps, for_batch, &ms);
         rbf_fmm_destroy(p);
         if (rc != RBF_OK) continue;
         if (ms < bms) {
@@ -231,7 +234,7 @@ extern "C" int rbf_fmm_autotune(const void *points, int64_t n, int d, int dtype,
                                 const rbf_opts *base, int reps, void *stream, rbf_opts *best, double *best_ms) {
     if (!points || !best) { set_error("rbf_fmm_autotune: null argument"); return RBF_EINVAL; }
     if (n < 1) { set_error("rbf_fmm_autotune: n must be positive"); return RBF_EINVAL; }
-    return autotune_impl(points, n, d, dtype, kernel, shape, tol, base, reps > 0 ? reps : 3, (hipStream_t)stream,
+    return autotune_impl(points, n, d, dtype, kernel, shape, tol, base, reps > 0 ? reps : 3, (hipStream_t)stream, false,
                          best, best_ms);
 }
 
@@ -280,7 +283,7 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
         else { o.coarse_level = -1; o.coarse_radius = -1; }
         if (autotune) {
             double ms = 0;
-            rc = autotune_impl(pq, nq, d, dtype, kernel, shapes[q], tol, &o, 2, b->stream, &o, &ms);
+            rc = autotune_impl(pq, nq, d, dtype, kernel, shapes[q], tol, &o, 2, b->stream, true, &o, &ms);
             if (rc != RBF_OK) break;
         }
         rbf_plan *p = nullptr;

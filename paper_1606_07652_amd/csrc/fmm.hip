@@ -97,43 +97,13 @@ __host__ __device__ constexpr int l2p_targets(int csize, int dim, int hmax) {
 }
 
 template <class T> struct KFun;
-template <class T> struct KFun;
-
-// Coefficient n of the Taylor series of 2^f = e^{f ln 2}: (ln 2)^n / n!.
-constexpr double exp2_taylor(int n) {
-    double c = 1.0;
-    for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / k;
-    return c;
-}
-
-// 2^t in FP64: t = k + f with k = rint(t) and |f| <= 1/2 (t - k is exact), 2^f from its
-// degree-11 Taylor polynomial (truncation error below 7e-15 relative), scaled by 2^k.  Very
-// negative t underflows to 0 in the scaling.  Used for the Gaussian with
-// t = -r^2 log2(e) / (2 s^2) <= 0 where no LDS table is set up (the device direct sum); the
-// near field uses exp2_tab64 below.
-__device__ __forceinline__ double exp2_fp64(double t) {
-    const double k = rint(t);
-    const double f = t - k;
-    double p = exp2_taylor(11);
-    p = fma(p, f, exp2_taylor(10));
-    p = fma(p, f, exp2_taylor(9));
-    p = fma(p, f, exp2_taylor(8));
-    p = fma(p, f, exp2_taylor(7));
-    p = fma(p, f, exp2_taylor(6));
-    p = fma(p, f, exp2_taylor(5));
-    p = fma(p, f, exp2_taylor(4));
-    p = fma(p, f, exp2_taylor(3));
-    p = fma(p, f, exp2_taylor(2));
-    p = fma(p, f, exp2_taylor(1));
-    p = fma(p, f, 1.0);
-    return ldexp(p, (int)k);   // the conversion saturates, so k below the int range gives 0
-}
 
 // 2^t in FP64 by the table-driven reduction of P. T. P. Tang (ACM TOMS 15(2), 1989), for the
-// near field: with s = 64 t rounded to the integer q = 64 k + j (0 <= j < 64) and u = s - q
-// (exact, |u| <= 1/2), 2^t = 2^k 2^(j/64) 2^(u/64); tab holds 2^(j/64) and 2^(u/64) comes from
-// its degree-5 Taylor polynomial, coefficients (ln 2 / 64)^n / n! (truncation below 4e-17
-// relative).  The argument is s = 64 t; very negative s underflows to 0 in the scaling.
+// near field and the direct sum: with s = 64 t rounded to the integer q = 64 k + j
+// (0 <= j < 64) and u = s - q (exact, |u| <= 1/2), 2^t = 2^k 2^(j/64) 2^(u/64); tab holds
+// 2^(j/64) and 2^(u/64) comes from its degree-5 Taylor polynomial, coefficients
+// (ln 2 / 64)^n / n! (truncation below 4e-17 relative).  The argument is s = 64 t; very
+// negative s underflows to 0 in the scaling.
 constexpr double exp2_64_taylor(int n) {
     double c = 1.0;
     for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / 64.0 / k;
@@ -152,15 +122,13 @@ __device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
     return ldexp(p * tab[q & 63], q >> 6);   // q >> 6 = floor(q / 64)
 }
 
-// Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32,
-// exp2_fp64 in FP64 (the near field's FP64 Gaussian goes through exp2_tab64 instead).
-// Multiquadric sqrt(r^2 + c^2): coef = c^2.
+// Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32 (in
+// FP64 the kernels call exp2_tab64 with its LDS table).  Multiquadric sqrt(r^2 + c^2): coef = c^2.
 template <> struct KFun<float> {
     static __device__ __forceinline__ float gauss(float r2, float coef) { return __builtin_amdgcn_exp2f(r2 * coef); }
     static __device__ __forceinline__ float mq(float r2, float c2) { return __builtin_amdgcn_sqrtf(r2 + c2); }
 };
 template <> struct KFun<double> {
-    static __device__ __forceinline__ double gauss(double r2, double coef) { return exp2_fp64(r2 * coef); }
     static __device__ __forceinline__ double mq(double r2, double c2) { return sqrt(r2 + c2); }
 };
 
@@ -232,7 +200,8 @@ __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, 
         r2 = fma(t, t, r2);
     }
     if constexpr (kTabExp<T, KER>) return exp2_tab64(r2 * coef, tab);
-    else return (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, coef) : KFun<T>::mq(r2, coef);
+    else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
+    else return KFun<T>::mq(r2, coef);
 }
 
 template <class T, int D, int KER>
@@ -354,6 +323,12 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
     T y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
+    __shared__ double tab[kWave];   // 2^(j/64), FP64 Gaussian only (filled before the first barrier)
+    T coef = d.coef;
+    if constexpr (kTabExp<T, KER>) {
+        if (threadIdx.x < kWave) tab[threadIdx.x] = exp2((double)threadIdx.x / kWave);
+        coef *= 64;   // exact
+    }
     T acc = 0;
     for (int64_t base = 0; base < n; base += kTile) {
         const int cnt = (int)min((int64_t)kTile, n - base);
@@ -371,7 +346,10 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
                 T t = y[k] - sdat[e * DP + k];
                 r2 += t * t;
             }
-            T ph = (KER == RBF_GAUSSIAN) ? KFun<T>::gauss(r2, d.coef) : KFun<T>::mq(r2, d.coef);
+            T ph;
+            if constexpr (kTabExp<T, KER>) ph = exp2_tab64(r2 * coef, tab);
+            else if constexpr (KER == RBF_GAUSSIAN) ph = KFun<T>::gauss(r2, coef);
+            else ph = KFun<T>::mq(r2, coef);
             acc += sdat[e * DP + D] * ph;
         }
     }
@@ -1185,6 +1163,18 @@ int product_t(int d, int HP, const Work<T> &w, int64_t const *nblocks, const int
     return RBF_EUNSUPPORTED;
 }
 
+// Adds the phase durations of the product just launched (events ev[2k], ev[2k + 1]).
+int add_phase_times(rbf_plan *p) {
+    RBF_HIP(hipEventSynchronize(p->ev[2 * RBF_NPHASES - 1]));
+    for (int k = 0; k < RBF_NPHASES; ++k) {
+        float ms = 0.f;
+        RBF_HIP(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));
+        p->phase_ms[k] += ms;
+    }
+    p->prof_calls += 1;
+    return RBF_OK;
+}
+
 template <class T>
 int matvec_t(rbf_plan *p, const void *lam, void *u) {
     Work<T> w{};
@@ -1196,15 +1186,7 @@ int matvec_t(rbf_plan *p, const void *lam, void *u) {
     for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
     ProductRun pt(p, true);
     RBF_TRY(product_t<T>(p->d, p->HP, w, nb, nullptr, p2m_shmem<T>(w.one, p->d), p->kernel, p->stream, pt));
-    if (p->profiling) {
-        RBF_HIP(hipEventSynchronize(p->ev[2 * RBF_NPHASES - 1]));
-        for (int k = 0; k < RBF_NPHASES; ++k) {
-            float ms = 0.f;
-            RBF_HIP(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));
-            p->phase_ms[k] += ms;
-        }
-        p->prof_calls += 1;
-    }
+    if (p->profiling) RBF_TRY(add_phase_times(p));
     return RBF_OK;
 }
 
@@ -1321,8 +1303,30 @@ template int launch_batch_group<float>(int, int, int, const Desc<float> *, int, 
 template int launch_batch_group<double>(int, int, int, const Desc<double> *, int, const int *const *,
                                         const int64_t *, size_t, const double *, double *, hipStream_t);
 
-int launch_matvec(rbf_plan *p, const void *lambda, void *u) {
+// A plan of one leaf without a far field (the autotuner's direct choice, the multiquadric) is the
+// exact sum over all pairs; the tiled direct kernel computes it faster than the near-field
+// kernel, whose waves would each stream the whole point set through scalar loads.  With
+// profiling the whole sum counts as the near field.  Plans for separate targets keep the
+// near-field kernel, which pairs targets with sources only.
+int direct_product(rbf_plan *p, const void *lambda, void *u) {
+    hipStream_t s = p->stream;
+    if (p->profiling)
+        for (int k = 0; k < 3; ++k) RBF_HIP(hipEventRecord(p->ev[k], s));
+    RBF_TRY(p->dtype == RBF_F32 ? direct_t<float>(p, lambda, u) : direct_t<double>(p, lambda, u));
+    if (p->profiling) {
+        for (int k = 3; k < 2 * RBF_NPHASES; ++k) RBF_HIP(hipEventRecord(p->ev[k], s));
+        RBF_TRY(add_phase_times(p));
+    }
+    return RBF_OK;
+}
+
+int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u) {
     return p->dtype == RBF_F32 ? matvec_t<float>(p, lambda, u) : matvec_t<double>(p, lambda, u);
+}
+
+int launch_matvec(rbf_plan *p, const void *lambda, void *u) {
+    if (p->nleaves == 1 && !p->far && p->n_src == 0) return direct_product(p, lambda, u);
+    return launch_matvec_phases(p, lambda, u);
 }
 
 int launch_direct(rbf_plan *p, const void *lambda, void *u) {

@@ -165,6 +165,8 @@ int plan_create(const void *points, int64_t n, int d, int dtype, int kernel, dou
 int build_tree(rbf_plan *p, const void *points);
 int build_near_lists(rbf_plan *p);
 int launch_matvec(rbf_plan *p, const void *lambda, void *u);
+// the product through the per-phase kernels (what a batch runs), never the direct kernel
+int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u);
 // RBF_EINVAL (with a message naming fn) when p is a plan for separate targets
 int reject_eval_plan(const rbf_plan *p, const char *fn);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);

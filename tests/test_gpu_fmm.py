@@ -270,30 +270,33 @@ def test_fp64_many_nodes_uses_the_small_target_tiles():
 
 def test_fp64_near_field_exponential_over_its_range():
     """One unit source and targets at distances whose exponent r^2/(2 s^2) runs from 0 to about
-    700, all in one leaf (near field only): every output is exp(-r^2/(2 s^2)) from the
-    near-field kernel's exponential, checked element by element against the oracle's libm
-    exp.  The bound allows the roundings of r^2 on both sides (about four each, fused on the
-    device and not in the oracle: each moves the value by ~1.1e-16 times the exponent) on top
-    of a few units in the last place."""
+    700, in one leaf of a plan for separate targets (near field only): every output is
+    exp(-r^2/(2 s^2)) from the near-field kernel's exponential, checked element by element
+    against the oracle's libm exp; the same for the device direct sum.  The bound allows the
+    roundings of r^2 on both sides (about four each, fused on the device and not in the oracle:
+    each moves the value by ~1.1e-16 times the exponent) on top of a few units in the last
+    place."""
+    from paper_1606_07652_amd import EvalPlan
     s = 0.03
-    n = 4096
+    m = 4095
     rng = np.random.default_rng(200)
-    t = np.sort(rng.uniform(0.0, 700.0, n - 1))
+    t = np.sort(rng.uniform(0.0, 700.0, m))
     r = s * np.sqrt(2.0 * t)
-    dirs = rng.normal(size=(n - 1, 3))
+    dirs = rng.normal(size=(m, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    x = np.concatenate([np.array([[0.5, 0.5, 0.5]]), 0.5 + dirs * r[:, None]])
-    lam = np.zeros(n)
-    lam[0] = 1.0
-    p = plan(dev(x), kernel="gaussian", shape=s, tol=1e-6, n_max=10 ** 6, coarse_level=0)
+    x0 = np.array([[0.5, 0.5, 0.5]])
+    y = 0.5 + dirs * r[:, None]
+    p = EvalPlan(dev(x0), dev(y), kernel="gaussian", shape=s, tol=1e-6, n_max=10 ** 6, coarse_level=0)
     inf = p.info()
     assert inf["nleaves"] == 1 and inf["far_field"] == 0
-    u = p.matvec(dev(lam)).cpu().numpy()
-    ref = direct.direct_sum(x, lam, "gaussian", s)
-    expo = ((x - x[0]) ** 2).sum(1) / (2 * s * s)
+    ref = direct.direct_sum(x0, np.array([1.0]), "gaussian", s, targets=y)
+    expo = ((y - x0) ** 2).sum(1) / (2 * s * s)
     ok = ref > 1e-300
-    rel = np.abs(u[ok] - ref[ok]) / ref[ok]
     bound = 8e-16 * (1.0 + expo[ok])
-    print(f"[exp range] max rel err {rel.max():.3e}, worst ratio to bound {(rel / bound).max():.3f}", flush=True)
-    assert np.all(rel <= bound)
-    assert np.all(u[~ok] <= 1e-290)
+    for name, u in (("near field", p.eval(dev(np.array([1.0])))), ("direct", p.direct(dev(np.array([1.0]))))):
+        u = u.cpu().numpy()
+        rel = np.abs(u[ok] - ref[ok]) / ref[ok]
+        print(f"[exp range, {name}] max rel err {rel.max():.3e}, worst ratio to bound {(rel / bound).max():.3f}",
+              flush=True)
+        assert np.all(rel <= bound)
+        assert np.all(u[~ok] <= 1e-290)
