@@ -260,17 +260,8 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
         for (int k = 0; k < 2 * RBF_NPHASES && rc == RBF_OK; ++k)
             if (hipEventCreate(&p->ev[k]) != hipSuccess) { set_error("hipEventCreate failed"); rc = RBF_EHIP; }
     }
-    if (rc == RBF_OK && (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
-                         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-                         hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)) {
-        set_error("creating the near-field stream or its events failed");
-        rc = RBF_EHIP;
-    }
     if (rc != RBF_OK) {
         for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
-        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-        if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-        if (p->side) (void)hipStreamDestroy(p->side);
         p->arena.release();
         delete p;
         return rc;

@@ -1163,6 +1163,25 @@ int product_t(int d, int HP, const Work<T> &w, int64_t const *nblocks, const int
     return RBF_EUNSUPPORTED;
 }
 
+// Creates the plan's near-field stream and its fork/join events on first use; without them
+// the product runs on one stream.
+void ensure_side_stream(rbf_plan *p) {
+    if (p->side_state != 0) return;
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) == hipSuccess) {
+        p->side_state = 1;
+        return;
+    }
+    (void)hipGetLastError();   // clear the failure: the product falls back to one stream
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    p->side = nullptr;
+    p->ev_fork = p->ev_join = nullptr;
+    p->side_state = -1;
+}
+
 // Adds the phase durations of the product just launched (events ev[2k], ev[2k + 1]).
 int add_phase_times(rbf_plan *p) {
     RBF_HIP(hipEventSynchronize(p->ev[2 * RBF_NPHASES - 1]));
@@ -1184,7 +1203,8 @@ int matvec_t(rbf_plan *p, const void *lam, void *u) {
     w.u = (T *)u;
     int64_t nb[PH_COUNT];
     for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
-    ProductRun pt(p, true);
+    ensure_side_stream(p);
+    ProductRun pt(p, p->side_state == 1);
     RBF_TRY(product_t<T>(p->d, p->HP, w, nb, nullptr, p2m_shmem<T>(w.one, p->d), p->kernel, p->stream, pt));
     if (p->profiling) RBF_TRY(add_phase_times(p));
     return RBF_OK;

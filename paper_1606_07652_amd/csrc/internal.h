@@ -126,8 +126,10 @@ struct rbf_plan {
     // the near field of a product runs on a second stream of default priority, forked after the
     // permutation and joined before the disaggregation (it reads nothing the far-field chain
     // writes, and only the disaggregation reads its result)
+    // (created at the first single-problem product; a plan used only inside a batch has none)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int side_state = 0;              // 0 not tried, 1 ready, -1 unavailable (one stream)
     // profiling
     int profiling = 0;
     hipEvent_t ev[2 * RBF_NPHASES] = {};
