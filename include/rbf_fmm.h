@@ -208,16 +208,19 @@ int rbf_fmm_autotune(const void *points, int64_t n, int d, int dtype, int kernel
 
 /* ---- batches of independent problems --------------------------------------------------
  * Many interpolation problems of uneven size, each with its own point set and shape, in
- * one set of launches: every phase of the product runs as one grid over all problems, and
- * the whole batched product is captured once into a HIP graph and replayed.
+ * one set of launches: problems that share a padded half grid form a group, every phase of
+ * the product runs as one grid over a group's problems, the groups run concurrently on up to
+ * eight private streams, and the whole batched product is captured once into a HIP graph and
+ * replayed.
  *   points   device, concatenated (sum n_p, d) row-major, dtype.
  *   offsets  host int64[nprob + 1]: problem p owns rows offsets[p] .. offsets[p+1]-1
  *            (strictly increasing, offsets[0] = 0).
  *   shapes   host double[nprob]: kernel shape of each problem.
  *   opts     host, may be NULL: applied to every problem (base of the autotuner).
  *   autotune nonzero: choose each problem's configuration with rbf_fmm_autotune (2 reps).
- * The batch owns a private stream ordered after `stream` with events; products are
- * asynchronous with respect to the host and ordered on `stream`. */
+ * The batch owns private streams ordered after `stream` with events (the group streams fork
+ * from the first and join it before the product ends); products are asynchronous with
+ * respect to the host and ordered on `stream`. */
 typedef struct rbf_batch rbf_batch;
 int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, int nprob, int d, int dtype, int kernel,
                        const double *shapes, double tol, const rbf_opts *opts, int autotune, void *stream,

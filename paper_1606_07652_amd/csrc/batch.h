@@ -13,7 +13,8 @@ struct rbf_batch {
     std::vector<int64_t> offsets;
     std::vector<int> n_max, nodes, far;
     struct Group {
-        int HP = 0, nprob = 0;
+        int HP = 0, nprob = 0, lane = 0;
+        int64_t points = 0;
         void *descs = nullptr;
         int *bstart[rbf::PH_COUNT] = {};
         int64_t nblocks[rbf::PH_COUNT] = {};
@@ -27,6 +28,11 @@ struct rbf_batch {
     const void *g_lam = nullptr;
     void *g_u = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // groups run concurrently on lanes: lane 0 is `stream`, lane k > 0 is lanes[k - 1], forked
+    // from `stream` at ev_fork and joined back at lane_done[k - 1]
+    std::vector<hipStream_t> lanes;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t ev_fork = nullptr;
     double plan_seconds = 0;
 };
 

@@ -152,6 +152,38 @@ int autotune_impl(const void *points, int64_t n, int d, int dtype, int kernel, d
     return RBF_OK;
 }
 
+// Groups touch disjoint problems, so they run concurrently: the largest group (by points) goes
+// first to the least-loaded lane.  One lane per group measured faster than fewer lanes even
+// though lanes share the process's few hardware queues; the cap bounds the streams a batch holds.
+constexpr int kBatchLanes = 8;
+
+int assign_lanes(rbf_batch *b) {
+    const int ng = (int)b->groups.size();
+    const int nl = std::min(ng, kBatchLanes);
+    std::vector<int> order(ng);
+    for (int k = 0; k < ng; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->groups[x].points > b->groups[y].points; });
+    std::vector<int64_t> load(nl, 0);
+    for (int k : order) {
+        int best = 0;
+        for (int l = 1; l < nl; ++l)
+            if (load[l] < load[best]) best = l;
+        b->groups[k].lane = best;
+        load[best] += b->groups[k].points;
+    }
+    for (int l = 1; l < nl; ++l) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        RBF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->lanes.push_back(s);
+        RBF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->lane_done.push_back(e);
+    }
+    if (nl > 1) RBF_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    return RBF_OK;
+}
+
 template <class T> int build_groups(rbf_batch *b) {
     // group problems by padded half grid (one kernel instantiation per group)
     std::vector<int> hps;
@@ -169,6 +201,7 @@ template <class T> int build_groups(rbf_batch *b) {
             std::memset(&d, 0, sizeof(d));
             fill_desc<T>(b->plans[q], &d);
             d.off = b->offsets[q];
+            g.points += b->offsets[q + 1] - b->offsets[q];
             // the XCD-range order of the leaf translation (m2l_sched 1) gives every problem a
             // multiple of 8 blocks, so problem-local block ids keep their XCD (id % 8)
             ds.push_back(d);
@@ -195,15 +228,25 @@ template <class T> int build_groups(rbf_batch *b) {
         }
         b->groups.push_back(g);
     }
-    return RBF_OK;
+    return assign_lanes(b);
 }
 
 template <class T> int launch_all(rbf_batch *b, const void *lam, void *u) {
+    // fork the lanes from the batch stream (also inside a graph capture, where the lanes join it)
+    if (!b->lanes.empty()) {
+        RBF_HIP(hipEventRecord(b->ev_fork, b->stream));
+        for (hipStream_t s : b->lanes) RBF_HIP(hipStreamWaitEvent(s, b->ev_fork, 0));
+    }
     for (auto &g : b->groups) {
         const int *bs[PH_COUNT];
         for (int k = 0; k < PH_COUNT; ++k) bs[k] = g.bstart[k];
+        hipStream_t s = g.lane ? b->lanes[g.lane - 1] : b->stream;
         RBF_TRY(launch_batch_group<T>(b->d, g.HP, b->kernel, (const Desc<T> *)g.descs, g.nprob, bs, g.nblocks,
-                                      g.p2m_sh, (const T *)lam, (T *)u, b->stream));
+                                      g.p2m_sh, (const T *)lam, (T *)u, s));
+    }
+    for (size_t l = 0; l < b->lanes.size(); ++l) {
+        RBF_HIP(hipEventRecord(b->lane_done[l], b->lanes[l]));
+        RBF_HIP(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
     }
     return RBF_OK;
 }
@@ -221,6 +264,12 @@ void batch_free(rbf_batch *b) {
     b->arena.release();
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (hipStream_t s : b->lanes) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : b->lane_done) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
