@@ -5,7 +5,8 @@
  * TEST INFRASTRUCTURE ONLY: built and called by the oracle package, never by the
  * product library.  Plain double-precision loops, IEEE arithmetic (no fast-math),
  * one OpenMP thread per block of targets.  Kernels: 0 = Gaussian exp(-r^2/(2 s^2)),
- * 1 = multiquadric sqrt(r^2 + c^2).  Points are row-major (n, d).
+ * 1 = multiquadric sqrt(r^2 + c^2), 2 = inverse multiquadric 1/sqrt(r^2 + c^2),
+ * 3 = Wendland (1 - e r)_+^3 (3 e r + 1) (section 7).  Points are row-major (n, d).
  */
 #include <math.h>
 #include <stdint.h>
@@ -29,7 +30,18 @@ void oracle_direct_sum(const double *src, int64_t n, int d, const double *lam,
                 double t = y[k] - x[k];
                 r2 += t * t;
             }
-            double phi = (kernel == 0) ? exp(-r2 * inv2s2) : sqrt(r2 + c2);
+            double phi;
+            if (kernel == 0) {
+                phi = exp(-r2 * inv2s2);
+            } else if (kernel == 1) {
+                phi = sqrt(r2 + c2);
+            } else if (kernel == 2) {
+                phi = 1.0 / sqrt(r2 + c2);
+            } else {
+                double er = shape * sqrt(r2);
+                double t = er < 1.0 ? 1.0 - er : 0.0;
+                phi = t * t * t * (3.0 * er + 1.0);
+            }
             acc += lam[j] * phi;
         }
         out[i] = acc;

@@ -2,7 +2,9 @@
 
 * Gaussian: the paper lists exp(-c r^2) (Tab. "Global functions", section 2.2); the
   workloads use the shape form exp(-r^2 / (2 s^2)), i.e. c = 1/(2 s^2).
-* Multiquadric: sqrt(r^2 + c^2) (same table).
+* Multiquadric: sqrt(r^2 + c^2) and inverse multiquadric 1/sqrt(r^2 + c^2) (same table).
+* Wendland's compactly supported function (1 - e r)_+^3 (3 e r + 1) (section 7, the third
+  kernel of the numerical examples, with the scaled support radius 1/e of its figure).
 * Fourier transform convention: eq. (5), Phi_hat(w) = int Phi(x) exp(-i w.x) dx, inverse
   with (2 pi)^-d (eq. 6).  Under this convention the Gaussian transforms to
   (2 pi s^2)^(d/2) exp(-s^2 |w|^2 / 2).  (The paper's Fourier-transform table prints the
@@ -12,7 +14,10 @@
 Pins: ``tests/test_oracle_rbf.py`` checks the transform by numerical integration
 (scipy.integrate.quad) and the kernels at closed-form points; the multiquadric
 evaluator and its second derivative reproduce the left column of the paper's
-Table "RMS errors" (tests/golden/tab_rms_left.txt).
+Table "RMS errors" (tests/golden/tab_rms_left.txt).  The inverse multiquadric is pinned
+to the paper's Fourier-transform table (a Bessel-K transform, by numerical integration) and
+Wendland's function to its expanded polynomial, its C^2 joint at the support radius and
+the positive definiteness of its matrices in three dimensions.
 """
 from __future__ import annotations
 
@@ -22,6 +27,8 @@ import numpy as np
 
 GAUSSIAN = "gaussian"
 MULTIQUADRIC = "multiquadric"
+INVERSE_MULTIQUADRIC = "inverse_multiquadric"
+WENDLAND = "wendland"
 
 
 def phi_of_r2(kernel: str, r2, shape: float):
@@ -31,12 +38,21 @@ def phi_of_r2(kernel: str, r2, shape: float):
         return np.exp(-r2 / (2.0 * shape * shape))
     if kernel == MULTIQUADRIC:
         return np.sqrt(r2 + shape * shape)
+    if kernel == INVERSE_MULTIQUADRIC:
+        return 1.0 / np.sqrt(r2 + shape * shape)
+    if kernel == WENDLAND:
+        er = shape * np.sqrt(r2)
+        return np.maximum(1.0 - er, 0.0) ** 3 * (3.0 * er + 1.0)
     raise ValueError(kernel)
 
 
 def phi0(kernel: str, shape: float) -> float:
     """Phi(0): the diagonal entry of the RBF matrix (eq. 54, A^diagonal)."""
-    return 1.0 if kernel == GAUSSIAN else float(shape)
+    if kernel == MULTIQUADRIC:
+        return float(shape)
+    if kernel == INVERSE_MULTIQUADRIC:
+        return 1.0 / float(shape)
+    return 1.0
 
 
 def gaussian_ft(xi, s: float, d: int):

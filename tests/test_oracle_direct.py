@@ -7,14 +7,27 @@ from oracle import direct
 from workloads import normal_weights, uniform_points
 
 
-def dense(x, kernel, shape):
-    r = cdist(x, x)
+def phi_of_r(r, kernel, shape):
+    """The kernels of the paper's tables as functions of the distance, each written in a form
+    other than the oracle's (Wendland's expanded polynomial, the inverse multiquadric by hypot)."""
     if kernel == "gaussian":
         return np.exp(-r ** 2 / (2 * shape ** 2))
-    return np.sqrt(r ** 2 + shape ** 2)
+    if kernel == "multiquadric":
+        return np.sqrt(r ** 2 + shape ** 2)
+    if kernel == "inverse_multiquadric":
+        return 1.0 / np.hypot(r, shape)
+    x = shape * r
+    return np.where(x < 1.0, 1.0 - 6.0 * x ** 2 + 8.0 * x ** 3 - 3.0 * x ** 4, 0.0)
 
 
-@pytest.mark.parametrize("kernel,shape", [("gaussian", 0.05), ("multiquadric", 0.02)])
+def dense(x, kernel, shape):
+    return phi_of_r(cdist(x, x), kernel, shape)
+
+
+KERNELS = [("gaussian", 0.05), ("multiquadric", 0.02), ("inverse_multiquadric", 0.03), ("wendland", 4.0)]
+
+
+@pytest.mark.parametrize("kernel,shape", KERNELS)
 @pytest.mark.parametrize("d", [2, 3, 5])
 def test_against_dense_matrix(kernel, shape, d):
     x = uniform_points(700, d, 11 + d)
@@ -61,16 +74,14 @@ def test_single_point_and_targets():
     assert np.array_equal(sub, full[50:60])
 
 
-@pytest.mark.parametrize("kernel,shape", [("gaussian", 0.05), ("multiquadric", 0.02)])
+@pytest.mark.parametrize("kernel,shape", KERNELS)
 def test_separate_targets_against_dense_matrix(kernel, shape):
     """Targets that are not sources (inside and outside the sources' box): the rectangular
     matrix Phi(|y_t - x_j|) from cdist, applied to lambda."""
     x = uniform_points(500, 3, 21)
     lam = normal_weights(500, 22)
     y = uniform_points(300, 3, 23) * 1.6 - 0.3
-    r = cdist(y, x)
-    a = np.exp(-r ** 2 / (2 * shape ** 2)) if kernel == "gaussian" else np.sqrt(r ** 2 + shape ** 2)
-    ref = a @ lam
+    ref = phi_of_r(cdist(y, x), kernel, shape) @ lam
     u = direct.direct_sum(x, lam, kernel, shape, targets=y)
     assert np.max(np.abs(u - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
     un = direct.direct_sum_numpy(x, lam, kernel, shape, targets=y)

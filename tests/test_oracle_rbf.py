@@ -19,6 +19,61 @@ def test_kernel_closed_form_points():
     assert rbf.phi0("multiquadric", 0.02) == 0.02
 
 
+def test_inverse_multiquadric_closed_form_points():
+    assert rbf.phi_of_r2("inverse_multiquadric", 0.0, 0.25) == 4.0
+    # 1/sqrt(r^2 + c^2) at r = sqrt(3) c is 1/(2c)
+    assert abs(rbf.phi_of_r2("inverse_multiquadric", 3.0 * 0.3 ** 2, 0.3) - 1.0 / 0.6) < 1e-14
+    assert rbf.phi0("inverse_multiquadric", 0.25) == 4.0
+    r2 = np.linspace(0.0, 4.0, 41)
+    prod = rbf.phi_of_r2("inverse_multiquadric", r2, 0.7) * rbf.phi_of_r2("multiquadric", r2, 0.7)
+    assert np.max(np.abs(prod - 1.0)) < 4e-16
+
+
+@pytest.mark.parametrize("xi", [0.25, 1.0, 3.0, 8.0])
+def test_inverse_multiquadric_transform_table(xi):
+    """The paper's Fourier-transform table (unitary convention) gives 1/sqrt(1 + r^2) in one
+    dimension the transform sqrt(2/pi) K_0(|xi|).  The cosine integral of the oracle's kernel
+    over the half line (QAWF) times 2 / sqrt(2 pi) must equal it; K_0 comes from scipy.special."""
+    from scipy.special import k0
+    half = integrate.quad(lambda x: float(rbf.phi_of_r2("inverse_multiquadric", x * x, 1.0)), 0.0, np.inf,
+                          weight="cos", wvar=xi, limlst=200)[0]
+    assert abs(2.0 * half / math.sqrt(2.0 * math.pi) - math.sqrt(2.0 / math.pi) * k0(xi)) < 1e-9
+
+
+def test_wendland_polynomial_and_support():
+    """(1 - e r)_+^3 (3 e r + 1) = 1 - 6 x^2 + 8 x^3 - 3 x^4 for x = e r < 1, and 0 beyond."""
+    e = 2.5
+    r = np.linspace(0.0, 0.6, 601)
+    x = e * r
+    val = rbf.phi_of_r2("wendland", r * r, e)
+    poly = np.where(x < 1.0, 1.0 - 6.0 * x ** 2 + 8.0 * x ** 3 - 3.0 * x ** 4, 0.0)
+    # the expanded form adds terms as large as 8 x^3: a few ulps of 8 is its own rounding
+    assert np.max(np.abs(val - poly)) < 4e-15
+    assert rbf.phi0("wendland", e) == 1.0
+    assert rbf.phi_of_r2("wendland", (1.0 / e) ** 2, e) == 0.0
+    assert np.all(val[x >= 1.0] == 0.0) and np.all(val[x < 1.0] > 0.0)
+
+
+def test_wendland_c2_joint():
+    """At the support radius the value and the first two derivatives vanish from the inside:
+    phi(1/e - h) = (e h)^3 (4 - 3 e h), so phi / h^3 tends to 4 e^3."""
+    e = 3.0
+    for h in [1e-2, 1e-3]:
+        r = 1.0 / e - h
+        v = float(rbf.phi_of_r2("wendland", r * r, e))
+        assert abs(v / h ** 3 - e ** 3 * (4.0 - 3.0 * e * h)) < 1e-6 * e ** 3
+
+
+def test_wendland_matrix_positive_definite_3d():
+    """Wendland's C^2 function of this form is positive definite in up to three dimensions:
+    its matrix on distinct points has a positive smallest eigenvalue."""
+    rng = np.random.default_rng(5)
+    x = rng.random((300, 3))
+    r2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    a = rbf.phi_of_r2("wendland", r2, 2.0)
+    assert np.min(np.linalg.eigvalsh(a)) > 0.0
+
+
 @pytest.mark.parametrize("xi", [0.0, 3.0, 17.5, 60.0])
 def test_gaussian_transform_by_quadrature(xi):
     """eq. (5) convention: int exp(-x^2/(2 s^2)) exp(-i xi x) dx, integrated numerically."""
