@@ -350,14 +350,16 @@ def run_c4(args):
 
 
 def run_c2mq(args):
-    """3-D mixed points (as the default workload), multiquadric c = 0.02: the plan holds one
-    leaf and the product is the exact sum through the tiled direct kernel (no band-limited
-    far field for this kernel in this build).  FP64 and FP32; the oracle checks 2048 targets."""
+    """3-D mixed points (as the default workload), multiquadric (or, with --mq-kernel, inverse
+    multiquadric) c = 0.02: the plan holds one leaf and the product is the exact sum through
+    the tiled direct kernel (no band-limited far field for these kernels in this build).  FP64
+    and FP32; the oracle checks 2048 targets."""
     import torch
 
     from paper_1606_07652_amd import FmmPlan
     from workloads import c2
 
+    kern = args.mq_kernel
     w = c2("multiquadric", n=args.n)
     n = w.points.shape[0]
     out = {}
@@ -368,12 +370,12 @@ def run_c2mq(args):
         from oracle import direct
         xs = w.points.astype(np.float64)
         t1 = time.perf_counter()
-        ref = direct.direct_sum(xs, w.lam.astype(np.float64), "multiquadric", w.shape, targets=xs[idx])
+        ref = direct.direct_sum(xs, w.lam.astype(np.float64), kern, w.shape, targets=xs[idx])
         tcpu = time.perf_counter() - t1
     for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
         X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
         lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
-        plan = FmmPlan(X, kernel="multiquadric", shape=w.shape, tol=1e-6)
+        plan = FmmPlan(X, kernel=kern, shape=w.shape, tol=1e-6)
         u = torch.empty_like(lam)
         plan.matvec(lam, u)
         torch.cuda.synchronize()
@@ -386,17 +388,99 @@ def run_c2mq(args):
         out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "pairs_per_s": float(n) * n / (ms * 1e-3)}
         if ref is not None:
             out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
-        log(f"[bench] multiquadric {name}: {ms:.1f} ms per product")
+        log(f"[bench] {kern} {name}: {ms:.1f} ms per product")
         plan.close()
-    result = {"metric": "RBF matvec points/s, multiquadric (exact sum)", "value": out["f64"]["points_per_s"],
+    result = {"metric": f"RBF matvec points/s, {kern.replace('_', ' ')} (exact sum)", "value": out["f64"]["points_per_s"],
               "unit": "points/s", "n_gpus": 1, "steps": max(2, args.steps // 4), "warmup": 1,
               "ms_per_step": out["f64"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-              "config": {"workload": "3d_mixed_uniform_blobs_multiquadric_c0.02", "n": n, "kernel": "multiquadric",
+              "config": {"workload": f"3d_mixed_uniform_blobs_{kern}_c0.02", "n": n, "kernel": kern,
                          "shape": w.shape}, "paths": out}
     if ref is not None:
         result["cpu_baseline"] = {"value": 2048 / tcpu, "unit": "points/s", "cores": direct.threads(),
                                   "kind": "oracle", "sample": f"2048 seeded targets x all {n} sources ({tcpu:.1f} s)"}
+    print(json.dumps(result), flush=True)
+
+
+# Wendland's function per near pair: the distance and the accumulation as for the Gaussian
+# (3d + 3), then e r (the square root counted as one flop, one multiply), 1 - e r and the clamp,
+# the cube (two multiplies), 3 e r + 1 (an fma, 2) and the product of the two factors: 9 flops.
+WENDLAND_PAIR_FLOPS = 9
+
+
+def run_wendland(args):
+    """Wendland's compactly supported function (1 - e r)_+^3 (3 e r + 1) on the default
+    workload's 2^20 mixed points, e = 25 (support radius 0.04): a uniform tree at the deepest
+    level whose cells hold the support radius, the adjacent cells as near field, no far field,
+    so the product is exact.  FP64 and FP32; value = points / time of one FP64 product; the
+    roofline is the near-field kernel's flops over its measured time; the oracle checks 2048
+    targets."""
+    import torch
+
+    from paper_1606_07652_amd import FmmPlan
+    from workloads import c2
+
+    w = c2("gaussian", n=args.n)
+    e = 25.0
+    n, d = w.points.shape
+    rng = np.random.default_rng(123)
+    idx = np.sort(rng.choice(n, 2048, replace=False))
+    ref = None
+    if not args.no_cpu:
+        from oracle import direct
+        xs = w.points.astype(np.float64)
+        t1 = time.perf_counter()
+        ref = direct.direct_sum(xs, w.lam.astype(np.float64), "wendland", e, targets=xs[idx])
+        tcpu = time.perf_counter() - t1
+    out = {}
+    for name, dt, peak in (("f64", torch.float64, FP64_VEC_TFLOPS), ("f32", torch.float32, FP32_VEC_TFLOPS)):
+        X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
+        lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
+        t0 = time.perf_counter()
+        plan = FmmPlan(X, kernel="wendland", shape=e, tol=1e-6)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        inf = plan.info()
+        u = torch.empty_like(lam)
+        for _ in range(args.warmup):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ph = plan.phase_times()
+        plan.set_profiling(False)
+        calls = max(ph.pop("calls"), 1)
+        phase_ms = {k: v / calls for k, v in ph.items()}
+        flops = float(inf["near_pairs"]) * (3 * d + 3 + WENDLAND_PAIR_FLOPS)
+        out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "plan_ms": plan_ms,
+                     "phase_ms": phase_ms, "level": inf["coarse_level"], "leaves": inf["nleaves"],
+                     "near_pairs": inf["near_pairs"], "far_field": inf["far_field"],
+                     "roofline": roofline_of("alu", flops, phase_ms["p2p"], peak)}
+        if ref is not None:
+            out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
+        log(f"[bench] wendland {name}: {ms:.2f} ms per product, level {inf['coarse_level']}, "
+            f"{inf['near_pairs']:.3e} near pairs")
+        plan.close()
+        del X, lam, u
+        torch.cuda.empty_cache()
+    f = out["f64"]
+    roof = dict(f["roofline"])
+    roof["traffic"] = None
+    result = {"metric": "RBF matvec points/s, Wendland (exact, near field only)", "value": f["points_per_s"],
+              "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+              "config": {"workload": "3d_mixed_uniform_blobs_wendland_e25", "n": n, "kernel": "wendland",
+                         "shape": e},
+              "roofline": roof, "paths": out}
+    if ref is not None:
+        result["cpu_baseline"] = {"value": len(idx) / tcpu, "unit": "points/s", "cores": direct.threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{len(idx)} seeded targets x all {n} sources ({tcpu:.1f} s)"}
     print(json.dumps(result), flush=True)
 
 
@@ -483,7 +567,7 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq", "eval"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq", "eval", "wendland"])
     ap.add_argument("--n-targets", type=int, default=1 << 20)
     ap.add_argument("--n-c4", type=int, default=1 << 18)
     ap.add_argument("--n-solve", type=int, default=1 << 21)
@@ -493,6 +577,8 @@ def main():
     ap.add_argument("--batched-solve", action="store_true",
                     help="with --workload batched: also run GMRES on all problems at once")
     ap.add_argument("--m2l-schedule", type=int, default=0)
+    ap.add_argument("--mq-kernel", default="multiquadric", choices=["multiquadric", "inverse_multiquadric"],
+                    help="with --workload c2mq: the kernel of the exact sum")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
@@ -509,6 +595,8 @@ def main():
         return run_c2mq(args)
     if args.workload == "eval":
         return run_eval(args)
+    if args.workload == "wendland":
+        return run_wendland(args)
 
     import torch
 

@@ -37,13 +37,20 @@ extern "C" {
 enum { RBF_OK = 0, RBF_ENOCONV = 1, RBF_EINVAL = -1, RBF_EUNSUPPORTED = -2, RBF_ENOMEM = -3,
        RBF_EHIP = -4, RBF_ESTATE = -5 };
 enum { RBF_F32 = 0, RBF_F64 = 1 };
-/* Kernels of the paper's table "Global functions" (section 2.2).  The Gaussian is used in
- * the shape form exp(-r^2 / (2 s^2)) (shape = s > 0); the multiquadric is sqrt(r^2 + c^2)
- * (shape = c > 0).  This build has no band-limited far field for the multiquadric: its plans
- * hold a single leaf and the product is the exact O(N^2) sum through the tiled direct kernel
- * (tol and the tree options are ignored).  Any plan of one leaf without a far field computes
- * its product that way. */
-enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1 };
+/* Kernels of the paper's table "Global functions" (section 2.2) and of its numerical examples
+ * (section 7).  The Gaussian is used in the shape form exp(-r^2 / (2 s^2)) (shape = s > 0);
+ * the multiquadric is sqrt(r^2 + c^2) and the inverse multiquadric 1/sqrt(r^2 + c^2)
+ * (shape = c > 0); Wendland's compactly supported function is (1 - e r)_+^3 (3 e r + 1)
+ * (shape = e > 0, support radius 1/e).
+ *   Only the Gaussian has a band-limited far field in this build.  Multiquadric and inverse
+ *   multiquadric plans hold a single leaf and the product is the exact O(N^2) sum through the
+ *   tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
+ *   support radius wide, with the adjacent cells as the near field and no far field: every
+ *   pair inside the support is a near pair, so the product is exact (a single leaf when no
+ *   such level below the root exists).  For these three kernels tol and the tree options are
+ *   ignored.  Any plan of one leaf without a far field computes its product with the tiled
+ *   direct kernel. */
+enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
 
 /* Optional planning overrides; zero or negative fields mean "choose automatically".

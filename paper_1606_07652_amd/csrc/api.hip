@@ -53,10 +53,11 @@ double band_t(double tol) {
     return hi;
 }
 
-// Multiquadric: this build has no band-limited far field for it (a kernel that does not
-// decay cannot be pruned, and one frequency grid for all levels would have to resolve the
-// finest near-zone width over the whole domain).  Every pair is a near pair of a single
-// leaf: the product is the exact sum, evaluated by the tiled near-field kernel.
+// Multiquadric and inverse multiquadric: this build has no band-limited far field for them
+// (a kernel that grows or decays like a power of r cannot be pruned, and one frequency grid for
+// all levels would have to resolve the finest near-zone width over the whole domain).  Every
+// pair is a near pair of a single leaf: the product is the exact sum, evaluated by the tiled
+// direct kernel.
 void multiquadric_params(rbf_plan *p) {
     p->sigma = 1.0;
     p->rcut = p->rfar = p->ext;
@@ -75,9 +76,32 @@ void multiquadric_params(rbf_plan *p) {
     p->L = 2.0 * M_PI / (2.0 * p->sigma / (p->mn - 1));
 }
 
+// Wendland's function vanishes from r = 1/e on.  In a uniform tree whose cells are at least
+// that wide, two points closer than 1/e lie in the same or adjacent cells, so the adjacent
+// cells as near field leave an empty far field and the product is exact.  The deepest such
+// level does the least work; without one below the root the plan is a single leaf.
+void wendland_params(rbf_plan *p) {
+    multiquadric_params(p);
+    const double rho = 1.0 / p->shape;
+    int lstar = 0;
+    while (lstar + 1 <= 18 / p->d && p->ext / std::ldexp(1.0, lstar + 1) >= rho) ++lstar;
+    p->rcut = rho;
+    if (lstar >= 1) {
+        p->lc = lstar;
+        p->r = 1;
+        p->rfar = std::min(2.0 * p->ext / std::ldexp(1.0, lstar), p->ext);
+        p->max_level = lstar;
+        p->min_level = lstar;
+    }
+}
+
 int choose_params(rbf_plan *p, const rbf_opts *o) {
-    if (p->kernel == RBF_MULTIQUADRIC) {
+    if (p->kernel == RBF_MULTIQUADRIC || p->kernel == RBF_INVERSE_MULTIQUADRIC) {
         multiquadric_params(p);
+        return RBF_OK;
+    }
+    if (p->kernel == RBF_WENDLAND) {
+        wendland_params(p);
         return RBF_OK;
     }
     const double s = p->shape, tol = p->tol;
@@ -166,7 +190,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (d < 1 || d > kMaxDim) { set_error("rbf_fmm_plan: d=%d out of range [1,5]", d); return RBF_EINVAL; }
     if (d != 2 && d != 3 && d != 5) { set_error("rbf_fmm_plan: d=%d is not compiled (2, 3, 5 are)", d); return RBF_EUNSUPPORTED; }
     if (dtype != RBF_F32 && dtype != RBF_F64) { set_error("rbf_fmm_plan: bad dtype %d", dtype); return RBF_EINVAL; }
-    if (kernel != RBF_GAUSSIAN && kernel != RBF_MULTIQUADRIC) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
+    if (kernel < RBF_GAUSSIAN || kernel > RBF_WENDLAND) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
     if (!(shape > 0) || !std::isfinite(shape)) { set_error("rbf_fmm_plan: shape must be positive"); return RBF_EINVAL; }
     if (!(tol > 0 && tol < 1)) { set_error("rbf_fmm_plan: tol must lie in (0, 1)"); return RBF_EINVAL; }
     rbf_plan *p = new (std::nothrow) rbf_plan();

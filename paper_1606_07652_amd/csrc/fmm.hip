@@ -123,13 +123,27 @@ __device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
 }
 
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32 (in
-// FP64 the kernels call exp2_tab64 with its LDS table).  Multiquadric sqrt(r^2 + c^2): coef = c^2.
+// FP64 the kernels call exp2_tab64 with its LDS table).  Multiquadric sqrt(r^2 + c^2) and inverse
+// multiquadric 1/sqrt(r^2 + c^2): coef = c^2.  Wendland's (1 - e r)_+^3 (3 e r + 1) (section 7):
+// coef = e, zero from r = 1/e on.
 template <> struct KFun<float> {
     static __device__ __forceinline__ float gauss(float r2, float coef) { return __builtin_amdgcn_exp2f(r2 * coef); }
     static __device__ __forceinline__ float mq(float r2, float c2) { return __builtin_amdgcn_sqrtf(r2 + c2); }
+    static __device__ __forceinline__ float imq(float r2, float c2) { return __builtin_amdgcn_rsqf(r2 + c2); }
+    static __device__ __forceinline__ float wendland(float r2, float e) {
+        const float er = e * __builtin_amdgcn_sqrtf(r2);
+        const float t = fmaxf(1.0f - er, 0.0f);
+        return t * t * t * fmaf(3.0f, er, 1.0f);
+    }
 };
 template <> struct KFun<double> {
     static __device__ __forceinline__ double mq(double r2, double c2) { return sqrt(r2 + c2); }
+    static __device__ __forceinline__ double imq(double r2, double c2) { return 1.0 / sqrt(r2 + c2); }
+    static __device__ __forceinline__ double wendland(double r2, double e) {
+        const double er = e * sqrt(r2);
+        const double t = fmax(1.0 - er, 0.0);
+        return t * t * t * fma(3.0, er, 1.0);
+    }
 };
 
 template <int D> struct Pad { static constexpr int v = (D + 2) & ~1; };
@@ -191,6 +205,15 @@ template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 // and tab the 64 table entries in LDS); other kernels and FP32 through KFun.
 template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
 
+// Phi at squared distance r2 for every kernel of the near field and the direct sum.
+template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, const double *tab) {
+    if constexpr (kTabExp<T, KER>) return exp2_tab64(r2 * coef, tab);
+    else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
+    else if constexpr (KER == RBF_MULTIQUADRIC) return KFun<T>::mq(r2, coef);
+    else if constexpr (KER == RBF_INVERSE_MULTIQUADRIC) return KFun<T>::imq(r2, coef);
+    else return KFun<T>::wendland(r2, coef);
+}
+
 template <class T, int D, int KER>
 __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, const double *tab) {
     T r2 = 0;
@@ -199,9 +222,7 @@ __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, 
         const T t = y[k] - x[k];
         r2 = fma(t, t, r2);
     }
-    if constexpr (kTabExp<T, KER>) return exp2_tab64(r2 * coef, tab);
-    else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
-    else return KFun<T>::mq(r2, coef);
+    return kphi<T, KER>(r2, coef, tab);
 }
 
 template <class T, int D, int KER>
@@ -346,11 +367,7 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
                 T t = y[k] - sdat[e * DP + k];
                 r2 += t * t;
             }
-            T ph;
-            if constexpr (kTabExp<T, KER>) ph = exp2_tab64(r2 * coef, tab);
-            else if constexpr (KER == RBF_GAUSSIAN) ph = KFun<T>::gauss(r2, coef);
-            else ph = KFun<T>::mq(r2, coef);
-            acc += sdat[e * DP + D] * ph;
+            acc += sdat[e * DP + D] * kphi<T, KER>(r2, coef, tab);
         }
     }
     if (act) u[d.off + d.perm[ti]] = acc;
@@ -1045,12 +1062,20 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
     switch (phase) {
         case PH_GATHER: k_gather<T><<<g, kThreads, 0, s>>>(w); break;
         case PH_P2P:
-            if (kernel == RBF_GAUSSIAN) k_p2p<T, D, RBF_GAUSSIAN><<<g, kWave, 0, s>>>(w);
-            else k_p2p<T, D, RBF_MULTIQUADRIC><<<g, kWave, 0, s>>>(w);
+            switch (kernel) {
+                case RBF_GAUSSIAN: k_p2p<T, D, RBF_GAUSSIAN><<<g, kWave, 0, s>>>(w); break;
+                case RBF_MULTIQUADRIC: k_p2p<T, D, RBF_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
+                case RBF_INVERSE_MULTIQUADRIC: k_p2p<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
+                default: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
+            }
             break;
         case PH_DIRECT:
-            if (kernel == RBF_GAUSSIAN) k_direct<T, D, RBF_GAUSSIAN><<<g, kThreads, 0, s>>>(w);
-            else k_direct<T, D, RBF_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w);
+            switch (kernel) {
+                case RBF_GAUSSIAN: k_direct<T, D, RBF_GAUSSIAN><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_MULTIQUADRIC: k_direct<T, D, RBF_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_INVERSE_MULTIQUADRIC: k_direct<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
+                default: k_direct<T, D, RBF_WENDLAND><<<g, kThreads, 0, s>>>(w); break;
+            }
             break;
         case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kThreads, 0, s>>>(w); break;
         case PH_P2M: k_p2m<T, D, HMAX><<<g, (kExpMfma<T> || D > 2) ? kThreads : kWave, shmem, s>>>(w); break;
@@ -1269,6 +1294,8 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->wc1 = p->wc1;
     if (p->kernel == RBF_GAUSSIAN)
         d->coef = (T)(-1.4426950408889634 / (2.0 * p->shape * p->shape));
+    else if (p->kernel == RBF_WENDLAND)
+        d->coef = (T)p->shape;
     else
         d->coef = (T)(p->shape * p->shape);
     d->lam_s = (T *)p->lam_s;
