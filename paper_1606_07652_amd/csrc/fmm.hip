@@ -136,11 +136,28 @@ template <> struct KFun<float> {
         return t * t * t * fmaf(3.0f, er, 1.0f);
     }
 };
+// Square root of a squared distance (0 <= a, far above the subnormal range) without the
+// library's range scaling: Goldschmidt's iteration from the hardware reciprocal square root,
+// y ~ 1/sqrt(a), g = a y, h = y/2, one multiplicative step and two additive corrections
+// g += (a - g^2) h; a = 0 gives 0.
+__device__ __forceinline__ double sqrt_dist2(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double e = fma(-g, g, a);
+    g = fma(e, h, g);
+    e = fma(-g, g, a);
+    g = fma(e, h, g);
+    return a > 0.0 ? g : 0.0;
+}
+
 template <> struct KFun<double> {
     static __device__ __forceinline__ double mq(double r2, double c2) { return sqrt(r2 + c2); }
     static __device__ __forceinline__ double imq(double r2, double c2) { return 1.0 / sqrt(r2 + c2); }
     static __device__ __forceinline__ double wendland(double r2, double e) {
-        const double er = e * sqrt(r2);
+        const double er = e * sqrt_dist2(r2);
         const double t = fmax(1.0 - er, 0.0);
         return t * t * t * fma(3.0, er, 1.0);
     }
@@ -225,8 +242,44 @@ __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, 
     return kphi<T, KER>(r2, coef, tab);
 }
 
+template <class T, int D>
+__device__ __forceinline__ T dist2(const T (&y)[D], const T (&x)[D]) {
+    T r2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T t = y[k] - x[k];
+        r2 = fma(t, t, r2);
+    }
+    return r2;
+}
+
+// One step of S sources for the wave's targets.  Wendland's function vanishes from r = 1/e on
+// (cut2 = 1/e^2): when no source of the step lies inside the support of any target of the
+// wave, the step adds only zeros and is skipped (a wave-uniform branch).
+template <class T, int D, int KER, int S>
+__device__ __forceinline__ T p2p_step(const T (&y)[D], const T (&x)[S][D], const T (&w)[S], T coef, T cut2,
+                                      const double *tab, T acc) {
+    if constexpr (KER == RBF_WENDLAND) {
+        T r2[S];
+#pragma unroll
+        for (int v = 0; v < S; ++v) r2[v] = dist2<T, D>(y, x[v]);
+        T mn = r2[0];
+#pragma unroll
+        for (int v = 1; v < S; ++v) mn = min(mn, r2[v]);
+        if (__any(mn < cut2)) {
+#pragma unroll
+            for (int v = 0; v < S; ++v) acc = fma(w[v], KFun<T>::wendland(r2[v], coef), acc);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
+    }
+    return acc;
+}
+
 template <class T, int D, int KER>
-__device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, const double *tab) {
+__device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, T cut2,
+                                       const double *tab) {
     constexpr int S = kP2pStep<T>;
     const int64_t n = d.n;
     const cptr<int> rng = uconst((const int *)d.src_rng);
@@ -243,8 +296,7 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
                 for (int v = 0; v < S; ++v) x[v][k] = X[k * n + j + v];
 #pragma unroll
             for (int v = 0; v < S; ++v) w[v] = L[j + v];
-#pragma unroll
-            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
+            acc = p2p_step<T, D, KER, S>(y, x, w, coef, cut2, tab, acc);
         }
         if (j < j1) {
             T x[S][D], w[S];
@@ -255,8 +307,7 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
                 for (int k = 0; k < D; ++k) x[v][k] = X[k * n + jj];
                 w[v] = j + v < j1 ? L[jj] : T(0);
             }
-#pragma unroll
-            for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
+            acc = p2p_step<T, D, KER, S>(y, x, w, coef, cut2, tab, acc);
         }
     }
     return acc;
@@ -266,7 +317,8 @@ __device__ __forceinline__ T p2p_whole(DescC<T> &d, const T (&y)[D], int r0, int
 // per lane per step, a source past the range end repeats the last one with weight 0.  The
 // result is the group sums added over the groups (in every lane of the target).
 template <class T, int D, int KER, int G>
-__device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, const double *tab) {
+__device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int r1, T coef, T cut2,
+                                       const double *tab) {
     constexpr int TP = kWave / G, U = 2;
     const int64_t n = d.n;
     const cptr<int> rng = uconst((const int *)d.src_rng);
@@ -286,8 +338,7 @@ __device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int
                 for (int k = 0; k < D; ++k) x[v][k] = X[k * n + jj];
                 w[v] = j < j1 ? L[jj] : T(0);
             }
-#pragma unroll
-            for (int v = 0; v < U; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
+            acc = p2p_step<T, D, KER, U>(y, x, w, coef, cut2, tab, acc);
         }
     }
 #pragma unroll
@@ -308,9 +359,10 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
     const int TP = kWave >> gl;
     const int ti = t0 + (int)threadIdx.x % TP;
     const bool act = ti < t1;
+    // a lane without a target takes the chunk's first one (its sum is not written)
     T y[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) y[k] = act ? d.xs[k * n + ti] : T(0);
+    for (int k = 0; k < D; ++k) y[k] = d.xs[k * n + (act ? ti : t0)];
     const int r0 = sp[a], r1 = sp[a + 1];
     __shared__ double tab[kWave];   // 2^(j/64), FP64 Gaussian only
     T coef = d.coef;
@@ -319,12 +371,13 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
         __syncthreads();
         coef *= 64;   // exact
     }
+    const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : T(0);
     T acc;
     switch (gl) {
-        case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1, coef, tab); break;
-        case 1: acc = p2p_split<T, D, KER, 2>(d, y, r0, r1, coef, tab); break;
-        case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1, coef, tab); break;
-        default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1, coef, tab); break;
+        case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1, coef, cut2, tab); break;
+        case 1: acc = p2p_split<T, D, KER, 2>(d, y, r0, r1, coef, cut2, tab); break;
+        case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1, coef, cut2, tab); break;
+        default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1, coef, cut2, tab); break;
     }
     if (act && (int)threadIdx.x < TP) {
         if (d.far) d.u_s[ti] = acc;
