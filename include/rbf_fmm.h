@@ -291,7 +291,10 @@ enum { RBF_MLP_BF16 = 0, RBF_MLP_F32 = 1 };
 
 /* Build (or rebuild) the block-Jacobi inverses with regularisation reg >= 0 (reg < 0: the
  * default, reg = 1e-2 Phi(0)).  Synchronous.  RBF_EINVAL if a block is numerically
- * singular at this reg (a pivot <= 0). */
+ * singular at this reg (a pivot <= 0).  Kernels with positive definite blocks only: the
+ * Gaussian, the inverse multiquadric and Wendland's function; RBF_EUNSUPPORTED for the
+ * multiquadric.  The learned preconditioner, its features, pairs and harvest are
+ * Gaussian-only (RBF_EUNSUPPORTED otherwise). */
 int rbf_pc_block_jacobi(rbf_plan *plan, double reg);
 /* Build the block inverses that form the learned map's features y (and those of
  * rbf_pc_pairs / rbf_pc_harvest) with their own regularisation (reg < 0: the default,

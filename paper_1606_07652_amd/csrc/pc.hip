@@ -32,9 +32,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// The kernels whose block matrices are positive definite: the Gaussian exp(-r^2/(2 s^2)), the
+// inverse multiquadric 1/sqrt(r^2 + c^2) and Wendland's (1 - e r)_+^3 (3 e r + 1), in FP64.
+__device__ double block_phi(int kernel, double r2, double shape) {
+    if (kernel == RBF_GAUSSIAN) return exp(-r2 / (2.0 * shape * shape));
+    if (kernel == RBF_INVERSE_MULTIQUADRIC) return 1.0 / sqrt(r2 + shape * shape);
+    const double er = shape * sqrt(r2);
+    const double t = fmax(1.0 - er, 0.0);
+    return t * t * t * (3.0 * er + 1.0);
+}
+
 template <class T>
-__global__ void __launch_bounds__(BS) k_bj_setup(const T *__restrict__ xs, int64_t n, int d, double coef, double reg,
-                                                 double *__restrict__ inv, int *__restrict__ flag) {
+__global__ void __launch_bounds__(BS) k_bj_setup(const T *__restrict__ xs, int64_t n, int d, int kernel, double shape,
+                                                 double reg, double *__restrict__ inv, int *__restrict__ flag) {
     __shared__ double L[BS * BS];
     __shared__ double px[kMaxDim][BS];
     const int i = threadIdx.x;
@@ -50,7 +60,7 @@ __global__ void __launch_bounds__(BS) k_bj_setup(const T *__restrict__ xs, int64
                 const double t = px[k][i] - px[k][j];
                 r2 += t * t;
             }
-            a = exp(coef * r2) + (i == j ? reg : 0.0);
+            a = block_phi(kernel, r2, shape) + (i == j ? reg : 0.0);
         } else {
             a = i == j ? 1.0 : 0.0;
         }
@@ -204,14 +214,13 @@ int ensure_pc_buffers(rbf_plan *p) {
 // factorise every block of (A_bb + reg I) into inv (nblk 64 x 64 doubles)
 int factor_blocks(rbf_plan *p, double reg, double *inv) {
     hipStream_t s = p->stream;
-    const double coef = -1.0 / (2.0 * p->shape * p->shape);
     RBF_HIP(hipMemsetAsync(p->pc_flag, 0, sizeof(int), s));
     if (p->dtype == RBF_F32)
-        k_bj_setup<float><<<(unsigned)p->nblk, BS, 0, s>>>((const float *)p->xs, p->n, p->d, coef, reg, inv,
-                                                            p->pc_flag);
+        k_bj_setup<float><<<(unsigned)p->nblk, BS, 0, s>>>((const float *)p->xs, p->n, p->d, p->kernel, p->shape,
+                                                            reg, inv, p->pc_flag);
     else
-        k_bj_setup<double><<<(unsigned)p->nblk, BS, 0, s>>>((const double *)p->xs, p->n, p->d, coef, reg, inv,
-                                                             p->pc_flag);
+        k_bj_setup<double><<<(unsigned)p->nblk, BS, 0, s>>>((const double *)p->xs, p->n, p->d, p->kernel, p->shape,
+                                                             reg, inv, p->pc_flag);
     RBF_HIP(hipGetLastError());
     int flag = 0;
     RBF_HIP(hipMemcpyAsync(&flag, p->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -223,19 +232,33 @@ int factor_blocks(rbf_plan *p, double reg, double *inv) {
     return RBF_OK;
 }
 
-int check_kernel(const rbf_plan *p) {
-    if (p->kernel != RBF_GAUSSIAN) {
-        set_error("preconditioners: only the Gaussian kernel is supported");
+// Block-Jacobi needs positive definite blocks (not the multiquadric's); the network's features
+// and training pairs are those of the Gaussian.
+int check_bj_kernel(const rbf_plan *p) {
+    if (p->kernel == RBF_MULTIQUADRIC) {
+        set_error("block-Jacobi: the multiquadric's blocks are not positive definite (Gaussian, inverse "
+                  "multiquadric and Wendland kernels are supported)");
         return RBF_EUNSUPPORTED;
     }
     return RBF_OK;
 }
 
+int check_learned_kernel(const rbf_plan *p) {
+    if (p->kernel != RBF_GAUSSIAN) {
+        set_error("learned preconditioner: only the Gaussian kernel is supported");
+        return RBF_EUNSUPPORTED;
+    }
+    return RBF_OK;
+}
+
+// Phi(0), the scale of the default regularisations
+double phi_zero(const rbf_plan *p) { return p->kernel == RBF_INVERSE_MULTIQUADRIC ? 1.0 / p->shape : 1.0; }
+
 int build_lp(rbf_plan *p, double reg);
 
 // block-Jacobi inverses at reg
 int build_bj(rbf_plan *p, double reg) {
-    RBF_TRY(check_kernel(p));
+    RBF_TRY(check_bj_kernel(p));
     RBF_TRY(ensure_pc_buffers(p));
     if (!p->bj_inv) RBF_TRY(p->pc_arena.alloc((void **)&p->bj_inv, sizeof(double) * p->nblk * BS * BS));
     // feature inverses that share this storage keep their reg: they move to their own
@@ -250,7 +273,7 @@ int build_bj(rbf_plan *p, double reg) {
 
 // feature inverses of the learned map at reg (shares the block-Jacobi storage when the regs agree)
 int build_lp(rbf_plan *p, double reg) {
-    RBF_TRY(check_kernel(p));
+    RBF_TRY(check_learned_kernel(p));
     RBF_TRY(ensure_pc_buffers(p));
     p->lp_reg = -1.0;
     p->lp_inv = nullptr;
@@ -294,7 +317,7 @@ int pc_ready(rbf_plan *p, int kind) {
         set_error("unknown preconditioner %d", kind);
         return RBF_EINVAL;
     }
-    if (p->bj_reg < 0) RBF_TRY(build_bj(p, kDefaultBjReg));
+    if (p->bj_reg < 0) RBF_TRY(build_bj(p, kDefaultBjReg * phi_zero(p)));
     if (kind == RBF_PC_LEARNED) {
         if (!p->mlp) {
             set_error("learned preconditioner: no network attached (rbf_pc_set_learned)");
@@ -333,7 +356,7 @@ extern "C" int rbf_pc_block_jacobi(rbf_plan *plan, double reg) {
     if (!plan) { set_error("rbf_pc_block_jacobi: null plan"); return RBF_EINVAL; }
     RBF_TRY(reject_eval_plan(plan, "rbf_pc_block_jacobi"));
     if (!std::isfinite(reg)) { set_error("rbf_pc_block_jacobi: reg must be finite"); return RBF_EINVAL; }
-    return build_bj(plan, reg < 0 ? kDefaultBjReg : reg);
+    return build_bj(plan, reg < 0 ? kDefaultBjReg * phi_zero(plan) : reg);
 }
 
 extern "C" int rbf_pc_learned_features(rbf_plan *plan, double reg) {
