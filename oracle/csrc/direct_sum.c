@@ -6,7 +6,9 @@
  * product library.  Plain double-precision loops, IEEE arithmetic (no fast-math),
  * one OpenMP thread per block of targets.  Kernels: 0 = Gaussian exp(-r^2/(2 s^2)),
  * 1 = multiquadric sqrt(r^2 + c^2), 2 = inverse multiquadric 1/sqrt(r^2 + c^2),
- * 3 = Wendland (1 - e r)_+^3 (3 e r + 1) (section 7).  Points are row-major (n, d).
+ * 3 = Wendland (1 - e r)_+^3 (3 e r + 1) (section 7), 4 = thin-plate spline r^2 log r
+ * (0 at r = 0), 5 = r^5 (the Fourier-transform table; shape ignored).  Points are row-major
+ * (n, d).
  */
 #include <math.h>
 #include <stdint.h>
@@ -37,10 +39,14 @@ void oracle_direct_sum(const double *src, int64_t n, int d, const double *lam,
                 phi = sqrt(r2 + c2);
             } else if (kernel == 2) {
                 phi = 1.0 / sqrt(r2 + c2);
-            } else {
+            } else if (kernel == 3) {
                 double er = shape * sqrt(r2);
                 double t = er < 1.0 ? 1.0 - er : 0.0;
                 phi = t * t * t * (3.0 * er + 1.0);
+            } else if (kernel == 4) {
+                phi = r2 > 0.0 ? 0.5 * r2 * log(r2) : 0.0;
+            } else {
+                phi = r2 * r2 * sqrt(r2);
             }
             acc += lam[j] * phi;
         }

@@ -17,7 +17,7 @@ import subprocess
 
 import numpy as np
 
-from .rbf import GAUSSIAN, INVERSE_MULTIQUADRIC, MULTIQUADRIC, WENDLAND, phi_of_r2
+from .rbf import GAUSSIAN, INVERSE_MULTIQUADRIC, MULTIQUADRIC, R5, THIN_PLATE, WENDLAND, phi_of_r2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "csrc", "direct_sum.c")
@@ -60,7 +60,7 @@ def direct_sum(points, lam, kernel: str, shape: float, targets=None) -> np.ndarr
     tgt = src if targets is None else np.ascontiguousarray(targets, dtype=np.float64)
     nt = tgt.shape[0]
     out = np.zeros(nt)
-    kid = {GAUSSIAN: 0, MULTIQUADRIC: 1, INVERSE_MULTIQUADRIC: 2, WENDLAND: 3}[kernel]
+    kid = {GAUSSIAN: 0, MULTIQUADRIC: 1, INVERSE_MULTIQUADRIC: 2, WENDLAND: 3, THIN_PLATE: 4, R5: 5}[kernel]
     _load().oracle_direct_sum(src.ctypes.data, n, d, lam64.ctypes.data, tgt.ctypes.data, nt,
                               kid, float(shape), out.ctypes.data)
     return out

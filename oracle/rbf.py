@@ -5,6 +5,8 @@
 * Multiquadric: sqrt(r^2 + c^2) and inverse multiquadric 1/sqrt(r^2 + c^2) (same table).
 * Wendland's compactly supported function (1 - e r)_+^3 (3 e r + 1) (section 7, the third
   kernel of the numerical examples, with the scaled support radius 1/e of its figure).
+* The piecewise smooth kernels of the Fourier-transform table: the thin-plate spline r^2 log r
+  (0 at r = 0) and r^5.  Both are scale-free (the shape argument is ignored).
 * Fourier transform convention: eq. (5), Phi_hat(w) = int Phi(x) exp(-i w.x) dx, inverse
   with (2 pi)^-d (eq. 6).  Under this convention the Gaussian transforms to
   (2 pi s^2)^(d/2) exp(-s^2 |w|^2 / 2).  (The paper's Fourier-transform table prints the
@@ -17,7 +19,8 @@ evaluator and its second derivative reproduce the left column of the paper's
 Table "RMS errors" (tests/golden/tab_rms_left.txt).  The inverse multiquadric is pinned
 to the paper's Fourier-transform table (a Bessel-K transform, by numerical integration) and
 Wendland's function to its expanded polynomial, its C^2 joint at the support radius and
-the positive definiteness of its matrices in three dimensions.
+the positive definiteness of its matrices in three dimensions.  The thin-plate spline and r^5
+are pinned by finite-difference Laplacians (4 log r + 4 in 2-D, 30 r^3 in 3-D).
 """
 from __future__ import annotations
 
@@ -29,6 +32,8 @@ GAUSSIAN = "gaussian"
 MULTIQUADRIC = "multiquadric"
 INVERSE_MULTIQUADRIC = "inverse_multiquadric"
 WENDLAND = "wendland"
+THIN_PLATE = "thin_plate"
+R5 = "r5"
 
 
 def phi_of_r2(kernel: str, r2, shape: float):
@@ -43,6 +48,12 @@ def phi_of_r2(kernel: str, r2, shape: float):
     if kernel == WENDLAND:
         er = shape * np.sqrt(r2)
         return np.maximum(1.0 - er, 0.0) ** 3 * (3.0 * er + 1.0)
+    if kernel == THIN_PLATE:
+        # r^2 log r = r^2 log(r^2) / 2, continued by 0 at r = 0
+        safe = np.where(r2 > 0.0, r2, 1.0)
+        return np.where(r2 > 0.0, 0.5 * r2 * np.log(safe), 0.0)
+    if kernel == R5:
+        return r2 * r2 * np.sqrt(r2)
     raise ValueError(kernel)
 
 
@@ -52,6 +63,8 @@ def phi0(kernel: str, shape: float) -> float:
         return float(shape)
     if kernel == INVERSE_MULTIQUADRIC:
         return 1.0 / float(shape)
+    if kernel in (THIN_PLATE, R5):
+        return 0.0
     return 1.0
 
 

@@ -16,6 +16,10 @@ def phi_of_r(r, kernel, shape):
         return np.sqrt(r ** 2 + shape ** 2)
     if kernel == "inverse_multiquadric":
         return 1.0 / np.hypot(r, shape)
+    if kernel == "thin_plate":
+        return np.where(r > 0.0, r * r * np.log(np.where(r > 0.0, r, 1.0)), 0.0)
+    if kernel == "r5":
+        return r ** 5
     x = shape * r
     return np.where(x < 1.0, 1.0 - 6.0 * x ** 2 + 8.0 * x ** 3 - 3.0 * x ** 4, 0.0)
 
@@ -24,7 +28,8 @@ def dense(x, kernel, shape):
     return phi_of_r(cdist(x, x), kernel, shape)
 
 
-KERNELS = [("gaussian", 0.05), ("multiquadric", 0.02), ("inverse_multiquadric", 0.03), ("wendland", 4.0)]
+KERNELS = [("gaussian", 0.05), ("multiquadric", 0.02), ("inverse_multiquadric", 0.03), ("wendland", 4.0),
+           ("thin_plate", 1.0), ("r5", 1.0)]
 
 
 @pytest.mark.parametrize("kernel,shape", KERNELS)

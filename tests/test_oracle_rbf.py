@@ -74,6 +74,44 @@ def test_wendland_matrix_positive_definite_3d():
     assert np.min(np.linalg.eigvalsh(a)) > 0.0
 
 
+def laplacian_fd(f, p, h):
+    """Second-order central-difference Laplacian of f at the point p."""
+    p = np.asarray(p, dtype=np.float64)
+    acc = 0.0
+    for k in range(p.shape[0]):
+        e = np.zeros_like(p)
+        e[k] = h
+        acc += (f(p + e) - 2.0 * f(p) + f(p - e)) / (h * h)
+    return acc
+
+
+@pytest.mark.parametrize("p", [[0.3, 0.4], [1.5, -0.2], [0.05, 0.02]])
+def test_thin_plate_laplacian_2d(p):
+    """r^2 log r in the plane has the Laplacian 4 log r + 4 away from the origin (it is the
+    biharmonic fundamental solution up to a constant)."""
+    f = lambda q: float(rbf.phi_of_r2("thin_plate", float(np.dot(q, q)), 1.0))
+    r = math.hypot(*p)
+    h = 1e-4 * r
+    assert abs(laplacian_fd(f, p, h) - (4.0 * math.log(r) + 4.0)) < 1e-4 * (1.0 + abs(4.0 * math.log(r)))
+
+
+@pytest.mark.parametrize("p", [[0.3, 0.4, 0.1], [1.0, -2.0, 0.5]])
+def test_r5_laplacian_3d(p):
+    """Delta r^k = k (k + d - 2) r^(k-2): r^5 in 3-D has the Laplacian 30 r^3."""
+    f = lambda q: float(rbf.phi_of_r2("r5", float(np.dot(q, q)), 1.0))
+    r = math.sqrt(sum(t * t for t in p))
+    h = 1e-4 * r
+    assert abs(laplacian_fd(f, p, h) - 30.0 * r ** 3) < 1e-5 * 30.0 * r ** 3 + 1e-9
+
+
+def test_piecewise_smooth_closed_form_points():
+    assert rbf.phi_of_r2("thin_plate", 0.0, 1.0) == 0.0
+    assert rbf.phi_of_r2("thin_plate", 1.0, 1.0) == 0.0
+    assert abs(rbf.phi_of_r2("thin_plate", math.e ** 2, 1.0) - math.e ** 2) < 1e-14
+    assert rbf.phi_of_r2("r5", 4.0, 1.0) == 32.0
+    assert rbf.phi0("thin_plate", 1.0) == 0.0 and rbf.phi0("r5", 1.0) == 0.0
+
+
 @pytest.mark.parametrize("xi", [0.0, 3.0, 17.5, 60.0])
 def test_gaussian_transform_by_quadrature(xi):
     """eq. (5) convention: int exp(-x^2/(2 s^2)) exp(-i xi x) dx, integrated numerically."""
