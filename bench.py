@@ -586,7 +586,8 @@ def main():
     ap.add_argument("--batched-solve", action="store_true",
                     help="with --workload batched: also run GMRES on all problems at once")
     ap.add_argument("--m2l-schedule", type=int, default=0)
-    ap.add_argument("--mq-kernel", default="multiquadric", choices=["multiquadric", "inverse_multiquadric"],
+    ap.add_argument("--mq-kernel", default="multiquadric",
+                    choices=["multiquadric", "inverse_multiquadric", "thin_plate", "r5"],
                     help="with --workload c2mq: the kernel of the exact sum")
     args = ap.parse_args()
     if args.gpus != 1:

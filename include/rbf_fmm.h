@@ -38,19 +38,24 @@ enum { RBF_OK = 0, RBF_ENOCONV = 1, RBF_EINVAL = -1, RBF_EUNSUPPORTED = -2, RBF_
        RBF_EHIP = -4, RBF_ESTATE = -5 };
 enum { RBF_F32 = 0, RBF_F64 = 1 };
 /* Kernels of the paper's table "Global functions" (section 2.2) and of its numerical examples
- * (section 7).  The Gaussian is used in the shape form exp(-r^2 / (2 s^2)) (shape = s > 0);
+ * (section 5).  The Gaussian is used in the shape form exp(-r^2 / (2 s^2)) (shape = s > 0);
  * the multiquadric is sqrt(r^2 + c^2) and the inverse multiquadric 1/sqrt(r^2 + c^2)
  * (shape = c > 0); Wendland's compactly supported function is (1 - e r)_+^3 (3 e r + 1)
- * (shape = e > 0, support radius 1/e).
- *   Only the Gaussian has a band-limited far field in this build.  Multiquadric and inverse
- *   multiquadric plans hold a single leaf and the product is the exact O(N^2) sum through the
- *   tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
+ * (shape = e > 0, support radius 1/e).  The thin-plate spline r^2 log r (0 at r = 0) and r^5
+ * of the paper's Fourier-transform table (section 3) have no shape (any positive value is
+ * accepted and ignored); they are conditionally positive definite, so rbf_interp_solve,
+ * rbf_interp_solve_batch and block-Jacobi reject them (RBF_EUNSUPPORTED: the polynomial
+ * augmentation their interpolation needs is not built); products and evaluation work.
+ *   Only the Gaussian has a band-limited far field in this build.  Multiquadric, inverse
+ *   multiquadric, thin-plate and r^5 plans hold a single leaf and the product is the exact
+ *   O(N^2) sum through the tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
  *   support radius wide, with the adjacent cells as the near field and no far field: every
  *   pair inside the support is a near pair, so the product is exact (a single leaf when no
  *   such level below the root exists).  For these three kernels tol and the tree options are
  *   ignored.  Any plan of one leaf without a far field computes its product with the tiled
  *   direct kernel. */
-enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3 };
+enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3,
+       RBF_THIN_PLATE = 4, RBF_R5 = 5 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
 
 /* Optional planning overrides; zero or negative fields mean "choose automatically".
@@ -293,7 +298,7 @@ enum { RBF_MLP_BF16 = 0, RBF_MLP_F32 = 1 };
  * default, reg = 1e-2 Phi(0)).  Synchronous.  RBF_EINVAL if a block is numerically
  * singular at this reg (a pivot <= 0).  Kernels with positive definite blocks only: the
  * Gaussian, the inverse multiquadric and Wendland's function; RBF_EUNSUPPORTED for the
- * multiquadric.  The learned preconditioner, its features, pairs and harvest are
+ * multiquadric, the thin-plate spline and r^5.  The learned preconditioner, its features, pairs and harvest are
  * Gaussian-only (RBF_EUNSUPPORTED otherwise). */
 int rbf_pc_block_jacobi(rbf_plan *plan, double reg);
 /* Build the block inverses that form the learned map's features y (and those of

@@ -6,7 +6,7 @@
  * product library.  Plain double-precision loops, IEEE arithmetic (no fast-math),
  * one OpenMP thread per block of targets.  Kernels: 0 = Gaussian exp(-r^2/(2 s^2)),
  * 1 = multiquadric sqrt(r^2 + c^2), 2 = inverse multiquadric 1/sqrt(r^2 + c^2),
- * 3 = Wendland (1 - e r)_+^3 (3 e r + 1) (section 7), 4 = thin-plate spline r^2 log r
+ * 3 = Wendland (1 - e r)_+^3 (3 e r + 1) (section 5), 4 = thin-plate spline r^2 log r
  * (0 at r = 0), 5 = r^5 (the Fourier-transform table; shape ignored).  Points are row-major
  * (n, d).
  */

@@ -3,7 +3,7 @@
 * Gaussian: the paper lists exp(-c r^2) (Tab. "Global functions", section 2.2); the
   workloads use the shape form exp(-r^2 / (2 s^2)), i.e. c = 1/(2 s^2).
 * Multiquadric: sqrt(r^2 + c^2) and inverse multiquadric 1/sqrt(r^2 + c^2) (same table).
-* Wendland's compactly supported function (1 - e r)_+^3 (3 e r + 1) (section 7, the third
+* Wendland's compactly supported function (1 - e r)_+^3 (3 e r + 1) (section 5, the third
   kernel of the numerical examples, with the scaled support radius 1/e of its figure).
 * The piecewise smooth kernels of the Fourier-transform table: the thin-plate spline r^2 log r
   (0 at r = 0) and r^5.  Both are scale-free (the shape argument is ignored).

@@ -53,9 +53,10 @@ double band_t(double tol) {
     return hi;
 }
 
-// Multiquadric and inverse multiquadric: this build has no band-limited far field for them
-// (a kernel that grows or decays like a power of r cannot be pruned, and one frequency grid for
-// all levels would have to resolve the finest near-zone width over the whole domain).  Every
+// Multiquadric, inverse multiquadric, thin-plate spline and r^5: this build has no band-limited
+// far field for them (a kernel that grows or decays like a power of r cannot be pruned, and one
+// frequency grid for all levels would have to resolve the finest near-zone width over the whole
+// domain).  Every
 // pair is a near pair of a single leaf: the product is the exact sum, evaluated by the tiled
 // direct kernel.
 void multiquadric_params(rbf_plan *p) {
@@ -96,7 +97,8 @@ void wendland_params(rbf_plan *p) {
 }
 
 int choose_params(rbf_plan *p, const rbf_opts *o) {
-    if (p->kernel == RBF_MULTIQUADRIC || p->kernel == RBF_INVERSE_MULTIQUADRIC) {
+    if (p->kernel == RBF_MULTIQUADRIC || p->kernel == RBF_INVERSE_MULTIQUADRIC || p->kernel == RBF_THIN_PLATE ||
+        p->kernel == RBF_R5) {
         multiquadric_params(p);
         return RBF_OK;
     }
@@ -190,7 +192,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (d < 1 || d > kMaxDim) { set_error("rbf_fmm_plan: d=%d out of range [1,5]", d); return RBF_EINVAL; }
     if (d != 2 && d != 3 && d != 5) { set_error("rbf_fmm_plan: d=%d is not compiled (2, 3, 5 are)", d); return RBF_EUNSUPPORTED; }
     if (dtype != RBF_F32 && dtype != RBF_F64) { set_error("rbf_fmm_plan: bad dtype %d", dtype); return RBF_EINVAL; }
-    if (kernel < RBF_GAUSSIAN || kernel > RBF_WENDLAND) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
+    if (kernel < RBF_GAUSSIAN || kernel > RBF_R5) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
     if (!(shape > 0) || !std::isfinite(shape)) { set_error("rbf_fmm_plan: shape must be positive"); return RBF_EINVAL; }
     if (!(tol > 0 && tol < 1)) { set_error("rbf_fmm_plan: tol must lie in (0, 1)"); return RBF_EINVAL; }
     rbf_plan *p = new (std::nothrow) rbf_plan();

@@ -124,8 +124,9 @@ __device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
 
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32 (in
 // FP64 the kernels call exp2_tab64 with its LDS table).  Multiquadric sqrt(r^2 + c^2) and inverse
-// multiquadric 1/sqrt(r^2 + c^2): coef = c^2.  Wendland's (1 - e r)_+^3 (3 e r + 1) (section 7):
-// coef = e, zero from r = 1/e on.
+// multiquadric 1/sqrt(r^2 + c^2): coef = c^2.  Wendland's (1 - e r)_+^3 (3 e r + 1) (section 5):
+// coef = e, zero from r = 1/e on.  The thin-plate spline r^2 log r = r^2 log(r^2) / 2 (0 at
+// r = 0) and r^5 have no shape.
 template <> struct KFun<float> {
     static __device__ __forceinline__ float gauss(float r2, float coef) { return __builtin_amdgcn_exp2f(r2 * coef); }
     static __device__ __forceinline__ float mq(float r2, float c2) { return __builtin_amdgcn_sqrtf(r2 + c2); }
@@ -135,6 +136,8 @@ template <> struct KFun<float> {
         const float t = fmaxf(1.0f - er, 0.0f);
         return t * t * t * fmaf(3.0f, er, 1.0f);
     }
+    static __device__ __forceinline__ float thin_plate(float r2) { return r2 > 0.0f ? 0.5f * r2 * logf(r2) : 0.0f; }
+    static __device__ __forceinline__ float r5(float r2) { return r2 * r2 * __builtin_amdgcn_sqrtf(r2); }
 };
 // Square root of a squared distance (0 <= a, far above the subnormal range) without the
 // library's range scaling: Goldschmidt's iteration from the hardware reciprocal square root,
@@ -153,14 +156,29 @@ __device__ __forceinline__ double sqrt_dist2(double a) {
     return a > 0.0 ? g : 0.0;
 }
 
+// 1/sqrt(a) for a positive normal a: two Newton steps y += y (1 - a y^2) / 2 from the hardware
+// reciprocal square root (each step squares the relative error).
+__device__ __forceinline__ double rsqrt_pos(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    double e = fma(-a * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 template <> struct KFun<double> {
-    static __device__ __forceinline__ double mq(double r2, double c2) { return sqrt(r2 + c2); }
-    static __device__ __forceinline__ double imq(double r2, double c2) { return 1.0 / sqrt(r2 + c2); }
+    static __device__ __forceinline__ double mq(double r2, double c2) {
+        const double a = r2 + c2;
+        return a * rsqrt_pos(a);
+    }
+    static __device__ __forceinline__ double imq(double r2, double c2) { return rsqrt_pos(r2 + c2); }
     static __device__ __forceinline__ double wendland(double r2, double e) {
         const double er = e * sqrt_dist2(r2);
         const double t = fmax(1.0 - er, 0.0);
         return t * t * t * fma(3.0, er, 1.0);
     }
+    static __device__ __forceinline__ double thin_plate(double r2) { return r2 > 0.0 ? 0.5 * r2 * log(r2) : 0.0; }
+    static __device__ __forceinline__ double r5(double r2) { return r2 * r2 * sqrt_dist2(r2); }
 };
 
 template <int D> struct Pad { static constexpr int v = (D + 2) & ~1; };
@@ -228,7 +246,9 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
     else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
     else if constexpr (KER == RBF_MULTIQUADRIC) return KFun<T>::mq(r2, coef);
     else if constexpr (KER == RBF_INVERSE_MULTIQUADRIC) return KFun<T>::imq(r2, coef);
-    else return KFun<T>::wendland(r2, coef);
+    else if constexpr (KER == RBF_WENDLAND) return KFun<T>::wendland(r2, coef);
+    else if constexpr (KER == RBF_THIN_PLATE) return KFun<T>::thin_plate(r2);
+    else return KFun<T>::r5(r2);
 }
 
 template <class T, int D, int KER>
@@ -1119,7 +1139,9 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_GAUSSIAN: k_p2p<T, D, RBF_GAUSSIAN><<<g, kWave, 0, s>>>(w); break;
                 case RBF_MULTIQUADRIC: k_p2p<T, D, RBF_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
                 case RBF_INVERSE_MULTIQUADRIC: k_p2p<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
-                default: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
+                case RBF_WENDLAND: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
+                case RBF_THIN_PLATE: k_p2p<T, D, RBF_THIN_PLATE><<<g, kWave, 0, s>>>(w); break;
+                default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
             }
             break;
         case PH_DIRECT:
@@ -1127,7 +1149,9 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_GAUSSIAN: k_direct<T, D, RBF_GAUSSIAN><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_MULTIQUADRIC: k_direct<T, D, RBF_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_INVERSE_MULTIQUADRIC: k_direct<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
-                default: k_direct<T, D, RBF_WENDLAND><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_WENDLAND: k_direct<T, D, RBF_WENDLAND><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_THIN_PLATE: k_direct<T, D, RBF_THIN_PLATE><<<g, kThreads, 0, s>>>(w); break;
+                default: k_direct<T, D, RBF_R5><<<g, kThreads, 0, s>>>(w); break;
             }
             break;
         case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kThreads, 0, s>>>(w); break;

@@ -232,11 +232,11 @@ int factor_blocks(rbf_plan *p, double reg, double *inv) {
     return RBF_OK;
 }
 
-// Block-Jacobi needs positive definite blocks (not the multiquadric's); the network's features
-// and training pairs are those of the Gaussian.
+// Block-Jacobi needs positive definite blocks (not those of the multiquadric, the thin-plate spline
+// or r^5); the network's features and training pairs are those of the Gaussian.
 int check_bj_kernel(const rbf_plan *p) {
-    if (p->kernel == RBF_MULTIQUADRIC) {
-        set_error("block-Jacobi: the multiquadric's blocks are not positive definite (Gaussian, inverse "
+    if (p->kernel != RBF_GAUSSIAN && p->kernel != RBF_INVERSE_MULTIQUADRIC && p->kernel != RBF_WENDLAND) {
+        set_error("block-Jacobi: the blocks of this kernel are not positive definite (Gaussian, inverse "
                   "multiquadric and Wendland kernels are supported)");
         return RBF_EUNSUPPORTED;
     }

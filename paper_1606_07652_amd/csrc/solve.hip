@@ -317,6 +317,11 @@ extern "C" int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, dou
     using namespace rbf;
     if (!plan || !f || !lambda) { set_error("rbf_interp_solve: null argument"); return RBF_EINVAL; }
     RBF_TRY(reject_eval_plan(plan, "rbf_interp_solve"));
+    if (plan->kernel == RBF_THIN_PLATE || plan->kernel == RBF_R5) {
+        set_error("rbf_interp_solve: the thin-plate spline and r^5 are conditionally positive definite; their "
+                  "interpolation needs polynomial augmentation, which this build does not provide");
+        return RBF_EUNSUPPORTED;
+    }
     if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve: rtol must lie in (0, 1)"); return RBF_EINVAL; }
     if (opts && (opts->restart < 0 || opts->restart > 1000)) { set_error("rbf_interp_solve: restart out of range"); return RBF_EINVAL; }
     if (opts && (opts->precond < RBF_PC_NONE || opts->precond > RBF_PC_LEARNED)) {

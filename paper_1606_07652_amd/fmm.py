@@ -14,7 +14,8 @@ import torch
 from . import _lib as L
 
 _KERNELS = {"gaussian": L.RBF_GAUSSIAN, "multiquadric": L.RBF_MULTIQUADRIC,
-            "inverse_multiquadric": L.RBF_INVERSE_MULTIQUADRIC, "wendland": L.RBF_WENDLAND}
+            "inverse_multiquadric": L.RBF_INVERSE_MULTIQUADRIC, "wendland": L.RBF_WENDLAND,
+            "thin_plate": L.RBF_THIN_PLATE, "r5": L.RBF_R5}
 _PCS = {"none": L.RBF_PC_NONE, "block_jacobi": L.RBF_PC_BLOCK_JACOBI, "learned": L.RBF_PC_LEARNED}
 
 

@@ -1,5 +1,5 @@
 """GPU parity of the inverse multiquadric and of Wendland's compactly supported function (the
-kernels of the paper's numerical examples, section 7) against the oracle's direct sum of eq. 1,
+kernels of the paper's numerical examples, section 5) against the oracle's direct sum of eq. 1,
 through the C ABI.
 
 * inverse multiquadric: single-leaf plans, the exact sum by the tiled direct kernel;
@@ -215,3 +215,51 @@ def test_preconditioner_kernel_errors():
     with pytest.raises(RbfError) as e:
         pc.learned_features(pi)
     assert e.value.code == RBF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kernel", ["thin_plate", "r5"])
+@pytest.mark.parametrize("dtype,bound", [(torch.float64, 1e-13), (torch.float32, 1e-5)])
+@pytest.mark.parametrize("d,n", [(2, 2300), (3, 3001)])
+def test_piecewise_smooth_kernels_are_the_exact_sum(kernel, dtype, bound, d, n):
+    """The thin-plate spline and r^5 (no shape): single-leaf plans, the exact sum, with
+    duplicated points (r = 0 pairs beside the diagonal)."""
+    x = uniform_points(n, d, 400 + d)
+    x[n // 2:n // 2 + 50] = x[:50]
+    lam = normal_weights(n, 401)
+    p = plan(x, kernel, 1.0, dtype, n_max=64)
+    inf = p.info()
+    assert inf["nleaves"] == 1 and inf["far_field"] == 0
+    X, L = dev(x, dtype), dev(lam, dtype)
+    u = p.matvec(L).double().cpu().numpy()
+    ref = direct.direct_sum(X.double().cpu().numpy(), L.double().cpu().numpy(), kernel, 1.0)
+    assert np.all(np.isfinite(u))
+    assert direct.rel_l2(u, ref) <= bound
+
+
+@pytest.mark.parametrize("kernel", ["thin_plate", "r5"])
+def test_piecewise_smooth_kernels_at_separate_targets(kernel):
+    from paper_1606_07652_amd import EvalPlan
+    x = uniform_points(2000, 3, 410)
+    lam = normal_weights(2000, 411)
+    y = uniform_points(900, 3, 412) * 1.4 - 0.2
+    y[:100] = x[:100]
+    p = EvalPlan(dev(x), dev(y), kernel=kernel, shape=1.0, tol=1e-6)
+    u = p.eval(dev(lam)).cpu().numpy()
+    assert direct.rel_l2(u, direct.direct_sum(x, lam, kernel, 1.0, targets=y)) <= 1e-13
+
+
+def test_piecewise_smooth_kernels_reject_solve_and_block_jacobi():
+    """Conditionally positive definite kernels: interpolation needs polynomial augmentation
+    (not built), and their blocks are not positive definite."""
+    from paper_1606_07652_amd import pc
+    from paper_1606_07652_amd._lib import RBF_EUNSUPPORTED, RbfError
+    x = uniform_points(400, 2, 420)
+    f = np.sin(3 * x[:, 0])
+    for kernel in ("thin_plate", "r5"):
+        p = plan(x, kernel, 1.0, torch.float64)
+        with pytest.raises(RbfError) as e:
+            p.solve(dev(f), rtol=1e-6)
+        assert e.value.code == RBF_EUNSUPPORTED
+        with pytest.raises(RbfError) as e:
+            pc.block_jacobi(p)
+        assert e.value.code == RBF_EUNSUPPORTED
