@@ -160,6 +160,26 @@ typedef struct rbf_solve_info {
 int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, double rtol,
                      const rbf_solve_opts *opts, rbf_solve_info *info);
 
+/* Interpolation with the polynomial terms that conditionally positive definite kernels need
+ * (the paper's thin-plate spline and r^5 of its Fourier-transform table, section 3, and the
+ * multiquadric): u(x) = sum_j lambda_j Phi(x - x_j) + sum_k c_k p_k(t(x)), with
+ * sum_j lambda_j p_k(t(x_j)) = 0, solved as the square system [A P; P' 0][lambda; c] = [f; 0]
+ * by the same GMRES over vectors of n + q entries.
+ *   Degree: 0 for the multiquadric, 1 for the thin-plate spline, 2 for r^5; the positive
+ *   definite kernels (Gaussian, inverse multiquadric, Wendland) have q = 0 and this call is
+ *   rbf_interp_solve.  Basis: monomials of t = (x - lo) / ext, lo and ext the plan's root
+ *   cube (rbf_plan_info.lo and .ext): 1; t_1 .. t_d; t_a t_b for a <= b in row-major order.
+ *   coeffs  device, q = rbf_poly_terms(plan) entries, plan dtype: initial guess in (unless
+ *           opts->zero_init), coefficients out; may be NULL when q = 0.
+ *   rtol    on ||[f; 0] - [A P; P' 0][lambda; c]|| / ||f||.
+ * Augmented systems take no preconditioner (RBF_EUNSUPPORTED unless opts->precond is
+ * RBF_PC_NONE).  Otherwise as rbf_interp_solve. */
+int rbf_interp_solve_poly(rbf_plan *plan, const void *f, void *lambda, void *coeffs, double rtol,
+                          const rbf_solve_opts *opts, rbf_solve_info *info);
+/* Number q of polynomial terms of rbf_interp_solve_poly for this plan (0, 1, 1 + d or
+ * 1 + d + d (d + 1) / 2), or a negative error code. */
+int rbf_poly_terms(const rbf_plan *plan);
+
 /* Destroy a plan and free its device memory (NULL is accepted). */
 int rbf_fmm_destroy(rbf_plan *plan);
 

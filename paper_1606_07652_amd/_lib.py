@@ -81,6 +81,10 @@ SIGNATURES = {
     "rbf_direct_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rbf_interp_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                         ctypes.POINTER(RbfSolveOpts), ctypes.POINTER(RbfSolveInfo)]),
+    "rbf_interp_solve_poly": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_double, ctypes.POINTER(RbfSolveOpts),
+                                             ctypes.POINTER(RbfSolveInfo)]),
+    "rbf_poly_terms": (ctypes.c_int, [ctypes.c_void_p]),
     "rbf_fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rbf_last_error": (ctypes.c_char_p, []),
     "rbf_fmm_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfPlanInfo)]),
@@ -145,5 +149,12 @@ def load():
 
 def check(code: int, allow=(RBF_OK,)) -> int:
     if code not in allow:
+        raise RbfError(code, load().rbf_last_error().decode(errors="replace"))
+    return code
+
+
+def check_count(code: int) -> int:
+    """A count (>= 0) or a negative error code."""
+    if code < 0:
         raise RbfError(code, load().rbf_last_error().decode(errors="replace"))
     return code

@@ -139,6 +139,7 @@ struct rbf_plan {
     // solver workspace (allocated on first solve)
     rbf::Arena solver_arena;
     int solver_m = 0;
+    int64_t solver_na = 0;           // Krylov vector length the solver buffers hold (n + polynomial terms)
     double *V = nullptr;             // Arnoldi basis [(m+1)][n] FP64
     double *Z = nullptr;             // preconditioned basis [m][n] FP64 (flexible GMRES)
     double *sv = nullptr;            // small device vectors (dots, norms)

@@ -85,37 +85,126 @@ __global__ void k_multiaxpy(double *__restrict__ w, const double *__restrict__ V
     w[i] += sign * s;
 }
 
+// Polynomial part of an augmented product (conditionally positive definite kernels): the
+// monomials of t = (x - lo) / ext up to degree 2 (1; t_1 .. t_d; t_a t_b for a <= b).
+struct Poly {
+    int q = 0, deg = -1, d = 0;
+    double lo[kMaxDim] = {0, 0, 0, 0, 0};
+    double inv_ext = 1.0;
+};
+constexpr int kMaxPolyTerms = 1 + kMaxDim + kMaxDim * (kMaxDim + 1) / 2;
+
+int poly_degree(int kernel) {
+    switch (kernel) {
+        case RBF_MULTIQUADRIC: return 0;
+        case RBF_THIN_PLATE: return 1;
+        case RBF_R5: return 2;
+        default: return -1;
+    }
+}
+
+int poly_terms(int d, int deg) {
+    if (deg < 0) return 0;
+    return 1 + (deg >= 1 ? d : 0) + (deg >= 2 ? d * (d + 1) / 2 : 0);
+}
+
+template <class T>
+__device__ __forceinline__ void monomials(const T *__restrict__ xs, int64_t n, int64_t s, const Poly &P,
+                                          double (&m)[kMaxPolyTerms]) {
+    double t[kMaxDim];
+    for (int a = 0; a < P.d; ++a) t[a] = ((double)xs[(int64_t)a * n + s] - P.lo[a]) * P.inv_ext;
+    int k = 0;
+    m[k++] = 1.0;
+    if (P.deg >= 1)
+        for (int a = 0; a < P.d; ++a) m[k++] = t[a];
+    if (P.deg >= 2)
+        for (int a = 0; a < P.d; ++a)
+            for (int b = a; b < P.d; ++b) m[k++] = t[a] * t[b];
+}
+
+// y[perm[s]] += sum_k c_k p_k(t_s)
+template <class T>
+__global__ void k_poly_add(const T *__restrict__ xs, const int *__restrict__ perm, int64_t n, Poly P,
+                           const double *__restrict__ c, double *__restrict__ y) {
+    const int64_t s = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (s >= n) return;
+    double m[kMaxPolyTerms];
+    monomials(xs, n, s, P, m);
+    double v = 0.0;
+    for (int k = 0; k < P.q; ++k) v = fma(c[k], m[k], v);
+    y[perm[s]] += v;
+}
+
+// part[b * q + k] = sum over block b's slice of x[perm[s]] p_k(t_s)
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_poly_dots(const T *__restrict__ xs, const int *__restrict__ perm,
+                                                        int64_t n, Poly P, const double *__restrict__ x,
+                                                        double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    double acc[kMaxPolyTerms];
+    for (int k = 0; k < kMaxPolyTerms; ++k) acc[k] = 0.0;
+    for (int64_t s = i0 + threadIdx.x; s < i1; s += kThreads) {
+        double m[kMaxPolyTerms];
+        monomials(xs, n, s, P, m);
+        const double v = x[perm[s]];
+        for (int k = 0; k < P.q; ++k) acc[k] = fma(v, m[k], acc[k]);
+    }
+    for (int k = 0; k < P.q; ++k) {
+        const double t = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) part[blockIdx.x * P.q + k] = t;
+    }
+}
+
 __global__ void k_isfinite(const double *__restrict__ v, int64_t n, int *flag) {
     int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
     if (i < n && !isfinite(v[i])) *flag = 1;
 }
 
+// Krylov vectors have na = n + q entries: the weights in caller order, then the q polynomial
+// coefficients of an augmented system (q = 0 otherwise).
 struct Solver {
     rbf_plan *p;
-    int64_t n;
+    int64_t n, na;
     unsigned nb;
+    Poly poly;
     double *part = nullptr, *hdev = nullptr, *xd = nullptr, *fd = nullptr, *rd = nullptr, *wd = nullptr;
     int *flag = nullptr;
 
     int product(const double *x64, double *y64) {
-        // y = A x through the plan's dtype
+        // y = A x through the plan's dtype, then the polynomial blocks [P c; P' lambda]
         hipStream_t s = p->stream;
         if (p->dtype == RBF_F64) {
             RBF_TRY(launch_matvec(p, x64, y64));
-            return RBF_OK;
+        } else {
+            float *tin = (float *)p->tvec, *tout = tin + n;
+            k_cvt<double, float><<<nb, kThreads, 0, s>>>(x64, tin, n);
+            RBF_HIP(hipGetLastError());
+            RBF_TRY(launch_matvec(p, tin, tout));
+            k_cvt<float, double><<<nb, kThreads, 0, s>>>(tout, y64, n);
+            RBF_HIP(hipGetLastError());
         }
-        float *tin = (float *)p->tvec, *tout = tin + n;
-        k_cvt<double, float><<<nb, kThreads, 0, s>>>(x64, tin, n);
-        RBF_HIP(hipGetLastError());
-        RBF_TRY(launch_matvec(p, tin, tout));
-        k_cvt<float, double><<<nb, kThreads, 0, s>>>(tout, y64, n);
-        RBF_HIP(hipGetLastError());
+        if (poly.q > 0) {
+            if (p->dtype == RBF_F64) {
+                k_poly_add<double><<<nb, kThreads, 0, s>>>((const double *)p->xs, p->perm, n, poly, x64 + n, y64);
+                k_poly_dots<double><<<kDotBlocks, kThreads, 0, s>>>((const double *)p->xs, p->perm, n, poly, x64,
+                                                                    part);
+            } else {
+                k_poly_add<float><<<nb, kThreads, 0, s>>>((const float *)p->xs, p->perm, n, poly, x64 + n, y64);
+                k_poly_dots<float><<<kDotBlocks, kThreads, 0, s>>>((const float *)p->xs, p->perm, n, poly, x64,
+                                                                   part);
+            }
+            RBF_HIP(hipGetLastError());
+            k_reduce_parts<<<poly.q, kThreads, 0, s>>>(part, kDotBlocks, poly.q, y64 + n);
+            RBF_HIP(hipGetLastError());
+        }
         return RBF_OK;
     }
 
     int dots(const double *V, int k, const double *w, double *host_out) {
         hipStream_t s = p->stream;
-        k_multidot<<<kDotBlocks, kThreads, 0, s>>>(V, n, k, w, part);
+        k_multidot<<<kDotBlocks, kThreads, 0, s>>>(V, na, k, w, part);
         RBF_HIP(hipGetLastError());
         k_reduce_parts<<<k, kThreads, 0, s>>>(part, kDotBlocks, k, hdev);
         RBF_HIP(hipGetLastError());
@@ -134,10 +223,11 @@ struct Solver {
     }
 };
 
+// coeffs: the q polynomial coefficients of an augmented solve (plan dtype, device; q = 0: unused)
 int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_solve_opts *o,
-               rbf_solve_info *info) {
+               rbf_solve_info *info, int q = 0, void *coeffs = nullptr) {
     auto t_start = std::chrono::steady_clock::now();
-    const int64_t n = p->n;
+    const int64_t n = p->n, na = n + q;
     const int m = (o && o->restart > 0) ? o->restart : 50;
     const int maxit = (o && o->max_iters > 0) ? o->max_iters : 1000;
     int pck = o ? o->precond : RBF_PC_NONE;
@@ -148,37 +238,55 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         if (rc != RBF_OK) return rc;
     }
     hipStream_t s = p->stream;
-    if (p->solver_m < m) {
+    if (p->solver_m < m || p->solver_na < na) {
         p->solver_arena.release();
+        p->solver_m = 0;
+        p->solver_na = 0;
         Arena &ar = p->solver_arena;
-        RBF_TRY(ar.alloc((void **)&p->V, sizeof(double) * (size_t)(m + 1) * n));
-        RBF_TRY(ar.alloc((void **)&p->Z, sizeof(double) * (size_t)m * n));
-        RBF_TRY(ar.alloc((void **)&p->sv, sizeof(double) * ((size_t)kDotBlocks * (m + 2) + 4 * (m + 2) + 8)));
-        RBF_TRY(ar.alloc(&p->tvec, sizeof(double) * (size_t)7 * n));
+        const int kp = std::max(m + 2, kMaxPolyTerms);   // partial sums of the dots and of P' x
+        RBF_TRY(ar.alloc((void **)&p->V, sizeof(double) * (size_t)(m + 1) * na));
+        RBF_TRY(ar.alloc((void **)&p->Z, sizeof(double) * (size_t)m * na));
+        RBF_TRY(ar.alloc((void **)&p->sv, sizeof(double) * ((size_t)kDotBlocks * kp + 4 * (m + 2) + 8)));
+        RBF_TRY(ar.alloc(&p->tvec, sizeof(double) * (size_t)7 * na));
         p->solver_m = m;
+        p->solver_na = na;
     }
     Solver S;
     S.p = p;
     S.n = n;
+    S.na = na;
     S.nb = (unsigned)((n + kThreads - 1) / kThreads);
+    S.poly.q = q;
+    S.poly.deg = poly_degree(p->kernel);
+    S.poly.d = p->d;
+    for (int a = 0; a < p->d; ++a) S.poly.lo[a] = p->lo[a];
+    S.poly.inv_ext = 1.0 / p->ext;
+    const int kp = std::max(m + 2, kMaxPolyTerms);
     S.part = p->sv;
-    S.hdev = p->sv + (size_t)kDotBlocks * (m + 2);
+    S.hdev = p->sv + (size_t)kDotBlocks * kp;
     S.flag = (int *)(S.hdev + 2 * (m + 2));
     double *base = (double *)p->tvec;
-    S.xd = base + 2 * n;  // tvec[0..2n) holds the float in/out pair for F32 plans
-    S.fd = base + 3 * n;
-    S.rd = base + 4 * n;
-    S.wd = base + 5 * n;
-    const unsigned nb = S.nb;
-    // x0 and f in FP64
+    S.xd = base + 2 * na;  // tvec[0..2n) holds the float in/out pair for F32 plans
+    S.fd = base + 3 * na;
+    S.rd = base + 4 * na;
+    S.wd = base + 5 * na;
+    const unsigned nb = (unsigned)((na + kThreads - 1) / kThreads);   // grid over the Krylov length
+    const size_t tsz = p->dtype == RBF_F64 ? 8 : 4;
+    // x0 and f in FP64: [lambda; c] and [f; 0]
+    if (q > 0) RBF_HIP(hipMemsetAsync(S.fd + n, 0, sizeof(double) * q, s));
+    if (o && o->zero_init) RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * na, s));
     if (p->dtype == RBF_F64) {
         RBF_HIP(hipMemcpyAsync(S.fd, f, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        if (o && o->zero_init) RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
-        else RBF_HIP(hipMemcpyAsync(S.xd, lambda, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (!(o && o->zero_init)) {
+            RBF_HIP(hipMemcpyAsync(S.xd, lambda, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            if (q > 0) RBF_HIP(hipMemcpyAsync(S.xd + n, coeffs, tsz * q, hipMemcpyDeviceToDevice, s));
+        }
     } else {
-        k_cvt<float, double><<<nb, kThreads, 0, s>>>((const float *)f, S.fd, n);
-        if (o && o->zero_init) RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
-        else k_cvt<float, double><<<nb, kThreads, 0, s>>>((const float *)lambda, S.xd, n);
+        k_cvt<float, double><<<S.nb, kThreads, 0, s>>>((const float *)f, S.fd, n);
+        if (!(o && o->zero_init)) {
+            k_cvt<float, double><<<S.nb, kThreads, 0, s>>>((const float *)lambda, S.xd, n);
+            if (q > 0) k_cvt<float, double><<<1, kThreads, 0, s>>>((const float *)coeffs, S.xd + n, q);
+        }
         RBF_HIP(hipGetLastError());
     }
     double bnorm = 0;
@@ -195,11 +303,11 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     double best = INFINITY;
     double last_cycle_res = INFINITY;
     if (bnorm == 0.0) {
-        RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * n, s));
+        RBF_HIP(hipMemsetAsync(S.xd, 0, sizeof(double) * na, s));
     }
     while (bnorm > 0.0) {
         RBF_TRY(S.product(S.xd, S.wd));
-        k_sub<<<nb, kThreads, 0, s>>>(S.fd, S.wd, S.rd, n);
+        k_sub<<<nb, kThreads, 0, s>>>(S.fd, S.wd, S.rd, na);
         RBF_HIP(hipGetLastError());
         double beta = 0;
         RBF_TRY(S.norm(S.rd, &beta));
@@ -211,7 +319,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         if (cur != RBF_PC_NONE && fallback && restarts > 0 && rel > 0.999 * last_cycle_res)
             step_down();   // the preconditioned cycle did not reduce the true residual
         last_cycle_res = rel;
-        k_scale<<<nb, kThreads, 0, s>>>(S.rd, 1.0 / beta, p->V, n);
+        k_scale<<<nb, kThreads, 0, s>>>(S.rd, 1.0 / beta, p->V, na);
         RBF_HIP(hipGetLastError());
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
@@ -220,8 +328,8 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         bool pc_failed = false;
         const bool use_pc = cur != RBF_PC_NONE;
         for (int j = 0; j < m; ++j) {
-            double *vj = p->V + (size_t)j * n;
-            double *zj = use_pc ? p->Z + (size_t)j * n : vj;
+            double *vj = p->V + (size_t)j * na;
+            double *zj = use_pc ? p->Z + (size_t)j * na : vj;
             if (use_pc) {
                 // Flexible GMRES accepts any direction z_j.  With the learned map the cycle
                 // is block-Jacobi FGMRES except for its last direction, z_{m-1} =
@@ -238,7 +346,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
                 RBF_TRY(pc_apply(p, kind, src, zj));
                 int hf = 0;
                 RBF_HIP(hipMemsetAsync(S.flag, 0, sizeof(int), s));
-                k_isfinite<<<nb, kThreads, 0, s>>>(zj, n, S.flag);
+                k_isfinite<<<nb, kThreads, 0, s>>>(zj, na, S.flag);
                 RBF_HIP(hipMemcpyAsync(&hf, S.flag, sizeof(int), hipMemcpyDeviceToHost, s));
                 RBF_HIP(hipStreamSynchronize(s));
                 if (hf) { pc_failed = true; break; }
@@ -246,10 +354,10 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
             RBF_TRY(S.product(zj, S.wd));
             // CGS2
             RBF_TRY(S.dots(p->V, j + 1, S.wd, hh.data()));
-            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, n, j + 1, S.hdev, -1.0);
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, S.hdev, -1.0);
             RBF_HIP(hipGetLastError());
             RBF_TRY(S.dots(p->V, j + 1, S.wd, hh2.data()));
-            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, n, j + 1, S.hdev, -1.0);
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, S.hdev, -1.0);
             RBF_HIP(hipGetLastError());
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh2[i];
             double hn = 0;
@@ -270,7 +378,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
             k = j + 1;
             if (!std::isfinite(hn)) { pc_failed = use_pc; k = j; break; }
             if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || its >= maxit) break;
-            k_scale<<<nb, kThreads, 0, s>>>(S.wd, 1.0 / hn, p->V + (size_t)(j + 1) * n, n);
+            k_scale<<<nb, kThreads, 0, s>>>(S.wd, 1.0 / hn, p->V + (size_t)(j + 1) * na, na);
             RBF_HIP(hipGetLastError());
         }
         if (pc_failed) {
@@ -286,16 +394,19 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         }
         if (k > 0) {
             RBF_HIP(hipMemcpyAsync(S.hdev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.xd, use_pc ? p->Z : p->V, n, k, S.hdev, 1.0);
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.xd, use_pc ? p->Z : p->V, na, k, S.hdev, 1.0);
             RBF_HIP(hipGetLastError());
             RBF_HIP(hipStreamSynchronize(s));
         }
         ++restarts;
     }
-    // write the solution in the plan's dtype
-    if (p->dtype == RBF_F64) RBF_HIP(hipMemcpyAsync(lambda, S.xd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    else {
-        k_cvt<double, float><<<nb, kThreads, 0, s>>>(S.xd, (float *)lambda, n);
+    // write the solution (and the polynomial coefficients) in the plan's dtype
+    if (p->dtype == RBF_F64) {
+        RBF_HIP(hipMemcpyAsync(lambda, S.xd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (q > 0) RBF_HIP(hipMemcpyAsync(coeffs, S.xd + n, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
+    } else {
+        k_cvt<double, float><<<S.nb, kThreads, 0, s>>>(S.xd, (float *)lambda, n);
+        if (q > 0) k_cvt<double, float><<<1, kThreads, 0, s>>>(S.xd + n, (float *)coeffs, q);
         RBF_HIP(hipGetLastError());
     }
     RBF_HIP(hipStreamSynchronize(s));
@@ -319,7 +430,7 @@ extern "C" int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, dou
     RBF_TRY(reject_eval_plan(plan, "rbf_interp_solve"));
     if (plan->kernel == RBF_THIN_PLATE || plan->kernel == RBF_R5) {
         set_error("rbf_interp_solve: the thin-plate spline and r^5 are conditionally positive definite; their "
-                  "interpolation needs polynomial augmentation, which this build does not provide");
+                  "interpolation needs the polynomial terms of rbf_interp_solve_poly");
         return RBF_EUNSUPPORTED;
     }
     if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve: rtol must lie in (0, 1)"); return RBF_EINVAL; }
@@ -329,4 +440,30 @@ extern "C" int rbf_interp_solve(rbf_plan *plan, const void *f, void *lambda, dou
         return RBF_EINVAL;
     }
     return solve_impl(plan, f, lambda, rtol, opts, info);
+}
+
+extern "C" int rbf_poly_terms(const rbf_plan *plan) {
+    using namespace rbf;
+    if (!plan) { set_error("rbf_poly_terms: null plan"); return RBF_EINVAL; }
+    return poly_terms(plan->d, poly_degree(plan->kernel));
+}
+
+extern "C" int rbf_interp_solve_poly(rbf_plan *plan, const void *f, void *lambda, void *coeffs, double rtol,
+                                     const rbf_solve_opts *opts, rbf_solve_info *info) {
+    using namespace rbf;
+    if (!plan || !f || !lambda) { set_error("rbf_interp_solve_poly: null argument"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_interp_solve_poly"));
+    const int q = poly_terms(plan->d, poly_degree(plan->kernel));
+    if (q > 0 && !coeffs) { set_error("rbf_interp_solve_poly: %d polynomial coefficients need a buffer", q); return RBF_EINVAL; }
+    if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve_poly: rtol must lie in (0, 1)"); return RBF_EINVAL; }
+    if (opts && (opts->restart < 0 || opts->restart > 1000)) { set_error("rbf_interp_solve_poly: restart out of range"); return RBF_EINVAL; }
+    if (opts && (opts->precond < RBF_PC_NONE || opts->precond > RBF_PC_LEARNED)) {
+        set_error("rbf_interp_solve_poly: unknown preconditioner %d", opts->precond);
+        return RBF_EINVAL;
+    }
+    if (q > 0 && opts && opts->precond != RBF_PC_NONE) {
+        set_error("rbf_interp_solve_poly: augmented systems run without a preconditioner");
+        return RBF_EUNSUPPORTED;
+    }
+    return solve_impl(plan, f, lambda, rtol, opts, info, q, coeffs);
 }

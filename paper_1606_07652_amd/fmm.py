@@ -191,6 +191,33 @@ class FmmPlan:
                      "fallback_used": int(info.fallback_used), "true_res": info.true_res,
                      "seconds": info.seconds, "history": list(info.history[:info.nhistory])}
 
+    def poly_terms(self) -> int:
+        """Number of polynomial terms of solve_poly (rbf_poly_terms)."""
+        return L.check_count(L.load().rbf_poly_terms(self._h))
+
+    def solve_poly(self, f: torch.Tensor, lam: Optional[torch.Tensor] = None, coeffs: Optional[torch.Tensor] = None,
+                   rtol: float = 1e-8, restart: int = 50, max_iters: int = 1000, time_limit_s: float = 0.0):
+        """Interpolation with the kernel's polynomial terms (rbf_interp_solve_poly); returns
+        (lambda, coeffs, info)."""
+        self._check_vec(f)
+        q = self.poly_terms()
+        zero = lam is None
+        if lam is None:
+            lam = torch.zeros_like(f)
+        self._check_vec(lam)
+        if coeffs is None:
+            coeffs = torch.zeros(max(q, 1), dtype=f.dtype, device=f.device)
+        if coeffs.dtype != f.dtype or coeffs.device != f.device or coeffs.numel() < q:
+            raise ValueError(f"coeffs must hold {q} entries of the plan's dtype on its device")
+        o = L.RbfSolveOpts(restart, max_iters, L.RBF_PC_NONE, 1 if zero else 0, 0, float(time_limit_s))
+        info = L.RbfSolveInfo()
+        code = L.load().rbf_interp_solve_poly(self._h, _ptr(f), _ptr(lam), _ptr(coeffs), float(rtol),
+                                              ctypes.byref(o), ctypes.byref(info))
+        L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
+        return lam, coeffs[:q], {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
+                                 "true_res": info.true_res, "seconds": info.seconds,
+                                 "history": list(info.history[:info.nhistory])}
+
     # -- introspection ---------------------------------------------------------------
     def info(self) -> dict:
         inf = L.RbfPlanInfo()

@@ -263,3 +263,85 @@ def test_piecewise_smooth_kernels_reject_solve_and_block_jacobi():
         with pytest.raises(RbfError) as e:
             pc.block_jacobi(p)
         assert e.value.code == RBF_EUNSUPPORTED
+
+
+AUGMENTED = [("thin_plate", 2, 300, 1.0), ("r5", 3, 250, 1.0), ("multiquadric", 3, 300, 0.1), ("thin_plate", 3, 400, 1.0)]
+
+
+@pytest.mark.parametrize("kernel,d,n,shape", AUGMENTED)
+def test_augmented_solve_matches_oracle(kernel, d, n, shape):
+    """[A P; P' 0][lambda; c] = [f; 0] by full GMRES (restart = n + q): the true residual of the
+    returned vector under the oracle's augmented matrix meets the tolerance, and the vector is
+    the oracle's dense solution to the condition number times the tolerance (cond <= 6e7 on
+    these sets, so 1e-4 with margin)."""
+    from oracle import poly
+    x = uniform_points(n, d, 500 + d)
+    f = np.sin(3 * x[:, 0]) + np.cos(2 * x[:, 1])
+    p = plan(x, kernel, shape, torch.float64)
+    q = p.poly_terms()
+    assert q == poly.nterms(d, poly.DEGREE[kernel])
+    lam, c, info = p.solve_poly(dev(f), rtol=1e-10, restart=n + q, max_iters=2 * (n + q))
+    print(f"[augmented {kernel} d={d}] q={q} iters={info['iters']} true_res={info['true_res']:.2e}", flush=True)
+    assert info["converged"]
+    sol = np.concatenate([lam.cpu().numpy(), c.cpu().numpy()])
+    M = poly.augmented_matrix(x, kernel, shape)
+    rhs = np.concatenate([f, np.zeros(q)])
+    assert np.linalg.norm(M @ sol - rhs) <= 2e-10 * np.linalg.norm(f)
+    lo, co = poly.augmented_solve(x, kernel, shape, f)
+    ref = np.concatenate([lo, co])
+    assert np.linalg.norm(sol - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kernel,d", [("thin_plate", 2), ("r5", 3)])
+def test_augmented_solve_reproduces_polynomials(kernel, d):
+    """A right-hand side in the polynomial space comes back as lambda = 0 and its coefficients
+    (the oracle's monomials of the root cube's normalised coordinates), to what the stopping
+    rule allows: a residual of rtol ||f|| moves the solution by at most rtol ||f|| / s_min, s_min
+    the smallest singular value of the oracle's augmented matrix (twice that as the bound)."""
+    from oracle import poly
+    x = uniform_points(200, d, 520 + d) * 2.0 - 0.5
+    P = poly.basis(x, poly.DEGREE[kernel])
+    ct = np.random.default_rng(521).standard_normal(P.shape[1])
+    f = P @ ct
+    rtol = 1e-12
+    smin = np.linalg.svd(poly.augmented_matrix(x, kernel, 1.0), compute_uv=False)[-1]
+    bound = 2.0 * rtol * np.linalg.norm(f) / smin
+    p = plan(x, kernel, 1.0, torch.float64)
+    q = p.poly_terms()
+    lam, c, info = p.solve_poly(dev(f), rtol=rtol, restart=200 + q, max_iters=2 * (200 + q))
+    assert info["converged"]
+    assert np.max(np.abs(c.cpu().numpy() - ct)) <= bound
+    assert np.max(np.abs(lam.cpu().numpy())) <= bound
+
+
+def test_augmented_solve_fp32_and_errors():
+    """FP32 plans solve the augmented system in FP64 Krylov vectors (products in FP32); the
+    positive definite kernels have q = 0; a preconditioner is refused for q > 0."""
+    from oracle import poly
+    from paper_1606_07652_amd._lib import RBF_EUNSUPPORTED, RbfError
+    x = uniform_points(300, 2, 530)
+    f = np.sin(3 * x[:, 0]) + x[:, 1]
+    p = plan(x, "thin_plate", 1.0, torch.float32)
+    # FP32 products carry ~1e-6 relative error times ||A|| ||lambda|| / ||f|| (about 30 here)
+    lam, c, info = p.solve_poly(dev(f, torch.float32), rtol=1e-4, restart=303, max_iters=606)
+    assert info["converged"]
+    M = poly.augmented_matrix(x.astype(np.float32).astype(np.float64), "thin_plate", 1.0)
+    sol = np.concatenate([lam.double().cpu().numpy(), c.double().cpu().numpy()])
+    rhs = np.concatenate([f.astype(np.float32).astype(np.float64), np.zeros(3)])
+    # the returned FP32 vector: its residual under the FP64 matrix is the solve's plus the
+    # rounding of the vector to float
+    assert np.linalg.norm(M @ sol - rhs) <= 1e-3 * np.linalg.norm(f)
+    assert plan(x, "gaussian", 0.1, torch.float64).poly_terms() == 0
+    p64 = plan(x, "thin_plate", 1.0, torch.float64)
+    from paper_1606_07652_amd import _lib as L
+    import ctypes
+    o = L.RbfSolveOpts(30, 60, L.RBF_PC_BLOCK_JACOBI, 1, 0, 0.0)
+    info_c = L.RbfSolveInfo()
+    F = dev(f)
+    lam0 = torch.zeros_like(F)
+    cf = torch.zeros(3, dtype=torch.float64, device="cuda")
+    code = L.load().rbf_interp_solve_poly(p64._h, F.data_ptr(), lam0.data_ptr(), cf.data_ptr(), 1e-6,
+                                          ctypes.byref(o), ctypes.byref(info_c))
+    assert code == RBF_EUNSUPPORTED
+    with pytest.raises(RbfError):
+        p64.solve(F, rtol=1e-6)
