@@ -43,9 +43,10 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
  * (shape = c > 0); Wendland's compactly supported function is (1 - e r)_+^3 (3 e r + 1)
  * (shape = e > 0, support radius 1/e).  The thin-plate spline r^2 log r (0 at r = 0) and r^5
  * of the paper's Fourier-transform table (section 3) have no shape (any positive value is
- * accepted and ignored); they are conditionally positive definite, so rbf_interp_solve,
- * rbf_interp_solve_batch and block-Jacobi reject them (RBF_EUNSUPPORTED: the polynomial
- * augmentation their interpolation needs is not built); products and evaluation work.
+ * accepted and ignored); they are conditionally positive definite, so their interpolation
+ * needs polynomial terms (rbf_interp_solve_poly); rbf_interp_solve, rbf_interp_solve_batch
+ * and block-Jacobi reject them (RBF_EUNSUPPORTED).  Products and evaluation work as for
+ * every kernel.
  *   Only the Gaussian has a band-limited far field in this build.  Multiquadric, inverse
  *   multiquadric, thin-plate and r^5 plans hold a single leaf and the product is the exact
  *   O(N^2) sum through the tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
