@@ -346,8 +346,8 @@ extern "C" int rbf_interp_solve_batch(rbf_batch *batch, const void *f, void *lam
                                       const rbf_solve_opts *opts, rbf_solve_info *info) {
     if (!batch || !f || !lambda) { set_error("rbf_interp_solve_batch: null argument"); return RBF_EINVAL; }
     if (batch->kernel == RBF_THIN_PLATE || batch->kernel == RBF_R5) {
-        set_error("rbf_interp_solve_batch: the thin-plate spline and r^5 need polynomial augmentation, which "
-                  "this build does not provide");
+        set_error("rbf_interp_solve_batch: the thin-plate spline and r^5 need polynomial terms, which only the "
+                  "single-problem rbf_interp_solve_poly provides");
         return RBF_EUNSUPPORTED;
     }
     if (!(rtol > 0 && rtol < 1)) { set_error("rbf_interp_solve_batch: rtol must lie in (0, 1)"); return RBF_EINVAL; }
