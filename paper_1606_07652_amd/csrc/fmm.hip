@@ -1060,7 +1060,10 @@ template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) 
     if constexpr (kExpMfma<T>) p2m_body<T, D, HMAX>(d, lb, smem_raw);
     else p2m_valu_body<T, D, HMAX>(d, lb, smem_raw);
 }
+// The upward pass runs beside the near field (on the plan's second stream); its memory-bound
+// waves take instruction-issue priority over the near field's arithmetic waves on shared CUs.
 template <class T> __global__ void __launch_bounds__(kThreads) k_m2m(Work<T> w) {
+    __builtin_amdgcn_s_setprio(2);
     int lb;
     DescC<T> &d = *resolve(w, lb);
     m2m_body<T>(d, lb);

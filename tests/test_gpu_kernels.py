@@ -345,3 +345,23 @@ def test_augmented_solve_fp32_and_errors():
     assert code == RBF_EUNSUPPORTED
     with pytest.raises(RbfError):
         p64.solve(F, rtol=1e-6)
+
+
+def test_wendland_batched_solve_matches_oracle():
+    """GMRES on a batch of Wendland problems at once: every problem converges, and the
+    oracle's product of its weights reproduces its right-hand side."""
+    from paper_1606_07652_amd import BatchPlan
+    sizes = [1500, 900, 2200]
+    shapes = [12.0, 10.0, 16.0]
+    xs = [uniform_points(m, 3, 540 + k) for k, m in enumerate(sizes)]
+    fs = [np.sin(2 * np.pi * x[:, 0]) + x[:, 1] for x in xs]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print("[batch solve] wendland", flush=True)
+    b = BatchPlan(dev(np.concatenate(xs)), off, shapes, kernel="wendland", tol=1e-6)
+    lam, infos = b.solve(dev(np.concatenate(fs)), rtol=1e-9, restart=50, max_iters=600)
+    lam = lam.cpu().numpy()
+    for k in range(len(sizes)):
+        assert infos[k]["converged"], (k, infos[k])
+        lk = lam[off[k]:off[k + 1]]
+        r = fs[k] - direct.direct_sum(xs[k], lk, "wendland", shapes[k])
+        assert np.linalg.norm(r) <= 2e-9 * np.linalg.norm(fs[k])
