@@ -365,3 +365,33 @@ def test_wendland_batched_solve_matches_oracle():
         lk = lam[off[k]:off[k + 1]]
         r = fs[k] - direct.direct_sum(xs[k], lk, "wendland", shapes[k])
         assert np.linalg.norm(r) <= 2e-9 * np.linalg.norm(fs[k])
+
+
+def test_augmented_solve_edge_cases():
+    """Zero right-hand side (zero weights and coefficients, no iterations); a missing coefficient
+    buffer and an evaluation plan are refused; the positive definite kernels need no buffer."""
+    import ctypes
+    from paper_1606_07652_amd import EvalPlan
+    from paper_1606_07652_amd import _lib as L
+    x = uniform_points(200, 2, 550)
+    p = plan(x, "thin_plate", 1.0, torch.float64)
+    lam, c, info = p.solve_poly(dev(np.zeros(200)), rtol=1e-8, restart=50, max_iters=100)
+    assert info["converged"] and info["iters"] == 0
+    assert torch.count_nonzero(lam).item() == 0 and torch.count_nonzero(c).item() == 0
+    o = L.RbfSolveOpts(50, 100, L.RBF_PC_NONE, 1, 0, 0.0)
+    inf = L.RbfSolveInfo()
+    F = dev(np.ones(200))
+    out = torch.zeros_like(F)
+    code = L.load().rbf_interp_solve_poly(p._h, F.data_ptr(), out.data_ptr(), None, 1e-6, ctypes.byref(o),
+                                          ctypes.byref(inf))
+    assert code == L.RBF_EINVAL
+    g = plan(x, "gaussian", 0.1, torch.float64)
+    code = L.load().rbf_interp_solve_poly(g._h, F.data_ptr(), out.data_ptr(), None, 1e-6, ctypes.byref(o),
+                                          ctypes.byref(inf))
+    assert code in (L.RBF_OK, L.RBF_ENOCONV) and inf.iters > 0
+    e = EvalPlan(dev(x), dev(uniform_points(50, 2, 551)), kernel="thin_plate", shape=1.0, tol=1e-6)
+    code = L.load().rbf_interp_solve_poly(e._h, F.data_ptr(), out.data_ptr(), None, 1e-6, ctypes.byref(o),
+                                          ctypes.byref(inf))
+    assert code == L.RBF_EINVAL
+    with pytest.raises(ValueError):
+        p.solve_poly(dev(np.ones(200)), coeffs=torch.zeros(2, dtype=torch.float64, device="cuda"))
