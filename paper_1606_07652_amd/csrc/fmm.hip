@@ -99,31 +99,31 @@ __host__ __device__ constexpr int l2p_targets(int csize, int dim, int hmax) {
 template <class T> struct KFun;
 
 // 2^t in FP64 by the table-driven reduction of P. T. P. Tang (ACM TOMS 15(2), 1989), for the
-// near field and the direct sum: with s = 64 t rounded to the integer q = 64 k + j
-// (0 <= j < 64) and u = s - q (exact, |u| <= 1/2), 2^t = 2^k 2^(j/64) 2^(u/64); tab holds
-// 2^(j/64) and 2^(u/64) comes from its degree-5 Taylor polynomial, coefficients
-// (ln 2 / 64)^n / n! (truncation below 4e-17 relative).  The argument is s = 64 t; very
+// near field and the direct sum: with s = 256 t rounded to the integer q = 256 k + j
+// (0 <= j < 256) and u = s - q (exact, |u| <= 1/2), 2^t = 2^k 2^(j/256) 2^(u/256); tab holds
+// 2^(j/256) and 2^(u/256) comes from its degree-4 Taylor polynomial, coefficients
+// (ln 2 / 256)^n / n! (truncation below 4e-17 relative).  The argument is s = 256 t; very
 // negative s underflows to 0 in the scaling.
-constexpr double exp2_64_taylor(int n) {
+constexpr int kExpBits = 8, kExpTab = 1 << kExpBits;
+constexpr double exp2_tab_taylor(int n) {
     double c = 1.0;
-    for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / 64.0 / k;
+    for (int k = 1; k <= n; ++k) c *= 0.693147180559945309417232121458176568 / kExpTab / k;
     return c;
 }
-__device__ __forceinline__ double exp2_tab64(double s, const double *tab) {
+__device__ __forceinline__ double exp2_tab(double s, const double *tab) {
     const double qd = rint(s);
     const double u = s - qd;
     const int q = (int)qd;   // saturates; a saturated q gives 2^(huge negative) = 0
-    double p = exp2_64_taylor(5);
-    p = fma(p, u, exp2_64_taylor(4));
-    p = fma(p, u, exp2_64_taylor(3));
-    p = fma(p, u, exp2_64_taylor(2));
-    p = fma(p, u, exp2_64_taylor(1));
+    double p = exp2_tab_taylor(4);
+    p = fma(p, u, exp2_tab_taylor(3));
+    p = fma(p, u, exp2_tab_taylor(2));
+    p = fma(p, u, exp2_tab_taylor(1));
     p = fma(p, u, 1.0);
-    return ldexp(p * tab[q & 63], q >> 6);   // q >> 6 = floor(q / 64)
+    return ldexp(p * tab[q & (kExpTab - 1)], q >> kExpBits);   // q >> 8 = floor(q / 256)
 }
 
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32 (in
-// FP64 the kernels call exp2_tab64 with its LDS table).  Multiquadric sqrt(r^2 + c^2) and inverse
+// FP64 the kernels call exp2_tab with its LDS table).  Multiquadric sqrt(r^2 + c^2) and inverse
 // multiquadric 1/sqrt(r^2 + c^2): coef = c^2.  Wendland's (1 - e r)_+^3 (3 e r + 1) (section 5):
 // coef = e, zero from r = 1/e on.  The thin-plate spline r^2 log r = r^2 log(r^2) / 2 (0 at
 // r = 0) and r^5 have no shape.
@@ -236,13 +236,13 @@ __device__ __forceinline__ void gather_body(DescC<T> &d, const T *__restrict__ l
 //    wave and a quarter wave of source steps instead of two full waves.
 template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 
-// The FP64 Gaussian of the near field goes through exp2_tab64 (coef then carries the factor 64
-// and tab the 64 table entries in LDS); other kernels and FP32 through KFun.
+// The FP64 Gaussian of the near field goes through exp2_tab (coef then carries the factor 256
+// and tab the 256 table entries in LDS); other kernels and FP32 through KFun.
 template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
 
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
 template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, const double *tab) {
-    if constexpr (kTabExp<T, KER>) return exp2_tab64(r2 * coef, tab);
+    if constexpr (kTabExp<T, KER>) return exp2_tab(r2 * coef, tab);
     else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
     else if constexpr (KER == RBF_MULTIQUADRIC) return KFun<T>::mq(r2, coef);
     else if constexpr (KER == RBF_INVERSE_MULTIQUADRIC) return KFun<T>::imq(r2, coef);
@@ -384,12 +384,12 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = d.xs[k * n + (act ? ti : t0)];
     const int r0 = sp[a], r1 = sp[a + 1];
-    __shared__ double tab[kWave];   // 2^(j/64), FP64 Gaussian only
+    __shared__ double tab[kExpTab];   // 2^(j/256), FP64 Gaussian only
     T coef = d.coef;
     if constexpr (kTabExp<T, KER>) {
-        tab[threadIdx.x] = exp2((double)threadIdx.x / kWave);
+        for (int j = threadIdx.x; j < kExpTab; j += kWave) tab[j] = exp2((double)j / kExpTab);
         __syncthreads();
-        coef *= 64;   // exact
+        coef *= kExpTab;   // exact
     }
     const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : T(0);
     T acc;
@@ -417,11 +417,11 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
     T y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
-    __shared__ double tab[kWave];   // 2^(j/64), FP64 Gaussian only (filled before the first barrier)
+    __shared__ double tab[kExpTab];   // 2^(j/256), FP64 Gaussian only (filled before the first barrier)
     T coef = d.coef;
     if constexpr (kTabExp<T, KER>) {
-        if (threadIdx.x < kWave) tab[threadIdx.x] = exp2((double)threadIdx.x / kWave);
-        coef *= 64;   // exact
+        for (int j = threadIdx.x; j < kExpTab; j += kThreads) tab[j] = exp2((double)j / kExpTab);
+        coef *= kExpTab;   // exact
     }
     T acc = 0;
     for (int64_t base = 0; base < n; base += kTile) {
