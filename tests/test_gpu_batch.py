@@ -191,3 +191,33 @@ def test_batched_solve_matches_single_solves(dtype, rtol):
         fq = F[sl].double().cpu().numpy()
         assert np.linalg.norm(fq - u) / np.linalg.norm(fq) <= 10 * rtol
     b.close()
+
+
+def test_more_groups_than_streams():
+    """Eleven problems whose shapes give eleven different padded half grids (the tolerance rule of
+    oracle/params.py): more groups than the batch's eight streams, so groups share streams.  Direct
+    launches and graph replays equal one plan per problem exactly."""
+    from paper_1606_07652_amd import BatchPlan, FmmPlan
+    shapes = [0.004, 0.284, 0.1557, 0.1062, 0.0808, 0.0649, 0.0551, 0.0419, 0.0337, 0.0286, 0.0243]
+    sizes = [1500 + 150 * k for k in range(len(shapes))]
+    pts = [uniform_points(m, 3, 700 + k) for k, m in enumerate(sizes)]
+    lams = [normal_weights(m, 800 + k) for k, m in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = dev(np.concatenate(pts), torch.float64)
+    lam = dev(np.concatenate(lams), torch.float64)
+    print(f"[batch] {len(shapes)} problems, n={off[-1]}", flush=True)
+    b = BatchPlan(X, off, shapes, kernel="gaussian", tol=1e-4, n_max=64)
+    assert b.info()["ngroups"] >= 9
+    b.set_graph(False)
+    u_direct = b.matvec(lam).cpu().numpy()
+    b.set_graph(True)
+    u1 = b.matvec(lam).cpu().numpy()
+    u2 = b.matvec(lam).cpu().numpy()
+    assert np.array_equal(u1, u_direct) and np.array_equal(u2, u_direct)
+    for q in range(len(shapes)):
+        sl = slice(off[q], off[q + 1])
+        p = FmmPlan(X[sl].contiguous(), kernel="gaussian", shape=shapes[q], tol=1e-4, n_max=64)
+        uq = p.matvec(lam[sl].contiguous()).cpu().numpy()
+        assert np.array_equal(u_direct[sl], uq), q
+        p.close()
+    b.close()
