@@ -122,6 +122,26 @@ __device__ __forceinline__ double exp2_tab(double s, const double *tab) {
     return ldexp(p * tab[q & (kExpTab - 1)], q >> kExpBits);   // q >> 8 = floor(q / 256)
 }
 
+// Natural logarithm of a positive normal a by the table-driven method of P. T. P. Tang (ACM TOMS
+// 16(4), 1990): a = 2^e m with m in [1, 2); c = 1 + j/256 the table point at or below m (j the top
+// eight fraction bits); r = (m - c) / c through the tabulated 1/c (m - c is exact), |r| < 2^-8;
+// log a = e ln 2 + log c + log1p(r) with log1p(r) from its Taylor polynomial of degree 6
+// (truncation below 2^-56 / 7).  tab holds log(1 + j/256) then 1 / (1 + j/256).
+constexpr int kLogBits = 8, kLogTab = 1 << kLogBits;
+__device__ __forceinline__ double log_tab(double a, const double *tab) {
+    int e;
+    const double m = 2.0 * frexp(a, &e);   // a = m 2^(e - 1), m in [1, 2)
+    const int j = (int)((m - 1.0) * kLogTab);
+    const double c = 1.0 + j * (1.0 / kLogTab);
+    const double r = (m - c) * tab[kLogTab + j];
+    double p = fma(r, -1.0 / 6.0, 1.0 / 5.0);
+    p = fma(p, r, -0.25);
+    p = fma(p, r, 1.0 / 3.0);
+    p = fma(p, r, -0.5);
+    p = fma(p, r, 1.0);
+    return fma((double)(e - 1), 0.693147180559945309417232121458176568, fma(p, r, tab[j]));
+}
+
 // Gaussian exp(-r^2/(2 s^2)) = 2^(r^2 coef), coef = -log2(e)/(2 s^2): hardware exp2 in FP32 (in
 // FP64 the kernels call exp2_tab with its LDS table).  Multiquadric sqrt(r^2 + c^2) and inverse
 // multiquadric 1/sqrt(r^2 + c^2): coef = c^2.  Wendland's (1 - e r)_+^3 (3 e r + 1) (section 5):
@@ -239,6 +259,20 @@ template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 // The FP64 Gaussian of the near field goes through exp2_tab (coef then carries the factor 256
 // and tab the 256 table entries in LDS); other kernels and FP32 through KFun.
 template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
+// The FP64 thin-plate spline goes through log_tab (tab: its two tables of 256 entries).
+template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
+template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kExpTab;
+// fills the LDS table of the kernel (stride: the workgroup size); a barrier must follow
+template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab, int stride) {
+    if constexpr (kTabExp<T, KER>) {
+        for (int j = threadIdx.x; j < kExpTab; j += stride) tab[j] = exp2((double)j / kExpTab);
+    } else if constexpr (kTabLog<T, KER>) {
+        for (int j = threadIdx.x; j < kLogTab; j += stride) {
+            tab[j] = log1p((double)j / kLogTab);
+            tab[kLogTab + j] = 1.0 / (1.0 + (double)j / kLogTab);
+        }
+    }
+}
 
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
 template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, const double *tab) {
@@ -247,6 +281,7 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
     else if constexpr (KER == RBF_MULTIQUADRIC) return KFun<T>::mq(r2, coef);
     else if constexpr (KER == RBF_INVERSE_MULTIQUADRIC) return KFun<T>::imq(r2, coef);
     else if constexpr (KER == RBF_WENDLAND) return KFun<T>::wendland(r2, coef);
+    else if constexpr (kTabLog<T, KER>) return r2 > 0.0 ? 0.5 * r2 * log_tab(r2, tab) : 0.0;
     else if constexpr (KER == RBF_THIN_PLATE) return KFun<T>::thin_plate(r2);
     else return KFun<T>::r5(r2);
 }
@@ -384,13 +419,13 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = d.xs[k * n + (act ? ti : t0)];
     const int r0 = sp[a], r1 = sp[a + 1];
-    __shared__ double tab[kExpTab];   // 2^(j/256), FP64 Gaussian only
+    __shared__ double tab[kTabLen<T, KER>];   // FP64 Gaussian: 2^(j/256); FP64 thin-plate: log tables
     T coef = d.coef;
-    if constexpr (kTabExp<T, KER>) {
-        for (int j = threadIdx.x; j < kExpTab; j += kWave) tab[j] = exp2((double)j / kExpTab);
+    if constexpr (kTabExp<T, KER> || kTabLog<T, KER>) {
+        fill_tab<T, KER>(tab, kWave);
         __syncthreads();
-        coef *= kExpTab;   // exact
     }
+    if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
     const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : T(0);
     T acc;
     switch (gl) {
@@ -417,12 +452,10 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
     T y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = act ? xs[k * n + ti] : T(0);
-    __shared__ double tab[kExpTab];   // 2^(j/256), FP64 Gaussian only (filled before the first barrier)
+    __shared__ double tab[kTabLen<T, KER>];   // the kernel's table (filled before the first barrier)
     T coef = d.coef;
-    if constexpr (kTabExp<T, KER>) {
-        for (int j = threadIdx.x; j < kExpTab; j += kThreads) tab[j] = exp2((double)j / kExpTab);
-        coef *= kExpTab;   // exact
-    }
+    fill_tab<T, KER>(tab, kThreads);
+    if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
     T acc = 0;
     for (int64_t base = 0; base < n; base += kTile) {
         const int cnt = (int)min((int64_t)kTile, n - base);
