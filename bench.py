@@ -33,7 +33,8 @@ def log(msg):
 
 
 def phase_model(info, dtype_bytes, n):
-    """Algorithmic work of one launch of each phase (documented in the design doc)."""
+    """Algorithmic work of one launch of each phase: flops for the arithmetic phases, compulsory HBM
+    bytes for the memory-bound ones."""
     P = info["half_nodes"]
     d = info["d"]
     nl = info["nleaves"]
@@ -591,8 +592,8 @@ def main():
                     help="with --workload c2mq: the kernel of the exact sum")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs "
+              "is not built", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":

@@ -5,7 +5,7 @@ Definitions followed (Zhao & Stoll, sections 3 and 3.2):
 * Band-limited kernel (eq. 16, 28): Phi_sigma(r) = int_{[-sigma, sigma]^d} C(xi) e^{i xi.r} dxi
   with C = (2 pi)^-d Phi_hat (eq. 5 convention).  The cut-off is the box of eq. (28), with
   unit gain inside (eq. 13 and the low-rank section; the 1/sigma factor of eq. 14 is not
-  applied -- see the readings list in the design doc).
+  applied: it contradicts eq. 13 and the low-rank section, which use unit gain).
 * Quadrature (eq. "quadrature", 29): Phi^Q(r) = sum_m w_m C(xi_m) e^{i xi_m.r}.  Reading of
   the node rule: the paper spaces the nodes Delta xi = 2 sigma / M from -sigma; this oracle
   takes the tensor trapezoid rule on Mn equally spaced nodes from -sigma to +sigma

@@ -3,8 +3,7 @@
 The paper's first FMM step is a hierarchical tree partition of the domain (section 1,
 the list of FMM steps), with groups of points and their neighbour groups (section 4,
 eq. 38: G_b and N_a).  The paper does not fix the tree; this module writes out the
-definition used by the library (listed in the design doc), so that the device tree can be
-compared with it bit for bit:
+definition the library uses, so that the device tree can be compared with it bit for bit:
 
 * Root: the bounding cube of the points.  lo_k = min_i x_ik, ext = max_k (max_i x_ik - lo_k),
   computed in FP64 from the stored values (ext = 1 if all points coincide).
