@@ -7,7 +7,7 @@ tolerance 1e-6 (relative 2-norm error against the exact sum); the FP32 path (tol
 is reported beside it.  A step is one full product (permute, near field, aggregation,
 upward sum, coarse and leaf translation, disaggregation) with inputs resident in HBM.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the bench measures one GPU.
 """
 from __future__ import annotations
 
@@ -353,7 +353,7 @@ def run_c4(args):
 def run_c2mq(args):
     """3-D mixed points (as the default workload), multiquadric (or, with --mq-kernel, inverse
     multiquadric) c = 0.02: the plan holds one leaf and the product is the exact sum through
-    the tiled direct kernel (no band-limited far field for these kernels in this build).  FP64
+    the tiled direct kernel (no band-limited far field for these kernels in this library).  FP64
     and FP32; the oracle checks 2048 targets."""
     import torch
 

@@ -47,7 +47,7 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
  * needs polynomial terms (rbf_interp_solve_poly); rbf_interp_solve, rbf_interp_solve_batch
  * and block-Jacobi reject them (RBF_EUNSUPPORTED).  Products and evaluation work as for
  * every kernel.
- *   Only the Gaussian has a band-limited far field in this build.  Multiquadric, inverse
+ *   Only the Gaussian has a band-limited far field in this library.  Multiquadric, inverse
  *   multiquadric, thin-plate and r^5 plans hold a single leaf and the product is the exact
  *   O(N^2) sum through the tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
  *   support radius wide, with the adjacent cells as the near field and no far field: every

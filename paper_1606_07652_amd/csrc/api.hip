@@ -53,7 +53,7 @@ double band_t(double tol) {
     return hi;
 }
 
-// Multiquadric, inverse multiquadric, thin-plate spline and r^5: this build has no band-limited
+// Multiquadric, inverse multiquadric, thin-plate spline and r^5: this library has no band-limited
 // far field for them (a kernel that grows or decays like a power of r cannot be pruned, and one
 // frequency grid for all levels would have to resolve the finest near-zone width over the whole
 // domain).  Every
