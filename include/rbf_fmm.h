@@ -356,6 +356,20 @@ int rbf_mlp_load(const char *path, rbf_mlp **out);
  * precision RBF_MLP_BF16: the inference kernel (BF16 MFMA, FP32 accumulation);
  * RBF_MLP_F32: the FP32 training kernels.  Enqueued on `stream`. */
 int rbf_mlp_forward(rbf_mlp *mlp, const float *x, int64_t rows, float *y, int precision, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the FP32 forward of rbf_mlp_forward
+ * (precision RBF_MLP_F32; same kernels, same results bit for bit) with its hidden
+ * activations in a fixed static device workspace instead of the network's allocated one.
+ * It calls no hipMalloc, hipFree or allocating library routine.
+ *   x  device float[rows][64], y device float[rows][64] (may not alias x), stream: HIP stream
+ *   0 <= rows <= RBF_MLP_STATIC_MAX_ROWS; more rows -> RBF_EINVAL (split the call).
+ * The workspace (2 x 4096 x 256 floats = 8 MiB per device) is one per device, taken on the
+ * device current at the call, and shared by every call on that device: calls that overlap
+ * in time on one device (different streams, or different host threads without ordering)
+ * race and give wrong results.  Calls on one stream are ordered and safe.  The network and
+ * the arrays must live on the current device. */
+#define RBF_MLP_STATIC_MAX_ROWS 4096
+int rbf_mlp_forward_static(rbf_mlp *mlp, const float *x, int64_t rows, float *y, void *stream);
 /* Loss L = sum_r w_r ||g(x_r) - t_r||^2 / sum_r w_r of the rows (1 <= rows <= 2^20) in
  * FP32 and its gradient dL/dparams.  x, t device float[rows][64], w device float[rows];
  * loss host (may be NULL), grad host float[RBF_MLP_NPARAMS] (may be NULL).  Synchronous. */

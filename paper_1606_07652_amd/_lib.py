@@ -14,6 +14,7 @@ RBF_PC_NONE, RBF_PC_BLOCK_JACOBI, RBF_PC_LEARNED = 0, 1, 2
 RBF_NPHASES = 7
 RBF_PC_BLOCK, RBF_MLP_IN, RBF_MLP_HIDDEN, RBF_MLP_NPARAMS = 64, 64, 256, 164672
 RBF_MLP_BF16, RBF_MLP_F32 = 0, 1
+RBF_MLP_STATIC_MAX_ROWS = 4096
 PHASES = ["permute", "p2p", "p2m", "m2m", "m2l_coarse", "m2l_leaf", "l2p"]
 
 
@@ -113,6 +114,7 @@ SIGNATURES = {
     "rbf_mlp_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "rbf_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "rbf_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int, _P]),
+    "rbf_mlp_forward_static": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "rbf_mlp_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), _P, _P]),
     "rbf_mlp_train": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(RbfTrainOpts), _P,
                                      ctypes.POINTER(RbfTrainInfo)]),

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -701,5 +702,75 @@ extern "C" int rbf_mlp_train(rbf_mlp *m, const float *x, const float *t, const f
     RBF_HIP(hipStreamSynchronize(s));
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
+    return RBF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// FP32 forward without allocation.  The two hidden activation buffers of a call live in
+// `scratch`, a file-scope device array of fixed size; every device the library runs on
+// holds its own copy for the life of the process.  Host code never passes the array's
+// name to a kernel (on the host it only stands for the symbol): the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+
+constexpr int64_t kStaticRows = RBF_MLP_STATIC_MAX_ROWS;
+__device__ __align__(256) float scratch[2 * kStaticRows * HID];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(float **out) {
+    int dev = -1;
+    RBF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("rbf_mlp_forward_static: device %d out of range", dev);
+        return RBF_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        RBF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("rbf_mlp_forward_static: no device address for the scratch array on device %d", dev);
+            return RBF_EHIP;
+        }
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBF_OK;
+}
+
+}  // namespace
+
+extern "C" int rbf_mlp_forward_static(rbf_mlp *m, const float *x, int64_t rows, float *y, void *stream) {
+    if (!m || rows < 0 || (rows > 0 && (!x || !y))) {
+        set_error("rbf_mlp_forward_static: bad arguments");
+        return RBF_EINVAL;
+    }
+    if (rows > kStaticRows) {
+        set_error("rbf_mlp_forward_static: %lld rows exceed the static workspace of %lld rows; "
+                  "split the call", (long long)rows, (long long)kStaticRows);
+        return RBF_EINVAL;
+    }
+    float *ws = nullptr;
+    RBF_TRY(scratch_for_current_device(&ws));
+    if (rows == 0) return RBF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // h0 -> buffer A, h1 -> buffer B, h2 -> buffer A (h0 is dead once h1 is written),
+    // output layer straight into y.  Every row is written before it is read, so nothing
+    // needs clearing; the kernels and their summation order are those of rbf_mlp_forward.
+    float *bufA = ws, *bufB = ws + kStaticRows * HID;
+    const float *in = x;
+    float *outs[3] = {bufA, bufB, bufA};
+    for (int l = 0; l < 3; ++l) {
+        const Layer &L = kLayers[l];
+        RBF_TRY((gemm<false, true, 1>(s, (int)rows, L.out, L.in, L.in, in, L.in, m->params + L.w, L.in, outs[l],
+                                     L.out, 0, m->params + L.b, nullptr, 0)));
+        in = outs[l];
+    }
+    const Layer &L = kLayers[3];
+    RBF_TRY((gemm<false, true, 2>(s, (int)rows, L.out, L.in, L.in, in, L.in, m->params + L.w, L.in, y, L.out, 0,
+                                 m->params + L.b, nullptr, 0)));
     return RBF_OK;
 }

@@ -73,6 +73,14 @@ class Mlp:
                                          _PREC[precision], _stream(x.device)))
         return out
 
+    def forward_static(self, x: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """FP32 forward through rbf_mlp_forward_static (no allocation inside the library;
+        at most RBF_MLP_STATIC_MAX_ROWS rows; `out` is preallocated by the caller)."""
+        rows = x.shape[0]
+        L.check(L.load().rbf_mlp_forward_static(self._h, _f32(x, (rows, BLOCK)), rows, _f32(out, (rows, BLOCK)),
+                                                _stream(x.device)))
+        return out
+
     def loss_grad(self, x: torch.Tensor, t: torch.Tensor, w: torch.Tensor):
         rows = x.shape[0]
         g = np.empty(NPARAMS, np.float32)
