@@ -18,9 +18,15 @@ that it writes out):
 * ``tree``      quantisation, Morton order, adaptive boxes, neighbour (near) lists.
 * ``splitref``  oracle B: the near/far split of eq. (38) evaluated by brute force.
 * ``params``    the rule that turns a tolerance into (band limit, nodes, coarse level).
+* ``bands``     the translation factor from kernel samples (eq. "M2Loperator"), and the
+                split of the multiquadric kernels into Gaussian-mixture scale bands that
+                gives them per-level band limits (section 4.1).
 * ``gmres``     restarted GMRES (cited in section 1) with modified Gram-Schmidt.
-* ``mlp``       FP64 forward/backward of the per-leaf network used as a right
-                preconditioner (not in the paper).
+* ``precond``   block-Jacobi and the FP64 forward/backward of the per-block network used as
+                a right preconditioner (not in the paper).
+* ``poly``      interpolation with polynomial terms for the conditionally positive
+                definite kernels.
+* ``lagrange``  Lagrange interpolation between frequency grids (section 4.1).
 
 Parity status per function is listed in each module header.
 """
