@@ -47,14 +47,21 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
  * needs polynomial terms (rbf_interp_solve_poly); rbf_interp_solve, rbf_interp_solve_batch
  * and block-Jacobi reject them (RBF_EUNSUPPORTED).  Products and evaluation work as for
  * every kernel.
- *   Only the Gaussian has a band-limited far field in this library.  Multiquadric, inverse
- *   multiquadric, thin-plate and r^5 plans hold a single leaf and the product is the exact
- *   O(N^2) sum through the tiled direct kernel.  A Wendland plan is a uniform tree whose cells are at least the
- *   support radius wide, with the adjacent cells as the near field and no far field: every
- *   pair inside the support is a near pair, so the product is exact (a single leaf when no
- *   such level below the root exists).  For these three kernels tol and the tree options are
- *   ignored.  Any plan of one leaf without a far field computes its product with the tiled
- *   direct kernel. */
+ *   The Gaussian has the band-limited far field of one frequency grid.  The multiquadric and
+ *   the inverse multiquadric in 2-D and 3-D have a banded far field: the kernel is split by
+ *   Gaussian width into a short-range residual (summed directly over the adjacent cells of a
+ *   uniform tree whose level is opts->coarse_level, or about 256 points per cell), bands of
+ *   width ratio sqrt 2 (each a decaying Gaussian mixture with its own band limit, coarse
+ *   stencil, node count and factor C from the DFT of its samples: section 4.1's per-level
+ *   band limits and section 3.2's eq. "M2Loperator") and a windowed top band over the whole
+ *   domain; rbf_fmm_band_info reports the bands.  With opts->exact = 1, and in 5-D, their
+ *   plans hold a single leaf and the product is the exact O(N^2) sum through the tiled direct
+ *   kernel, as for the thin-plate spline and r^5.  A Wendland plan is a uniform tree whose
+ *   cells are at least the support radius wide, with the adjacent cells as the near field and
+ *   no far field: every pair inside the support is a near pair, so the product is exact (a
+ *   single leaf when no such level below the root exists).  For Wendland, thin-plate and r^5
+ *   tol and the tree options are ignored.  Any plan of one leaf without a far field computes
+ *   its product with the tiled direct kernel. */
 enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3,
        RBF_THIN_PLATE = 4, RBF_R5 = 5 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
@@ -71,7 +78,9 @@ typedef struct rbf_opts {
     double band;         /* band limit sigma (0 = rule) */
     int    m2l_schedule; /* leaf-translation block order: 0 or 1 = contiguous leaf ranges per
                             XCD (default), 2 = leaf-major over the whole grid */
-    int    reserved[7];
+    int    exact;        /* multiquadric and inverse multiquadric: 1 = exact sum (one leaf, the
+                            tiled direct kernel) instead of the banded far field */
+    int    reserved[6];
 } rbf_opts;
 
 typedef struct rbf_plan rbf_plan;
@@ -199,11 +208,28 @@ typedef struct rbf_plan_info {
     double  lo[5];
     int64_t device_bytes;
     int     far_field;    /* 0 when every kept pair is a near pair (no expansions) */
-    int     reserved;
+    int     nbands;       /* banded plans (multiquadric kernels): scale bands incl. the top */
+    double  residual_width; /* banded plans: Gaussian width s0 below which the kernel is summed
+                               directly over the near field */
 } rbf_plan_info;
 
 /* Parameters and sizes chosen by the plan (host struct). */
 int rbf_fmm_plan_info(const rbf_plan *plan, rbf_plan_info *info);
+
+/* One scale band of a banded plan (section 4.1's per-level band limits, section 3.2's factor
+ * C from kernel samples): band j in [0, nbands); the last is the windowed top band.  Host
+ * struct.  RBF_EINVAL for j out of range. */
+typedef struct rbf_band_info {
+    int     top;              /* 1: the windowed top band (widths >= width_lo) */
+    int     coarse_level, coarse_radius, nodes;
+    int64_t half_nodes;       /* stored nodes per expansion */
+    int     nunits, nchunks;  /* occupied coarse cells; aggregation chunks */
+    double  width_lo, width_hi; /* Gaussian widths of the band (top: width_hi = window width) */
+    double  tol;              /* tolerance relative to the band's largest value */
+    double  band, period, reach, rfar, scale;
+    int     reserved[4];
+} rbf_band_info;
+int rbf_fmm_band_info(const rbf_plan *plan, int j, rbf_band_info *info);
 
 /* Copy the tree to host arrays (for comparison with an independent tree):
  *   perm        host int64[n]: input index of the i-th point in Morton order

@@ -21,7 +21,8 @@ PHASES = ["permute", "p2p", "p2m", "m2m", "m2l_coarse", "m2l_leaf", "l2p"]
 class RbfOpts(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int), ("max_level", ctypes.c_int), ("min_level", ctypes.c_int),
                 ("coarse_level", ctypes.c_int), ("coarse_radius", ctypes.c_int), ("nodes", ctypes.c_int),
-                ("band", ctypes.c_double), ("m2l_schedule", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+                ("band", ctypes.c_double), ("m2l_schedule", ctypes.c_int), ("exact", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
 
 
 class RbfSolveOpts(ctypes.Structure):
@@ -44,7 +45,17 @@ class RbfPlanInfo(ctypes.Structure):
                 ("near_pairs", ctypes.c_int64), ("shape", ctypes.c_double), ("tol", ctypes.c_double),
                 ("band", ctypes.c_double), ("period", ctypes.c_double), ("rcut", ctypes.c_double),
                 ("rfar", ctypes.c_double), ("ext", ctypes.c_double), ("lo", ctypes.c_double * 5),
-                ("device_bytes", ctypes.c_int64), ("far_field", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("device_bytes", ctypes.c_int64), ("far_field", ctypes.c_int), ("nbands", ctypes.c_int),
+                ("residual_width", ctypes.c_double)]
+
+
+class RbfBandInfo(ctypes.Structure):
+    _fields_ = [("top", ctypes.c_int), ("coarse_level", ctypes.c_int), ("coarse_radius", ctypes.c_int),
+                ("nodes", ctypes.c_int), ("half_nodes", ctypes.c_int64), ("nunits", ctypes.c_int),
+                ("nchunks", ctypes.c_int), ("width_lo", ctypes.c_double), ("width_hi", ctypes.c_double),
+                ("tol", ctypes.c_double), ("band", ctypes.c_double), ("period", ctypes.c_double),
+                ("reach", ctypes.c_double), ("rfar", ctypes.c_double), ("scale", ctypes.c_double),
+                ("reserved", ctypes.c_int * 4)]
 
 
 class RbfBatchInfo(ctypes.Structure):
@@ -89,6 +100,7 @@ SIGNATURES = {
     "rbf_fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rbf_last_error": (ctypes.c_char_p, []),
     "rbf_fmm_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RbfPlanInfo)]),
+    "rbf_fmm_band_info": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(RbfBandInfo)]),
     "rbf_fmm_tree_export": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 6),
     "rbf_fmm_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rbf_fmm_phase_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),

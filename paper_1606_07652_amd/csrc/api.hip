@@ -40,11 +40,9 @@ void Arena::release() {
 
 int compute_bbox(rbf_plan *p, const void *points);
 
-namespace {
-
 // Band limit of the Gaussian: s sigma = t with erfc(t / sqrt 2) = tol / 4 (the largest
 // deviation of the band-limited Gaussian from the Gaussian is erfc(s sigma / sqrt 2), at r = 0).
-double band_t(double tol) {
+double band_limit_t(double tol) {
     double lo = 0.0, hi = 40.0, target = tol / 4.0;
     for (int i = 0; i < 200; ++i) {
         double mid = 0.5 * (lo + hi);
@@ -52,6 +50,8 @@ double band_t(double tol) {
     }
     return hi;
 }
+
+namespace {
 
 // Multiquadric, inverse multiquadric, thin-plate spline and r^5: this library has no band-limited
 // far field for them (a kernel that grows or decays like a power of r cannot be pruned, and one
@@ -96,7 +96,28 @@ void wendland_params(rbf_plan *p) {
     }
 }
 
+// Multiquadric and inverse multiquadric in 2-D and 3-D: banded far field.  The near field is a
+// uniform tree (adjacent cells, like the near-only Wendland plan); its level, by default the one
+// with about 256 points per cell on average, sets the residual width and so the finest band.
+void banded_params(rbf_plan *p, const rbf_opts *o) {
+    multiquadric_params(p);
+    const int d = p->d;
+    int l = (int)std::floor(std::log2(std::max(1.0, (double)p->n / 256.0)) / d + 0.5);
+    if (o && o->coarse_level >= 1) l = o->coarse_level;
+    l = std::max(1, std::min(l, 18 / d));
+    p->lc = l;
+    p->r = 1;
+    p->rfar = std::min(2.0 * p->ext / std::ldexp(1.0, l), p->ext);
+    p->rcut = p->rfar;
+    p->max_level = l;
+    p->min_level = l;
+}
+
 int choose_params(rbf_plan *p, const rbf_opts *o) {
+    if (banded_kernel(p->kernel, p->d) && !(o && o->exact)) {
+        banded_params(p, o);
+        return RBF_OK;
+    }
     if (p->kernel == RBF_MULTIQUADRIC || p->kernel == RBF_INVERSE_MULTIQUADRIC || p->kernel == RBF_THIN_PLATE ||
         p->kernel == RBF_R5) {
         multiquadric_params(p);
@@ -108,7 +129,7 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
     }
     const double s = p->shape, tol = p->tol;
     const int d = p->d;
-    p->sigma = (o && o->band > 0) ? o->band : band_t(tol) / s;
+    p->sigma = (o && o->band > 0) ? o->band : band_limit_t(tol) / s;
     p->rcut = s * std::sqrt(2.0 * std::log(4.0 / tol) + 1.0);
     const double margin = s * std::sqrt(2.0 * std::log(4.0 / tol));
     int lmax = 0;
@@ -221,6 +242,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
             rc = RBF_EUNSUPPORTED;
         }
     }
+    if (rc == RBF_OK && banded_kernel(kernel, d) && !(opts && opts->exact)) rc = plan_bands(p);
     const int64_t fboxes = p->far ? 1 : 0;   // expansions are allocated only with a far field
     if (rc == RBF_OK) {
         double need = (double)fboxes * csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) +
@@ -436,6 +458,7 @@ int rbf_fmm_destroy(rbf_plan *plan) {
     if (!plan) return RBF_OK;
     (void)hipStreamSynchronize(plan->stream);
     for (int k = 0; k < 2 * RBF_NPHASES; ++k) if (plan->ev[k]) (void)hipEventDestroy(plan->ev[k]);
+    for (hipEvent_t e : plan->band_ev) if (e) (void)hipEventDestroy(e);
     if (plan->side) (void)hipStreamSynchronize(plan->side);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
@@ -459,7 +482,35 @@ int rbf_fmm_plan_info(const rbf_plan *p, rbf_plan_info *info) {
     info->rcut = p->rcut; info->rfar = p->rfar; info->ext = p->ext;
     for (int k = 0; k < kMaxDim; ++k) info->lo[k] = p->lo[k];
     info->device_bytes = p->arena.bytes + p->solver_arena.bytes + p->pc_arena.bytes;
-    info->far_field = p->far;
+    info->far_field = (p->far || !p->bands.empty()) ? 1 : 0;
+    info->nbands = (int)p->bands.size();
+    info->residual_width = p->res_s0;
+    return RBF_OK;
+}
+
+int rbf_fmm_band_info(const rbf_plan *p, int j, rbf_band_info *info) {
+    if (!p || !info) { set_error("rbf_fmm_band_info: null argument"); return RBF_EINVAL; }
+    if (j < 0 || j >= (int)p->bands.size()) {
+        set_error("rbf_fmm_band_info: band %d out of range (the plan has %d)", j, (int)p->bands.size());
+        return RBF_EINVAL;
+    }
+    const Band &b = p->bands[j];
+    std::memset(info, 0, sizeof(*info));
+    info->top = b.top;
+    info->coarse_level = b.lc;
+    info->coarse_radius = b.r;
+    info->nodes = b.mn;
+    info->half_nodes = b.P;
+    info->nunits = b.nunits;
+    info->nchunks = b.nchunks;
+    info->width_lo = b.s_lo;
+    info->width_hi = b.s_hi;
+    info->tol = b.tau;
+    info->band = b.sigma;
+    info->period = b.L;
+    info->reach = b.reach;
+    info->rfar = b.rfar;
+    info->scale = b.scale;
     return RBF_OK;
 }
 

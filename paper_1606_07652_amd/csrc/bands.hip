@@ -1,0 +1,405 @@
+// Banded far field of the multiquadric kernels: planning (host).
+//
+// The multiquadric sqrt(r^2 + c^2) and the inverse multiquadric 1/sqrt(r^2 + c^2) (the
+// paper's table of global functions) do not decay, or decay like a power, so no single band
+// limit serves every separation.  The paper's multilevel method gives every level its own
+// band limit, scaled with the level's box size (section 4.1, the scaling lemma), and builds
+// the translation factor C from samples of the kernel (section 3.2, eq. "M2Loperator").
+// Here the scales are separated in the kernel itself: both kernels are superpositions of
+// Gaussians exp(-b^2 / (2 s^2)), b = sqrt(r^2 + c^2), over the width s,
+//     sqrt(b^2) = c + sqrt(2/pi) int_0^inf [exp(-c^2/(2 s^2)) - exp(-b^2/(2 s^2))] ds,
+//     1 / b     = sqrt(2/pi) int_0^inf s^-2 exp(-b^2/(2 s^2)) ds,
+// and cutting the width axis at s_0 < s_1 < ... < s_J gives
+//   * the residual (widths below s_0): short-range, summed directly over the adjacent cells
+//     of a uniform tree whose cells are wide enough for it to vanish beyond them;
+//   * bands j (widths in [s_j, s_{j+1}), ratio sqrt 2): Gaussian mixtures, smooth on the
+//     scale s_j and decaying like a Gaussian of width s_{j+1}; each gets the band limit,
+//     period, coarse stencil and node count that the Gaussian far field would get for those
+//     widths, and its C from the DFT of its samples;
+//   * the top band (widths from s_J = 2 ext on): smooth on the scale of the domain, not
+//     decaying; windowed by erfc steps per axis (1 inside the bounding cube, negligible at
+//     the half period) and expanded on one grid over the whole domain.
+// The quadrature kernel of a grid with an even node count is anti-periodic (period L per axis);
+// a band's samples are those of its anti-periodisation (the sum over its images one period
+// apart with alternating signs), so that the DFT gives exactly the coefficients of the
+// function the quadrature kernel reproduces.
+// The sum of the pieces is the kernel exactly; each piece is approximated to a tolerance
+// that splits the requested relative error over the pieces by their size.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace rbf {
+
+double band_limit_t(double tol);   // api.hip: s sigma with erfc(s sigma / sqrt 2) = tol / 4
+
+bool banded_kernel(int kernel, int d) {
+    return (kernel == RBF_MULTIQUADRIC || kernel == RBF_INVERSE_MULTIQUADRIC) && (d == 2 || d == 3);
+}
+
+namespace {
+
+constexpr double kSq2pi = 0.79788456080286535588;   // sqrt(2 / pi)
+constexpr double kRatio = 1.41421356237309504880;   // width ratio of consecutive band edges
+// node counts with a compiled half grid (HP = mn / 2, no padding of the local expansions)
+constexpr int kBandNodes[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+
+int round_nodes(int mn) {
+    for (int v : kBandNodes)
+        if (v >= mn) return v;
+    return 0;
+}
+
+// antiderivative in s of exp(-b^2 / (2 s^2))
+double G(double s, double b) {
+    return s * std::exp(-b * b / (2.0 * s * s)) - b * std::sqrt(M_PI / 2.0) * std::erfc(b / (std::sqrt(2.0) * s));
+}
+
+double band_value(int kernel, double b, double lo, double hi) {
+    if (kernel == RBF_MULTIQUADRIC) return -kSq2pi * (G(hi, b) - G(lo, b));
+    const double r2 = std::sqrt(2.0);
+    return (std::erf(b / (r2 * lo)) - std::erf(b / (r2 * hi))) / b;
+}
+
+double top_value(int kernel, double b, double st) {
+    const double x = b / (std::sqrt(2.0) * st);
+    if (kernel == RBF_MULTIQUADRIC) return b * std::erf(x) + kSq2pi * st * std::exp(-x * x);
+    return std::erf(x) / b;
+}
+
+double kernel_value(int kernel, double r2, double c) {
+    return kernel == RBF_MULTIQUADRIC ? std::sqrt(r2 + c * c) : 1.0 / std::sqrt(r2 + c * c);
+}
+
+// window of the top band along one axis: 1 to within 1e-8 on |t| <= ext, below 1e-12 from
+// |t| = ext + 9 tau on (the half period)
+double window(double t, double ext, double tau) { return 0.5 * std::erfc((std::fabs(t) - (ext + 4.0 * tau)) / tau); }
+
+// Root-mean-square of the kernel over all pairs of an evenly spaced sample of the points
+// (at most 2048 of them, in Morton order): the scale against which the tolerance is split.
+int kernel_rms(rbf_plan *p, double *rms) {
+    const int64_t n = p->n;
+    const int d = p->d;
+    const int m = (int)std::min<int64_t>(n, 2048);
+    const size_t tsz = p->dtype == RBF_F32 ? 4 : 8;
+    std::vector<char> buf((size_t)n * tsz);
+    std::vector<double> x((size_t)m * d);
+    for (int k = 0; k < d; ++k) {
+        RBF_HIP(hipMemcpy(buf.data(), (const char *)p->xs + (size_t)k * n * tsz, (size_t)n * tsz, hipMemcpyDeviceToHost));
+        for (int i = 0; i < m; ++i) {
+            const int64_t j = (int64_t)((double)i * n / m);
+            x[(size_t)i * d + k] = p->dtype == RBF_F32 ? (double)((const float *)buf.data())[j]
+                                                       : ((const double *)buf.data())[j];
+        }
+    }
+    double acc = 0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double r2 = 0;
+            for (int k = 0; k < d; ++k) {
+                const double t = x[(size_t)i * d + k] - x[(size_t)j * d + k];
+                r2 += t * t;
+            }
+            const double v = kernel_value(p->kernel, r2, p->shape);
+            acc += v * v;
+        }
+    *rms = std::sqrt(acc / ((double)m * m));
+    return RBF_OK;
+}
+
+// w(xi) C(xi) for the stored nodes of a band: C from the DFT of the band's samples over one
+// period (eq. "M2Loperator" in physical units: C(xi) = (h / 2 pi)^d sum_q K(q h) e^{-i h q.xi},
+// h = pi / sigma, the mn - 1 offsets q = -(mn-2)/2 .. (mn-2)/2 per axis), with K even in every
+// coordinate so that the DFT is a cosine transform along each axis; times the tensor
+// trapezoid weights.  Stored nodes: row digits m_1..m_{d-1} (any order: K is symmetric under
+// permutations of the axes, so C is too) and m_d = H + h.
+std::vector<double> band_table(const rbf_plan *p, const Band &b) {
+    const int d = p->d, mn = b.mn, Q = mn - 1;
+    const double dxi = 2.0 * b.sigma / (mn - 1);
+    const double h = M_PI / b.sigma;
+    std::vector<double> qx(Q), xi(mn), w(mn);
+    for (int i = 0; i < Q; ++i) qx[i] = (i - (mn - 2) / 2) * h;
+    for (int m = 0; m < mn; ++m) {
+        xi[m] = -b.sigma + m * dxi;
+        w[m] = (m == 0 || m == mn - 1) ? 0.5 * dxi : dxi;
+    }
+    // samples of the piece the quadrature kernel reproduces.  With an even node count the
+    // nodes are odd multiples of dxi / 2, so e^{i xi (r + L)} = -e^{i xi r}: the kernel is
+    // anti-periodic with period L along every axis (the (-1)^n of the Poisson sum).  A band
+    // is therefore summed over its images r + n L with the sign prod_k (-1)^{n_k}, within its
+    // reach (a coarse band's period can be shorter than its decay); the windowed top band
+    // vanishes beyond the half period and is sampled as it is.
+    int64_t nq = 1;
+    for (int k = 0; k < d; ++k) nq *= Q;
+    std::vector<double> K(nq);
+    const double c = p->shape, L = b.L;
+    const int nimg = b.top ? 0 : (int)std::ceil((b.reach + 0.5 * L) / L);
+    int64_t nimages = 1;
+    for (int k = 0; k < d; ++k) nimages *= 2 * nimg + 1;
+    for (int64_t s = 0; s < nq; ++s) {
+        double t[kMaxDim];
+        int64_t rest = s;
+        for (int k = 0; k < d; ++k) {
+            t[k] = qx[rest % Q];
+            rest /= Q;
+        }
+        if (b.top) {
+            double r2 = 0, win = 1.0;
+            for (int k = 0; k < d; ++k) {
+                r2 += t[k] * t[k];
+                win *= window(t[k], p->ext, b.s_hi);
+            }
+            K[s] = top_value(p->kernel, std::sqrt(r2 + c * c), b.s_lo) * win;
+            continue;
+        }
+        double acc = 0;
+        for (int64_t im = 0; im < nimages; ++im) {
+            int64_t ir = im;
+            double r2 = 0;
+            int odd = 0;
+            for (int k = 0; k < d; ++k) {
+                const int nk = (int)(ir % (2 * nimg + 1)) - nimg;
+                ir /= 2 * nimg + 1;
+                const double v = t[k] + L * (double)nk;
+                r2 += v * v;
+                odd ^= nk & 1;
+            }
+            if (r2 > b.reach * b.reach) continue;   // below the band's tolerance
+            const double v = band_value(p->kernel, std::sqrt(r2 + c * c), b.s_lo, b.s_hi);
+            acc += odd ? -v : v;
+        }
+        K[s] = acc;
+    }
+    // cosine transform along each axis: axis 0 is the fastest index of K; each pass maps the
+    // fastest axis from Q samples to mn nodes and rotates it to the slowest position
+    std::vector<double> A((size_t)Q * mn);
+    for (int i = 0; i < Q; ++i)
+        for (int m = 0; m < mn; ++m) A[(size_t)i * mn + m] = std::cos(qx[i] * xi[m]);
+    std::vector<double> cur = K, nxt;
+    int64_t rest_len = nq / Q;   // product of the other axes' current lengths
+    int fast = Q;
+    for (int k = 0; k < d; ++k) {
+        nxt.assign((size_t)rest_len * mn, 0.0);
+        // cur[rest][fast] (fast index i), out[m][rest]: the transformed axis becomes the slowest
+        for (int64_t rr = 0; rr < rest_len; ++rr) {
+            const double *src = cur.data() + rr * fast;
+            for (int m = 0; m < mn; ++m) {
+                double acc = 0;
+                for (int i = 0; i < fast; ++i) acc += src[i] * A[(size_t)i * mn + m];
+                nxt[(size_t)m * rest_len + rr] = acc;
+            }
+        }
+        cur.swap(nxt);
+        // the new fastest axis is the next untransformed one (length Q) unless all are done
+        if (k + 1 < d) {
+            rest_len = (int64_t)cur.size() / Q;
+            fast = Q;
+        }
+    }
+    // cur is now indexed [m_{d-1}]...[m_0] with m_0 slowest: index = sum m_k mn^(d-1-k)... every
+    // axis has length mn and C is symmetric in the axes, so the order of the digits is immaterial
+    const double scale = std::pow(h / (2.0 * M_PI), d);
+    std::vector<double> wt(b.P);
+    for (int64_t q = 0; q < b.P; ++q) {
+        const int hh = (int)(q % b.H);
+        int64_t rest = q / b.H;
+        int64_t idx = b.H + hh;
+        double wgt = w[b.H + hh];
+        int64_t stride = mn;
+        for (int k = 0; k < d - 1; ++k) {
+            const int m = (int)(rest % mn);
+            rest /= mn;
+            idx += m * stride;
+            stride *= mn;
+            wgt *= w[m];
+        }
+        wt[q] = scale * cur[idx] * wgt;
+    }
+    return wt;
+}
+
+int upload(Arena &ar, void **dst, const void *src, size_t bytes) {
+    RBF_TRY(ar.alloc(dst, bytes));
+    RBF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return RBF_OK;
+}
+
+// Grid of a band: the cheapest (coarse level, radius, nodes) whose stencil holds every pair
+// closer than the band's reach and whose period exceeds the stencil by the band's margin.
+bool choose_grid(const rbf_plan *p, Band &b, double margin) {
+    const int d = p->d;
+    double best = INFINITY;
+    for (int l = 0; l <= p->lc; ++l) {
+        int r = 0;
+        double rfar = p->ext;
+        if (l >= 1) {
+            const double w = p->ext / std::ldexp(1.0, l);
+            r = 1 + (int)std::floor(b.reach / w);
+            rfar = (r + 1) * w;
+            if (rfar >= p->ext) continue;   // the whole domain: level 0 does it with one cell
+        }
+        const double L = rfar + margin;
+        const int mn = round_nodes((int)std::ceil(b.sigma * L / M_PI) + 1);
+        if (mn == 0) continue;
+        int64_t P = mn / 2;
+        for (int k = 0; k < d - 1; ++k) P *= mn;
+        const double cells = std::ldexp(1.0, d * l);
+        const double cost = (double)P * ((double)p->n + 8.0 * cells);
+        if (cost < best) {
+            best = cost;
+            b.lc = l;
+            b.r = r;
+            b.rfar = rfar;
+            b.mn = mn;
+        }
+    }
+    return best < INFINITY;
+}
+
+}  // namespace
+
+int plan_bands(rbf_plan *p) {
+    const int d = p->d, kernel = p->kernel;
+    const double ext = p->ext, c = p->shape, tol = p->tol;
+    const double wn = ext / std::ldexp(1.0, p->lc);
+    // residual: negligible (x = b / (sqrt 2 s0) >= xcut) beyond the adjacent cells
+    const double xcut = std::sqrt(std::log(1.0 / tol) + 4.0);
+    p->res_s0 = wn / (std::sqrt(2.0) * xcut);
+    RBF_TRY(kernel_rms(p, &p->phi_rms));
+    const double s_top = 2.0 * ext;
+    std::vector<double> edges{p->res_s0};
+    while (edges.back() * kRatio * 1.1 < s_top) edges.push_back(edges.back() * kRatio);
+    edges.push_back(s_top);
+    const int J = (int)edges.size() - 1;
+    // Tolerance of a piece relative to its largest value: the requested relative error times
+    // the kernel's rms over pairs, split over the pieces (bands, top, residual) as independent
+    // errors, with a factor 4 for what the band-limit rule does not count (the truncated
+    // spectrum in each of the d axes, and the aliasing of the sampled C, which doubles it at
+    // the edge of the grid).
+    const double split = 4.0 * std::sqrt((double)(J + 2));
+    auto tau_for = [&](double mag) { return std::min(1e-2, std::max(1e-3 * tol, tol * p->phi_rms / (mag * split))); };
+    std::vector<Band> bands;
+    for (int j = 0; j < J; ++j) {
+        Band b;
+        b.s_lo = edges[j];
+        b.s_hi = edges[j + 1];
+        const double mag = std::fabs(band_value(kernel, c, b.s_lo, b.s_hi));
+        b.scale = mag;
+        b.tau = tau_for(mag);
+        b.sigma = band_limit_t(b.tau) / b.s_lo;
+        b.reach = b.s_hi * std::sqrt(2.0 * std::log(4.0 / b.tau) + 1.0);
+        const double margin = b.s_hi * std::sqrt(2.0 * std::log(4.0 / b.tau));
+        if (!choose_grid(p, b, margin)) {
+            set_error("rbf_fmm_plan: band %d (widths %g..%g) needs more than 64 nodes per dimension at tol %g", j,
+                      b.s_lo, b.s_hi, tol);
+            return RBF_EUNSUPPORTED;
+        }
+        b.L = M_PI * (b.mn - 1) / b.sigma;
+        bands.push_back(b);
+    }
+    {
+        Band b;
+        b.top = 1;
+        b.s_lo = s_top;
+        b.s_hi = 1.4 * s_top;   // window width
+        const double bmax = std::sqrt((double)d) * ext + c;
+        const double mag = kernel == RBF_MULTIQUADRIC ? top_value(kernel, bmax, s_top) : top_value(kernel, c, s_top);
+        b.scale = mag;
+        b.tau = tau_for(mag);
+        b.L = 2.0 * (ext + 9.0 * b.s_hi);
+        const double sig = band_limit_t(b.tau) / (1.2 * s_top);
+        b.mn = round_nodes((int)std::ceil(sig * b.L / M_PI) + 1);
+        if (b.mn == 0) {
+            set_error("rbf_fmm_plan: the top band needs more than 64 nodes per dimension at tol %g", tol);
+            return RBF_EUNSUPPORTED;
+        }
+        b.sigma = M_PI * (b.mn - 1) / b.L;   // the window fixes the period
+        b.reach = INFINITY;
+        b.lc = 0;
+        b.r = 0;
+        b.rfar = ext;
+        bands.push_back(b);
+    }
+    // units, chunks and tasks per band from the uniform leaves (all at level p->lc)
+    const int nl = p->nleaves;
+    std::vector<int> lb(nl + 1);
+    std::vector<uint64_t> pre(nl);
+    RBF_HIP(hipMemcpy(lb.data(), p->leaf_begin, sizeof(int) * (nl + 1), hipMemcpyDeviceToHost));
+    RBF_HIP(hipMemcpy(pre.data(), p->leaf_prefix, sizeof(uint64_t) * nl, hipMemcpyDeviceToHost));
+    Arena &ar = p->arena;
+    int64_t maxW = 0, maxLx = 0, maxC = 0, maxHP = 0;
+    for (Band &b : bands) {
+        b.H = b.mn / 2;
+        b.HP = b.H;
+        b.R = 1;
+        for (int k = 0; k < d - 1; ++k) b.R *= b.mn;
+        b.P = b.R * b.H;
+        b.ncells = (int64_t)1 << (d * b.lc);
+        const int sh = d * (p->lc - b.lc);
+        std::vector<int> ub, ucell, cb, ccell, cellb(b.ncells + 1, 0);
+        std::vector<int> task;
+        for (int a = 0; a < nl;) {
+            const uint64_t cell = pre[a] >> sh;
+            int e = a;
+            while (e < nl && (pre[e] >> sh) == cell) ++e;
+            const int u = (int)ucell.size();
+            ub.push_back(lb[a]);
+            ucell.push_back((int)cell);
+            for (int t = lb[a]; t < lb[e]; t += kBandChunk) {
+                cb.push_back(t);
+                ccell.push_back((int)cell);
+            }
+            for (int t = 0; t < lb[e] - lb[a]; t += kWave) {
+                task.push_back(u);
+                task.push_back(t);
+            }
+            a = e;
+        }
+        ub.push_back(lb[nl]);
+        b.nunits = (int)ucell.size();
+        b.nchunks = (int)cb.size();
+        cb.push_back(lb[nl]);
+        b.ntasks = (int)(task.size() / 2);
+        // chunk range of every dense cell (chunks are in cell order)
+        for (int64_t cc = 0; cc <= b.ncells; ++cc)
+            cellb[cc] = (int)(std::lower_bound(ccell.begin(), ccell.end(), (int)std::min<int64_t>(cc, INT32_MAX)) -
+                              ccell.begin());
+        cellb[b.ncells] = b.nchunks;
+        b.ngroups = (b.nunits + 7) / 8;
+        std::vector<int> gf(b.ngroups + 1), up(b.ngroups + 1, 0), pad(16, 0);
+        for (int g = 0; g <= b.ngroups; ++g) gf[g] = std::min(8 * g, b.nunits);
+        const std::vector<double> wt = band_table(p, b);
+        RBF_TRY(upload(ar, (void **)&b.unit_begin, ub.data(), sizeof(int) * ub.size()));
+        RBF_TRY(upload(ar, (void **)&b.unit_cell, ucell.data(), sizeof(int) * ucell.size()));
+        RBF_TRY(upload(ar, (void **)&b.chunk_begin, cb.data(), sizeof(int) * cb.size()));
+        RBF_TRY(upload(ar, (void **)&b.cell_begin, cellb.data(), sizeof(int) * cellb.size()));
+        RBF_TRY(upload(ar, (void **)&b.tasks, task.data(), sizeof(int) * task.size()));
+        RBF_TRY(upload(ar, (void **)&b.grp_first, gf.data(), sizeof(int) * gf.size()));
+        RBF_TRY(upload(ar, (void **)&b.uni_ptr, up.data(), sizeof(int) * up.size()));
+        RBF_TRY(upload(ar, (void **)&b.uni_pad, pad.data(), sizeof(int) * pad.size()));
+        RBF_TRY(upload(ar, (void **)&b.wtab, wt.data(), sizeof(double) * wt.size()));
+        maxW = std::max<int64_t>(maxW, (int64_t)b.nchunks * b.P);
+        maxLx = std::max<int64_t>(maxLx, (int64_t)b.nunits * b.R * b.HP);
+        maxC = std::max<int64_t>(maxC, b.ncells * b.P);
+        maxHP = std::max<int64_t>(maxHP, b.HP);
+    }
+    const size_t csz = p->dtype == RBF_F32 ? 8 : 16;
+    const double need = (double)csz * (maxW + maxLx + 3.0 * maxC + (double)maxHP * p->n);
+    if (need > 200e9) {
+        set_error("rbf_fmm_plan: band expansions need %.1f GB; raise tol", need / 1e9);
+        return RBF_ENOMEM;
+    }
+    RBF_TRY(ar.alloc(&p->bW, csz * maxW));
+    RBF_TRY(ar.alloc(&p->bLx, csz * maxLx));
+    RBF_TRY(ar.alloc(&p->bWc, csz * maxC));
+    RBF_TRY(ar.alloc(&p->bLc, csz * maxC));
+    RBF_TRY(ar.alloc(&p->bTmp, csz * maxC));
+    RBF_TRY(ar.alloc(&p->bdl, csz * maxHP * p->n));
+    p->bands = std::move(bands);
+    return RBF_OK;
+}
+
+}  // namespace rbf

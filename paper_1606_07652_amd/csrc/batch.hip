@@ -26,13 +26,30 @@ namespace {
 int pow2i(int l) { return 1 << l; }
 
 // Candidate configurations for the autotuner.
-std::vector<rbf_opts> candidates(const rbf_opts *base, int64_t n, int d, double shape, double tol, double ext) {
+std::vector<rbf_opts> candidates(const rbf_opts *base, int64_t n, int d, int kernel, double shape, double tol,
+                                 double ext) {
     std::vector<rbf_opts> out;
     rbf_opts o;
     std::memset(&o, 0, sizeof(o));
     if (base) o = *base;
     o.coarse_level = base ? base->coarse_level : -1;
     o.coarse_radius = base ? base->coarse_radius : -1;
+    if (banded_kernel(kernel, d) && !o.exact) {
+        // banded far field: the level of the near field's uniform tree around the default
+        // (about 256 points per cell), and the exact sum when it stays small enough to time
+        const int l0 = (int)std::floor(std::log2(std::max(1.0, (double)n / 256.0)) / d + 0.5);
+        for (int l = std::max(1, l0 - 1); l <= std::min(l0 + 1, 18 / d); ++l) {
+            rbf_opts c = o;
+            c.coarse_level = l;
+            out.push_back(c);
+        }
+        if (n <= (1 << 17)) {
+            rbf_opts c = o;
+            c.exact = 1;
+            out.push_back(c);
+        }
+        return out;
+    }
     for (int nm : {64, 128, 256, 512}) {
         rbf_opts c = o;
         c.n_max = nm;
@@ -121,7 +138,7 @@ int autotune_impl(const void *points, int64_t n, int d, int dtype, int kernel, d
                   const rbf_opts *base, int reps, hipStream_t s, bool for_batch, rbf_opts *best, double *best_ms) {
     double ext = 1.0;
     RBF_TRY(bbox_ext(points, n, d, dtype, s, &ext));
-    auto cands = candidates(base, n, d, shape, tol, ext);
+    auto cands = candidates(base, n, d, kernel, shape, tol, ext);
     const size_t tsz = dtype == RBF_F32 ? 4 : 8;
     void *lam = nullptr, *u = nullptr;
     RBF_HIP(hipMalloc(&lam, tsz * n));
@@ -330,6 +347,9 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
         std::memset(&o, 0, sizeof(o));
         if (opts) o = *opts;
         else { o.coarse_level = -1; o.coarse_radius = -1; }
+        // a batch runs the per-phase kernels of one frequency grid per problem: the banded far
+        // field of the multiquadric kernels is not batched, they take the exact sum
+        if (banded_kernel(kernel, d)) o.exact = 1;
         if (autotune) {
             double ms = 0;
             rc = autotune_impl(pq, nq, d, dtype, kernel, shapes[q], tol, &o, 2, b->stream, true, &o, &ms);

@@ -261,7 +261,9 @@ template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
 // The FP64 thin-plate spline goes through log_tab (tab: its two tables of 256 entries).
 template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
-template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kExpTab;
+// The residual kernels of a banded plan read their two constants from tab.
+template <int KER> constexpr bool kRes = KER == kResMQ || KER == kResIMQ;
+template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kRes<KER> ? 2 : kExpTab;
 // fills the LDS table of the kernel (stride: the workgroup size); a barrier must follow
 template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab, int stride) {
     if constexpr (kTabExp<T, KER>) {
@@ -274,9 +276,21 @@ template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab
     }
 }
 
+// Residual of the scale split of the multiquadric kernels (every Gaussian width below s0):
+// with b = sqrt(r^2 + c^2) and x = b / (sqrt 2 s0), the multiquadric's is
+// b erfc(x) - sqrt(2/pi) s0 e^{-x^2} and the inverse multiquadric's erfc(x) / b.
+// tab[0] = 1 / (sqrt 2 s0), tab[1] = sqrt(2/pi) s0; c2 = c^2.
+template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab) {
+    const T b = sqrt(r2 + c2);
+    const T x = b * (T)tab[0];
+    if constexpr (KER == kResMQ) return b * erfc(x) - (T)tab[1] * exp(-x * x);
+    else return erfc(x) / b;
+}
+
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
 template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, const double *tab) {
-    if constexpr (kTabExp<T, KER>) return exp2_tab(r2 * coef, tab);
+    if constexpr (kRes<KER>) return kres<T, KER>(r2, coef, tab);
+    else if constexpr (kTabExp<T, KER>) return exp2_tab(r2 * coef, tab);
     else if constexpr (KER == RBF_GAUSSIAN) return KFun<T>::gauss(r2, coef);
     else if constexpr (KER == RBF_MULTIQUADRIC) return KFun<T>::mq(r2, coef);
     else if constexpr (KER == RBF_INVERSE_MULTIQUADRIC) return KFun<T>::imq(r2, coef);
@@ -309,12 +323,24 @@ __device__ __forceinline__ T dist2(const T (&y)[D], const T (&x)[D]) {
 }
 
 // One step of S sources for the wave's targets.  Wendland's function vanishes from r = 1/e on
-// (cut2 = 1/e^2): when no source of the step lies inside the support of any target of the
-// wave, the step adds only zeros and is skipped (a wave-uniform branch).
+// (cut2 = 1/e^2), and the residual kernels of banded plans are negligible from r^2 = cut2 on:
+// when no source of the step lies inside that radius of any target of the wave, the step
+// adds only zeros and is skipped (a wave-uniform branch).
 template <class T, int D, int KER, int S>
 __device__ __forceinline__ T p2p_step(const T (&y)[D], const T (&x)[S][D], const T (&w)[S], T coef, T cut2,
                                       const double *tab, T acc) {
-    if constexpr (KER == RBF_WENDLAND) {
+    if constexpr (kRes<KER>) {
+        T r2[S];
+#pragma unroll
+        for (int v = 0; v < S; ++v) r2[v] = dist2<T, D>(y, x[v]);
+        T mn = r2[0];
+#pragma unroll
+        for (int v = 1; v < S; ++v) mn = min(mn, r2[v]);
+        if (__any(mn < cut2)) {
+#pragma unroll
+            for (int v = 0; v < S; ++v) acc = fma(w[v], kres<T, KER>(r2[v], coef, tab), acc);
+        }
+    } else if constexpr (KER == RBF_WENDLAND) {
         T r2[S];
 #pragma unroll
         for (int v = 0; v < S; ++v) r2[v] = dist2<T, D>(y, x[v]);
@@ -425,8 +451,15 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
         fill_tab<T, KER>(tab, kWave);
         __syncthreads();
     }
+    if constexpr (kRes<KER>) {
+        if (threadIdx.x == 0) {
+            tab[0] = d.res_a;
+            tab[1] = d.res_b;
+        }
+        __syncthreads();
+    }
     if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
-    const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : T(0);
+    const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : kRes<KER> ? (T)d.res_cut2 : T(0);
     T acc;
     switch (gl) {
         case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1, coef, cut2, tab); break;
@@ -514,7 +547,7 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
     const int mn = d.mn, R = d.R, CH = d.p2m_ch;
     const int ST = DM * mn;
     const int a = bid / d.wpl, part = bid % d.wpl;
-    const int t0 = d.leaf_begin[a], t1 = d.src_end[a];   // the leaf's sources
+    const int t0 = d.p2m_begin[a], t1 = d.p2m_end[a];   // the unit's sources
     const int row = part * blockDim.x + threadIdx.x;
     const bool act = row < R;
     const int64_t n = d.n;
@@ -621,7 +654,7 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
     const int mn = d.mn, R = d.R, CH = d.p2m_ch, H = d.H;
     const int ST = DM * mn;
     const int a = bid / d.wpl, part = bid % d.wpl;
-    const int t0 = d.leaf_begin[a], t1 = d.src_end[a];   // the leaf's sources
+    const int t0 = d.p2m_begin[a], t1 = d.p2m_end[a];   // the unit's sources
     const int64_t n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, jsel = lane >> 5, csel = (lane >> 4) & 1;
@@ -1019,7 +1052,8 @@ __device__ __forceinline__ void l2p_body(DescC<T> &d, T *__restrict__ u, int bid
     if (tid < nt) {
         const T sum = ((red[tid] + red[NT + tid]) + red[2 * NT + tid]) + red[3 * NT + tid];
         const int ti = tb + tid;
-        u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * sum;
+        if (d.l2p_acc) d.u_s[ti] = d.u_s[ti] + T(2) * sum;   // a band before the last
+        else u[d.off + d.perm[ti]] = d.u_s[ti] + T(2) * sum;
     }
 }
 
@@ -1149,7 +1183,7 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
         case PH_P2P: return d.nptasks;
         case PH_L2P:
             return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
-        case PH_P2M: return (int64_t)d.nleaves * d.wpl;
+        case PH_P2M: return (int64_t)d.p2m_n * d.wpl;
         case PH_M2M: return d.ncells * nch;
         case PH_M2L_AXIS: return (axis_by_lines(d.lc) ? d.ncells >> d.lc : d.ncells) * nch;
         case PH_M2L_LEAF: {
@@ -1177,6 +1211,8 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_INVERSE_MULTIQUADRIC: k_p2p<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
                 case RBF_WENDLAND: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
                 case RBF_THIN_PLATE: k_p2p<T, D, RBF_THIN_PLATE><<<g, kWave, 0, s>>>(w); break;
+                case kResMQ: k_p2p<T, D, kResMQ><<<g, kWave, 0, s>>>(w); break;
+                case kResIMQ: k_p2p<T, D, kResIMQ><<<g, kWave, 0, s>>>(w); break;
                 default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
             }
             break;
@@ -1371,7 +1407,206 @@ int direct_t(rbf_plan *p, const void *lam, void *u) {
     return RBF_EUNSUPPORTED;
 }
 
+// ---- banded far field (multiquadric kernels) -------------------------------------------
+// The product of a banded plan: the near field sums the residual kernel over the adjacent
+// cells of the uniform tree into u_s (on the side stream when there is one), then every band
+// runs aggregation, upward sum, coarse stencil, translation (empty near lists: the band
+// covers near and far pairs alike) and disaggregation, each adding its far field to u_s; the
+// last band writes u = u_s + its far field in caller order.
+
+template <class T> void fill_band_desc(const rbf_plan *p, const Band &b, bool acc, Desc<T> *d) {
+    using C = typename cplx<T>::type;
+    fill_desc<T>(p, d);
+    d->leaf_begin = b.unit_begin;
+    d->src_end = b.unit_begin + 1;
+    d->leaf_cell = b.unit_cell;
+    d->cell_begin = b.cell_begin;
+    d->tasks = b.tasks;
+    d->ntasks = b.ntasks;
+    d->nptasks = 0;
+    d->nleaves = b.nunits;
+    d->ncells = b.ncells;
+    d->lc = b.lc;
+    d->r = b.r;
+    d->mn = b.mn;
+    d->H = b.H;
+    d->HP = b.HP;
+    d->R = (int)b.R;
+    d->P = b.P;
+    const double dxi = 2.0 * b.sigma / (b.mn - 1);
+    d->dxi = dxi;
+    d->xi0 = -b.sigma;
+    d->xiH = -b.sigma + b.H * dxi;
+    d->W = (C *)p->bW;
+    d->Lx = (C *)p->bLx;
+    d->Wc = (C *)p->bWc;
+    d->Lc = (C *)p->bLc;
+    d->Tmp = (C *)p->bTmp;
+    d->dl = (C *)p->bdl;
+    d->wtab = b.wtab;
+    set_p2m_shape<T>(d, p->d, b.R, b.mn, b.HP);
+    d->far = 1;
+    d->ngroups = b.ngroups;
+    d->grp_first = b.grp_first;
+    d->uni_ptr = b.uni_ptr;
+    d->uni_idx = b.uni_pad;
+    d->uni_mask = b.uni_pad;
+    d->mn_magic = (unsigned)((1ull << 32) / (unsigned)b.mn + 1);
+    d->p2m_begin = b.chunk_begin;
+    d->p2m_end = b.chunk_begin + 1;
+    d->p2m_n = b.nchunks;
+    d->l2p_acc = acc ? 1 : 0;
+}
+
+// Phase timing of a banded product: event pair k of band j at band_ev[(j * NPHASES + k) * 2].
+struct BandTimer {
+    rbf_plan *p;
+    int j = 0, k = 0;
+    hipStream_t st = nullptr;
+    explicit BandTimer(rbf_plan *pp) : p(pp && pp->profiling ? pp : nullptr) {}
+    hipError_t begin(int kk, hipStream_t s) {
+        k = kk;
+        st = s;
+        return p ? hipEventRecord(p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2], s) : hipSuccess;
+    }
+    hipError_t end() { return p ? hipEventRecord(p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2 + 1], st) : hipSuccess; }
+};
+
+template <class T, int D, int HMAX>
+int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
+    int64_t nb[PH_COUNT];
+    for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
+    const size_t sh = p2m_shmem<T>(w.one, D);
+    const int kernel = RBF_GAUSSIAN;   // unused by the far-field phases
+    RBF_HIP(bt.begin(2, s));
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_PHASE_DL, nb[PH_PHASE_DL], s, 0, 0, kernel)));
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_P2M, nb[PH_P2M], s, 0, sh, kernel)));
+    RBF_HIP(bt.end());
+    RBF_HIP(bt.begin(3, s));
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2M, nb[PH_M2M], s, 0, 0, kernel)));
+    RBF_HIP(bt.end());
+    RBF_HIP(bt.begin(4, s));
+    for (int ax = 0; ax < D; ++ax)
+        RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_AXIS, nb[PH_M2L_AXIS], s, ax, 0, kernel)));
+    RBF_HIP(bt.end());
+    RBF_HIP(bt.begin(5, s));
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_LEAF, nb[PH_M2L_LEAF], s, 0, 0, kernel)));
+    RBF_HIP(bt.end());
+    if (join) RBF_HIP(hipStreamWaitEvent(s, join, 0));   // u_s holds the near field from here on
+    RBF_HIP(bt.begin(6, s));
+    RBF_TRY((launch_phase<T, D, HMAX>(w, PH_L2P, nb[PH_L2P], s, 0, 0, kernel)));
+    RBF_HIP(bt.end());
+    return RBF_OK;
+}
+
+template <class T, int D>
+int run_band_hp(int HP, const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
+    switch (HP) {
+        case 4: return run_band<T, D, 4>(w, s, join, bt);
+        case 6: return run_band<T, D, 6>(w, s, join, bt);
+        case 8: return run_band<T, D, 8>(w, s, join, bt);
+        case 10: return run_band<T, D, 10>(w, s, join, bt);
+        case 12: return run_band<T, D, 12>(w, s, join, bt);
+        case 14: return run_band<T, D, 14>(w, s, join, bt);
+        case 16: return run_band<T, D, 16>(w, s, join, bt);
+        case 20: return run_band<T, D, 20>(w, s, join, bt);
+        case 24: return run_band<T, D, 24>(w, s, join, bt);
+        case 28: return run_band<T, D, 28>(w, s, join, bt);
+        case 32: return run_band<T, D, 32>(w, s, join, bt);
+    }
+    set_error("padded half grid %d not compiled for banded products", HP);
+    return RBF_EUNSUPPORTED;
+}
+
+template <class T, int D>
+int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
+    Work<T> w{};
+    fill_desc<T>(p, &w.one);
+    w.one.far = 1;   // the near field writes u_s, which the bands complete
+    w.one.res_a = 1.0 / (std::sqrt(2.0) * p->res_s0);
+    w.one.res_b = std::sqrt(2.0 / M_PI) * p->res_s0;
+    {
+        // residual below 1e-17 of its scale from x = b / (sqrt 2 s0) = 6.3 on: skip steps beyond
+        const double bcut = 6.3 * std::sqrt(2.0) * p->res_s0;
+        w.one.res_cut2 = std::max(0.0, bcut * bcut - p->shape * p->shape);
+    }
+    w.lam = lam;
+    w.u = u;
+    const hipStream_t s = p->stream;
+    ensure_side_stream(p);
+    ProductRun pt(p, p->side_state == 1);
+    BandTimer bt(p);
+    RBF_HIP(pt.begin(0, s));
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_GATHER, phase_blocks<T>(w.one, PH_GATHER), s, 0, 0, p->kernel)));
+    RBF_HIP(pt.end());
+    hipStream_t sn = s;
+    if (pt.side) {
+        RBF_HIP(hipEventRecord(pt.fork, s));
+        RBF_HIP(hipStreamWaitEvent(pt.side, pt.fork, 0));
+        sn = pt.side;
+    }
+    const int rk = p->kernel == RBF_MULTIQUADRIC ? kResMQ : kResIMQ;
+    RBF_HIP(pt.begin(1, sn));
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_P2P, phase_blocks<T>(w.one, PH_P2P), sn, 0, 0, rk)));
+    RBF_HIP(pt.end());
+    if (pt.side) RBF_HIP(hipEventRecord(pt.join, sn));
+    const int nbands = (int)p->bands.size();
+    for (int j = 0; j < nbands; ++j) {
+        Work<T> wb{};
+        fill_band_desc<T>(p, p->bands[j], j + 1 < nbands, &wb.one);
+        wb.lam = lam;
+        wb.u = u;
+        bt.j = j;
+        RBF_TRY((run_band_hp<T, D>(p->bands[j].HP, wb, s, (j == 0 && pt.side) ? pt.join : nullptr, bt)));
+    }
+    if (p->profiling) {
+        // phases 0 and 1 from the plan's events, 2..6 summed over the bands
+        RBF_HIP(hipEventSynchronize(p->band_ev.back()));
+        RBF_HIP(hipEventSynchronize(p->ev[3]));
+        for (int k = 0; k < 2; ++k) {
+            float ms = 0.f;
+            RBF_HIP(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));
+            p->phase_ms[k] += ms;
+        }
+        for (int j = 0; j < nbands; ++j)
+            for (int k = 2; k < RBF_NPHASES; ++k) {
+                float ms = 0.f;
+                RBF_HIP(hipEventElapsedTime(&ms, p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2],
+                                            p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2 + 1]));
+                p->phase_ms[k] += ms;
+            }
+        p->prof_calls += 1;
+    }
+    return RBF_OK;
+}
+
+template <class T>
+int banded_matvec_t(rbf_plan *p, const void *lam, void *u) {
+    if (p->profiling && p->band_ev.size() != p->bands.size() * 2 * RBF_NPHASES) {
+        for (hipEvent_t e : p->band_ev) (void)hipEventDestroy(e);
+        p->band_ev.assign(p->bands.size() * 2 * RBF_NPHASES, nullptr);
+        for (hipEvent_t &e : p->band_ev) RBF_HIP(hipEventCreate(&e));
+    }
+    switch (p->d) {
+        case 2: return banded_matvec_d<T, 2>(p, (const T *)lam, (T *)u);
+        case 3: return banded_matvec_d<T, 3>(p, (const T *)lam, (T *)u);
+    }
+    set_error("banded products are compiled for d = 2 and 3, not %d", p->d);
+    return RBF_EUNSUPPORTED;
+}
+
 }  // namespace
+
+// Aggregation launch shape: rows per workgroup, and per point of a chunk the factors of the
+// d-1 leading dimensions (plus, on the matrix cores, the point's HP phases) in LDS.
+template <class T> void set_p2m_shape(Desc<T> *d, int dim, int64_t R, int mn, int HP) {
+    using C = typename cplx<T>::type;
+    const int rows = kExpMfma<T> ? p2m_rows(dim) : (dim > 2 ? kThreads : kWave);
+    d->wpl = (int)((R + rows - 1) / rows);
+    const size_t per_point = sizeof(C) * (size_t)((dim > 1 ? dim - 1 : 1) * mn + (kExpMfma<T> ? HP : 0));
+    d->p2m_ch = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point)) & ~1;
+    d->p2m_lds = (int)(per_point * d->p2m_ch);
+}
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     using C = typename cplx<T>::type;
@@ -1421,14 +1656,7 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->dl = (C *)p->dl;
     d->wtab = p->wtab;
     d->m2l_sched = p->m2l_sched;
-    // aggregation: rows per workgroup, and per point of a chunk the factors of the d-1
-    // leading dimensions (plus, on the matrix cores, the point's HP phases) in LDS
-    const int rows = kExpMfma<T> ? p2m_rows(p->d) : (p->d > 2 ? kThreads : kWave);
-    d->wpl = (int)((p->R + rows - 1) / rows);
-    const size_t per_point =
-        sizeof(C) * (size_t)((p->d > 1 ? p->d - 1 : 1) * p->mn + (kExpMfma<T> ? p->HP : 0));
-    d->p2m_ch = (int)std::max<size_t>(4, std::min<size_t>(64, (32 * 1024) / per_point)) & ~1;
-    d->p2m_lds = (int)(per_point * d->p2m_ch);
+    set_p2m_shape<T>(d, p->d, p->R, p->mn, p->HP);
     d->far = p->far;
     d->dim = p->d;
     d->ngroups = p->ngroups;
@@ -1437,6 +1665,11 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->uni_idx = p->uni_idx;
     d->uni_mask = p->uni_mask;
     d->mn_magic = (unsigned)((1ull << 32) / (unsigned)p->mn + 1);
+    d->p2m_begin = d->leaf_begin;
+    d->p2m_end = d->src_end;
+    d->p2m_n = p->nleaves;
+    d->l2p_acc = 0;
+    d->res_a = d->res_b = d->res_cut2 = 0.0;
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);
 template void fill_desc<double>(const rbf_plan *, Desc<double> *);
@@ -1485,6 +1718,8 @@ int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u) {
 }
 
 int launch_matvec(rbf_plan *p, const void *lambda, void *u) {
+    if (!p->bands.empty())
+        return p->dtype == RBF_F32 ? banded_matvec_t<float>(p, lambda, u) : banded_matvec_t<double>(p, lambda, u);
     if (p->nleaves == 1 && !p->far && p->n_src == 0) return direct_product(p, lambda, u);
     return launch_matvec_phases(p, lambda, u);
 }

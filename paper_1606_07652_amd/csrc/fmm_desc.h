@@ -46,9 +46,17 @@ template <class T> struct Desc {
     const int *grp_first, *uni_ptr, *uni_idx, *uni_mask;
     int p2m_lds;            // dynamic LDS bytes of the aggregation kernel
     unsigned mn_magic;      // floor(2^32 / mn) + 1: r / mn = (r * mn_magic) >> 32 for r < 2^22
+    // aggregation units: point ranges [p2m_begin[a], p2m_end[a]) written to W[a]
+    // (the leaves' sources, or a band's chunks)
+    const int *p2m_begin, *p2m_end;
+    int p2m_n;
+    int l2p_acc;            // 1: the disaggregation adds its far field to u_s (sorted order)
+    double res_a, res_b;    // residual near-field kernels: 1/(sqrt 2 s0) and sqrt(2/pi) s0
+    double res_cut2;        // residual kernels: r^2 from which every pair is skipped
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);
+template <class T> void set_p2m_shape(Desc<T> *d, int dim, int64_t R, int mn, int HP);
 template <class T> int64_t desc_blocks(const Desc<T> &d, int phase);
 template <class T>
 int launch_batch_group(int d, int HP, int kernel, const Desc<T> *descs, int nprob, const int *const *bstarts,

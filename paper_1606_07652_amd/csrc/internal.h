@@ -56,6 +56,37 @@ template <class T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
 
+// Near-field kernels of a banded plan: the residual of the scale split (widths below s0) of
+// the multiquadric and the inverse multiquadric.  Internal codes, not part of the ABI.
+constexpr int kResMQ = 16, kResIMQ = 17;
+
+// One scale band of a banded far field (multiquadric kernels).  A band is a smooth part of
+// the kernel with its own quadrature grid (band limit sigma, nodes mn, period L), its own
+// dense coarse grid (level lc, stencil radius r), and its own translation table wtab
+// (quadrature weight times the factor C from the band's samples).  Its points are
+// aggregated in chunks (p2m_*: at most kBandChunk consecutive points of one cell, sorted by
+// cell; cell_begin is the chunk range of every dense cell) and disaggregated per occupied
+// cell (unit_*: point range and dense cell index of each occupied cell).
+struct Band {
+    int top = 0;                 // 1: the windowed top band (widths >= s_lo)
+    double s_lo = 0, s_hi = 0;   // widths of the band's Gaussians (top: s_hi = window width)
+    double tau = 0;              // tolerance of the band relative to its largest value
+    double sigma = 0, L = 0, reach = 0, rfar = 0, scale = 0;
+    int lc = 0, r = 0, mn = 0, H = 0, HP = 0;
+    int64_t R = 0, P = 0, ncells = 0;
+    int nunits = 0, nchunks = 0, ntasks = 0, ngroups = 0;
+    int *unit_begin = nullptr;   // [nunits + 1]
+    int *unit_cell = nullptr;    // [nunits]
+    int *chunk_begin = nullptr;  // [nchunks + 1]
+    int *cell_begin = nullptr;   // [ncells + 1] chunk ranges
+    int2 *tasks = nullptr;       // (unit, first point offset) per 64 points [ntasks]
+    int *grp_first = nullptr;    // runs of at most 8 units [ngroups + 1]
+    int *uni_ptr = nullptr;      // empty near lists [ngroups + 1]
+    int *uni_pad = nullptr;      // zero entries the leaf translation reads ahead [16]
+    double *wtab = nullptr;      // [P]
+};
+constexpr int kBandChunk = 256;
+
 }  // namespace rbf
 
 struct rbf_plan {
@@ -123,6 +154,15 @@ struct rbf_plan {
     void *Lc = nullptr;              // coarse local expansions [ncells][P]
     void *Tmp = nullptr;             // stencil pass buffer [ncells][P]
 
+    // banded far field (multiquadric kernels): the near field (adjacent cells of a uniform
+    // tree) sums the residual of the scale split, every band adds its far field; the bands
+    // run in order on the plan's stream and share the buffers b* (sized for the largest)
+    std::vector<rbf::Band> bands;
+    double res_s0 = 0;               // width below which the kernel is summed directly
+    double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
+    void *bW = nullptr, *bLx = nullptr, *bWc = nullptr, *bLc = nullptr, *bTmp = nullptr, *bdl = nullptr;
+    std::vector<hipEvent_t> band_ev; // profiling: event pairs per band and phase
+
     // the near field of a product runs on a second stream of default priority, forked after the
     // permutation and joined before the disaggregation (it reads nothing the far-field chain
     // writes, and only the disaggregation reads its result)
@@ -173,6 +213,8 @@ int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u);
 // RBF_EINVAL (with a message naming fn) when p is a plan for separate targets
 int reject_eval_plan(const rbf_plan *p, const char *fn);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);
+int plan_bands(rbf_plan *p);                                         // bands.hip
+bool banded_kernel(int kernel, int d);                               // bands.hip
 int pc_ready(rbf_plan *p, int kind);                                 // pc.hip
 int pc_apply(rbf_plan *p, int kind, const double *v, double *z);     // pc.hip
 int mlp_infer_bf16(rbf_mlp *m, const float *x, int64_t rows, float *y, hipStream_t s);   // mlp.hip

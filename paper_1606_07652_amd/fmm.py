@@ -36,13 +36,15 @@ def _ptr(t: torch.Tensor) -> int:
 
 
 def _opts(n_max=0, max_level=0, min_level=0, coarse_level=-1, coarse_radius=-1, nodes=0, band=0.0,
-          m2l_schedule=0):
-    return L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
+          m2l_schedule=0, exact=0):
+    return L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule,
+                     1 if exact else 0)
 
 
 def _opts_dict(o: "L.RbfOpts") -> dict:
     return {"n_max": o.n_max, "max_level": o.max_level, "min_level": o.min_level, "coarse_level": o.coarse_level,
-            "coarse_radius": o.coarse_radius, "nodes": o.nodes, "band": o.band, "m2l_schedule": o.m2l_schedule}
+            "coarse_radius": o.coarse_radius, "nodes": o.nodes, "band": o.band, "m2l_schedule": o.m2l_schedule,
+            "exact": o.exact}
 
 
 def autotune(points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05, tol: float = 1e-6,
@@ -136,7 +138,7 @@ class FmmPlan:
     def __init__(self, points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05,
                  tol: float = 1e-6, n_max: int = 0, max_level: int = 0, min_level: int = 0,
                  coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0, band: float = 0.0,
-                 m2l_schedule: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 m2l_schedule: int = 0, exact: bool = False, stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         if points.dim() != 2:
             raise ValueError("points must be (n, d)")
@@ -144,7 +146,7 @@ class FmmPlan:
         self.dtype = points.dtype
         self.device = points.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
-        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact)
         h = ctypes.c_void_p()
         L.check(lib.rbf_fmm_plan(_ptr(points), self.n, self.d, _dtype_code(points), _KERNELS[kernel],
                                  float(shape), float(tol), ctypes.byref(opts),
@@ -226,6 +228,15 @@ class FmmPlan:
         out["lo"] = list(inf.lo)[: self.d]
         return out
 
+    def bands(self) -> list:
+        """Scale bands of a banded plan (rbf_fmm_band_info), one dict per band, the top last."""
+        out = []
+        for j in range(self.info()["nbands"]):
+            b = L.RbfBandInfo()
+            L.check(L.load().rbf_fmm_band_info(self._h, j, ctypes.byref(b)))
+            out.append({name: getattr(b, name) for name, _ in L.RbfBandInfo._fields_ if name != "reserved"})
+        return out
+
     def tree(self) -> dict:
         inf = self.info()
         nl, nn = inf["nleaves"], inf["nnear"]
@@ -268,7 +279,8 @@ class EvalPlan(FmmPlan):
     def __init__(self, sources: torch.Tensor, targets: torch.Tensor, kernel: str = "gaussian",
                  shape: float = 0.05, tol: float = 1e-6, n_max: int = 0, max_level: int = 0,
                  min_level: int = 0, coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0,
-                 band: float = 0.0, m2l_schedule: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 band: float = 0.0, m2l_schedule: int = 0, exact: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         if sources.dim() != 2 or targets.dim() != 2 or targets.shape[1] != sources.shape[1]:
             raise ValueError("sources (n, d) and targets (m, d) must share d")
@@ -280,7 +292,7 @@ class EvalPlan(FmmPlan):
         self.dtype = sources.dtype
         self.device = sources.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(sources.device)
-        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact)
         h = ctypes.c_void_p()
         tp = _ptr(targets) if self.m > 0 else None
         L.check(lib.rbf_fmm_plan_eval(_ptr(sources), self.n_src, tp, self.m, self.d, _dtype_code(sources),

@@ -42,7 +42,7 @@ def test_binding_declares_the_same_functions():
 
 
 STRUCTS = {"rbf_opts": "RbfOpts", "rbf_solve_opts": "RbfSolveOpts", "rbf_solve_info": "RbfSolveInfo",
-           "rbf_plan_info": "RbfPlanInfo", "rbf_batch_info": "RbfBatchInfo", "rbf_train_opts": "RbfTrainOpts",
+           "rbf_plan_info": "RbfPlanInfo", "rbf_band_info": "RbfBandInfo", "rbf_batch_info": "RbfBatchInfo", "rbf_train_opts": "RbfTrainOpts",
            "rbf_train_info": "RbfTrainInfo"}
 
 

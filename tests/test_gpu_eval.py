@@ -84,7 +84,7 @@ def test_eval_multiquadric_is_the_exact_sum():
     x = mixed_points(6000, 3, 70, 4, 0.02)
     lam = normal_weights(6000, 71)
     y = targets_for(x, 2000, 72)
-    p = eval_plan(dev(x), dev(y), kernel="multiquadric", shape=0.02, tol=1e-6)
+    p = eval_plan(dev(x), dev(y), kernel="multiquadric", shape=0.02, tol=1e-6, exact=True)
     assert p.info()["nleaves"] == 1 and p.info()["far_field"] == 0
     u = p.eval(dev(lam)).cpu().numpy()
     ref = direct.direct_sum(x, lam, "multiquadric", 0.02, targets=y)

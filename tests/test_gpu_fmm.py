@@ -221,7 +221,7 @@ def test_multiquadric_plan_is_the_exact_sum(dtype, bound):
     lam = normal_weights(3000, 72)
     X = torch.as_tensor(x, dtype=dtype, device="cuda")
     L = torch.as_tensor(lam, dtype=dtype, device="cuda")
-    p = FmmPlan(X, kernel="multiquadric", shape=0.02, tol=1e-6, n_max=64)
+    p = FmmPlan(X, kernel="multiquadric", shape=0.02, tol=1e-6, n_max=64, exact=True)
     inf = p.info()
     assert inf["nleaves"] == 1 and inf["far_field"] == 0
     u = p.matvec(L).double().cpu().numpy()
