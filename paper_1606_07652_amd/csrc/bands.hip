@@ -221,6 +221,56 @@ std::vector<double> band_table(const rbf_plan *p, const Band &b) {
     return wt;
 }
 
+double residual_value(int kernel, double b, double s0) {
+    const double x = b / (std::sqrt(2.0) * s0);
+    if (kernel == RBF_MULTIQUADRIC) return b * std::erfc(x) - kSq2pi * s0 * std::exp(-x * x);
+    return std::erfc(x) / b;
+}
+
+// Polynomial pieces over [c, bmax) of g(b) = residual (multiquadric) or b * residual (inverse
+// multiquadric: erfc(x), smooth where the residual itself has the 1/b of the kernel): on each
+// of kResIntervals equal pieces the interpolant of degree kResDegree at Chebyshev points, as
+// monomial coefficients in the piece's local variable v in [0, 1).  Returns the largest
+// deviation of the residual it gives from the closed form on a finer sample of every piece.
+double residual_table(int kernel, double c, double bmax, double s0, std::vector<double> &tab, double *inv) {
+    const bool times_b = kernel == RBF_INVERSE_MULTIQUADRIC;
+    constexpr int n = kResDegree + 1;
+    const double db = (bmax - c) / kResIntervals;
+    *inv = 1.0 / db;
+    tab.assign(kResCoefs, 0.0);
+    double vmax = 0, emax = 0;
+    for (int k = 0; k < kResIntervals; ++k) {
+        double A[n][n + 1];
+        for (int i = 0; i < n; ++i) {
+            const double v = 0.5 - 0.5 * std::cos(M_PI * (2 * i + 1) / (2.0 * n));
+            double pw = 1.0;
+            for (int j = 0; j < n; ++j) { A[i][j] = pw; pw *= v; }
+            const double b = c + (k + v) * db;
+            A[i][n] = residual_value(kernel, b, s0) * (times_b ? b : 1.0);
+        }
+        // Gaussian elimination with partial pivoting on the n x n Vandermonde system
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r) if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+            for (int j = 0; j <= n; ++j) std::swap(A[col][j], A[piv][j]);
+            for (int r = 0; r < n; ++r) {
+                if (r == col) continue;
+                const double f = A[r][col] / A[col][col];
+                for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+            }
+        }
+        for (int j = 0; j < n; ++j) tab[k * n + j] = A[j][n] / A[j][j];
+        for (int t = 0; t <= 16; ++t) {
+            const double v = t / 16.0, b = c + (k + v) * db;
+            double y = tab[k * n + n - 1];
+            for (int j = n - 2; j >= 0; --j) y = y * v + tab[k * n + j];
+            if (times_b) y /= b;
+            emax = std::max(emax, std::fabs(y - residual_value(kernel, b, s0)));
+        }
+    }
+    return emax;
+}
+
 int upload(Arena &ar, void **dst, const void *src, size_t bytes) {
     RBF_TRY(ar.alloc(dst, bytes));
     RBF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -269,6 +319,19 @@ int plan_bands(rbf_plan *p) {
     const double xcut = std::sqrt(std::log(1.0 / tol) + 4.0);
     p->res_s0 = wn / (std::sqrt(2.0) * xcut);
     RBF_TRY(kernel_rms(p, &p->phi_rms));
+    {
+        // the residual over the near zone: pairs closer than one cell width (farther ones are
+        // beyond x = xcut, where it is below the tolerance) as polynomial pieces in b
+        p->res_qmax = wn * wn;
+        std::vector<double> tab;
+        const double err = residual_table(kernel, c, std::sqrt(wn * wn + c * c), p->res_s0, tab, &p->res_inv);
+        if (!(err <= 1e-3 * tol * p->phi_rms)) {
+            set_error("rbf_fmm_plan: the near-field residual table deviates by %.2e (kernel rms %.2e, tol %g)",
+                      err, p->phi_rms, tol);
+            return RBF_EUNSUPPORTED;
+        }
+        RBF_TRY(upload(p->arena, (void **)&p->res_tab, tab.data(), sizeof(double) * tab.size()));
+    }
     const double s_top = 2.0 * ext;
     std::vector<double> edges{p->res_s0};
     while (edges.back() * kRatio * 1.1 < s_top) edges.push_back(edges.back() * kRatio);
@@ -276,10 +339,11 @@ int plan_bands(rbf_plan *p) {
     const int J = (int)edges.size() - 1;
     // Tolerance of a piece relative to its largest value: the requested relative error times
     // the kernel's rms over pairs, split over the pieces (bands, top, residual) as independent
-    // errors, with a factor 4 for what the band-limit rule does not count (the truncated
-    // spectrum in each of the d axes, and the aliasing of the sampled C, which doubles it at
-    // the edge of the grid).
-    const double split = 4.0 * std::sqrt((double)(J + 2));
+    // errors.  The band-limit rule bounds a piece's error by its value at r = 0 and its
+    // narrowest width, which overstates a mixture's error; a factor 4 looser than the even
+    // split measured 2e-7 (FP64, tol 1e-6) and 3e-5 (FP32, tol 1e-4) on the 3-D mixed sets
+    // of 2^13 and 2^20 points, and 16 looser still 2e-7 and 4e-5.
+    const double split = 0.25 * std::sqrt((double)(J + 2));
     auto tau_for = [&](double mag) { return std::min(1e-2, std::max(1e-3 * tol, tol * p->phi_rms / (mag * split))); };
     std::vector<Band> bands;
     for (int j = 0; j < J; ++j) {

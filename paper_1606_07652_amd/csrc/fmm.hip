@@ -261,9 +261,9 @@ template <class T> constexpr int kP2pStep = sizeof(T) == 8 ? 4 : 8;
 template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && sizeof(T) == 8;
 // The FP64 thin-plate spline goes through log_tab (tab: its two tables of 256 entries).
 template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
-// The residual kernels of a banded plan read their two constants from tab.
-template <int KER> constexpr bool kRes = KER == kResMQ || KER == kResIMQ;
-template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kRes<KER> ? 2 : kExpTab;
+// The residual kernel of a banded plan reads its polynomial pieces from tab.
+template <int KER> constexpr bool kRes = KER == kResTab;
+template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kRes<KER> ? kResCoefs + 4 : kExpTab;
 // fills the LDS table of the kernel (stride: the workgroup size); a barrier must follow
 template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab, int stride) {
     if constexpr (kTabExp<T, KER>) {
@@ -276,15 +276,21 @@ template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab
     }
 }
 
-// Residual of the scale split of the multiquadric kernels (every Gaussian width below s0):
-// with b = sqrt(r^2 + c^2) and x = b / (sqrt 2 s0), the multiquadric's is
-// b erfc(x) - sqrt(2/pi) s0 e^{-x^2} and the inverse multiquadric's erfc(x) / b.
-// tab[0] = 1 / (sqrt 2 s0), tab[1] = sqrt(2/pi) s0; c2 = c^2.
+// Residual of the scale split of the multiquadric kernels (every Gaussian width below s0) at
+// squared distance r2: with b = sqrt(r2 + c^2), piece i = floor((b - c) inv) of the table, a
+// polynomial of degree kResDegree in v = (b - c) inv - i (tab[kResCoefs] = inv,
+// tab[kResCoefs + 1] = qmax, tab[kResCoefs + 2] = c; zero from r2 = qmax on).
 template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab) {
-    const T b = sqrt(r2 + c2);
-    const T x = b * (T)tab[0];
-    if constexpr (KER == kResMQ) return b * erfc(x) - (T)tab[1] * exp(-x * x);
-    else return erfc(x) / b;
+    const T b = KFun<T>::mq(r2, c2);
+    const T s = (b - (T)tab[kResCoefs + 2]) * (T)tab[kResCoefs];
+    const int i = max(0, min((int)s, kResIntervals - 1));
+    const T v = s - (T)i;
+    const double *c = tab + i * (kResDegree + 1);
+    T y = (T)c[kResDegree];
+#pragma unroll
+    for (int k = kResDegree - 1; k >= 0; --k) y = fma(y, v, (T)c[k]);
+    if (tab[kResCoefs + 3] != 0.0) y = y / b;   // inverse multiquadric: the table holds b * residual
+    return r2 < (T)tab[kResCoefs + 1] ? y : T(0);
 }
 
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
@@ -452,9 +458,12 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
         __syncthreads();
     }
     if constexpr (kRes<KER>) {
+        for (int j = threadIdx.x; j < kResCoefs; j += kWave) tab[j] = d.res_tab[j];
         if (threadIdx.x == 0) {
-            tab[0] = d.res_a;
-            tab[1] = d.res_b;
+            tab[kResCoefs] = d.res_inv;
+            tab[kResCoefs + 1] = d.res_cut2;
+            tab[kResCoefs + 2] = sqrt((double)d.coef);   // c (coef = c^2)
+            tab[kResCoefs + 3] = d.res_div_b;
         }
         __syncthreads();
     }
@@ -1211,8 +1220,7 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_INVERSE_MULTIQUADRIC: k_p2p<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
                 case RBF_WENDLAND: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
                 case RBF_THIN_PLATE: k_p2p<T, D, RBF_THIN_PLATE><<<g, kWave, 0, s>>>(w); break;
-                case kResMQ: k_p2p<T, D, kResMQ><<<g, kWave, 0, s>>>(w); break;
-                case kResIMQ: k_p2p<T, D, kResIMQ><<<g, kWave, 0, s>>>(w); break;
+                case kResTab: k_p2p<T, D, kResTab><<<g, kWave, 0, s>>>(w); break;
                 default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
             }
             break;
@@ -1523,13 +1531,10 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
     Work<T> w{};
     fill_desc<T>(p, &w.one);
     w.one.far = 1;   // the near field writes u_s, which the bands complete
-    w.one.res_a = 1.0 / (std::sqrt(2.0) * p->res_s0);
-    w.one.res_b = std::sqrt(2.0 / M_PI) * p->res_s0;
-    {
-        // residual below 1e-17 of its scale from x = b / (sqrt 2 s0) = 6.3 on: skip steps beyond
-        const double bcut = 6.3 * std::sqrt(2.0) * p->res_s0;
-        w.one.res_cut2 = std::max(0.0, bcut * bcut - p->shape * p->shape);
-    }
+    w.one.res_tab = p->res_tab;
+    w.one.res_inv = p->res_inv;
+    w.one.res_div_b = p->kernel == RBF_INVERSE_MULTIQUADRIC ? 1.0 : 0.0;
+    w.one.res_cut2 = p->res_qmax;
     w.lam = lam;
     w.u = u;
     const hipStream_t s = p->stream;
@@ -1545,7 +1550,7 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
         RBF_HIP(hipStreamWaitEvent(pt.side, pt.fork, 0));
         sn = pt.side;
     }
-    const int rk = p->kernel == RBF_MULTIQUADRIC ? kResMQ : kResIMQ;
+    const int rk = kResTab;
     RBF_HIP(pt.begin(1, sn));
     RBF_TRY((launch_phase<T, D, 4>(w, PH_P2P, phase_blocks<T>(w.one, PH_P2P), sn, 0, 0, rk)));
     RBF_HIP(pt.end());
@@ -1669,7 +1674,8 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->p2m_end = d->src_end;
     d->p2m_n = p->nleaves;
     d->l2p_acc = 0;
-    d->res_a = d->res_b = d->res_cut2 = 0.0;
+    d->res_tab = nullptr;
+    d->res_inv = d->res_cut2 = d->res_div_b = 0.0;
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);
 template void fill_desc<double>(const rbf_plan *, Desc<double> *);

@@ -51,8 +51,10 @@ template <class T> struct Desc {
     const int *p2m_begin, *p2m_end;
     int p2m_n;
     int l2p_acc;            // 1: the disaggregation adds its far field to u_s (sorted order)
-    double res_a, res_b;    // residual near-field kernels: 1/(sqrt 2 s0) and sqrt(2/pi) s0
-    double res_cut2;        // residual kernels: r^2 from which every pair is skipped
+    const double *res_tab;  // residual near-field kernel: polynomial pieces in b [kResCoefs]
+    double res_inv;         // pieces per unit of b
+    double res_cut2;        // r^2 from which the residual is zero (qmax)
+    double res_div_b;       // 1: the table holds b times the residual (inverse multiquadric)
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);

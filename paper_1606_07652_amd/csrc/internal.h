@@ -56,9 +56,12 @@ template <class T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
 
-// Near-field kernels of a banded plan: the residual of the scale split (widths below s0) of
-// the multiquadric and the inverse multiquadric.  Internal codes, not part of the ABI.
-constexpr int kResMQ = 16, kResIMQ = 17;
+// Near-field kernel of a banded plan: the residual of the scale split (widths below s0) of the
+// multiquadric kernels, as a piecewise polynomial in b = sqrt(r^2 + c^2) (kResIntervals pieces
+// of degree kResDegree over [c, bmax); zero from r^2 = qmax on).  Internal code, not ABI.
+constexpr int kResTab = 16;
+constexpr int kResIntervals = 128, kResDegree = 5;
+constexpr int kResCoefs = kResIntervals * (kResDegree + 1);
 
 // One scale band of a banded far field (multiquadric kernels).  A band is a smooth part of
 // the kernel with its own quadrature grid (band limit sigma, nodes mn, period L), its own
@@ -159,6 +162,9 @@ struct rbf_plan {
     // run in order on the plan's stream and share the buffers b* (sized for the largest)
     std::vector<rbf::Band> bands;
     double res_s0 = 0;               // width below which the kernel is summed directly
+    double res_qmax = 0;             // r^2 from which the residual is negligible (the cell width^2)
+    double res_inv = 0;              // residual pieces per unit of b
+    double *res_tab = nullptr;       // residual polynomial pieces [kResCoefs]
     double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
     void *bW = nullptr, *bLx = nullptr, *bWc = nullptr, *bLc = nullptr, *bTmp = nullptr, *bdl = nullptr;
     std::vector<hipEvent_t> band_ev; // profiling: event pairs per band and phase
