@@ -154,7 +154,8 @@ typedef struct rbf_solve_info {
     int    restarts;
     int    converged;
     int    fallback_used;/* number of preconditioner step-downs during the solve */
-    double true_res;     /* ||f - A lambda|| / ||f|| with a fresh product at exit */
+    double true_res;     /* ||f - A lambda|| / ||f|| of the returned lambda (the best iterate,
+                            its residual from a fresh product at the restart that reached it) */
     double seconds;      /* wall time of the solve */
     double history[256]; /* true relative residual at each restart (first 256) */
     int    nhistory;
@@ -323,8 +324,10 @@ int rbf_interp_solve_batch(rbf_batch *batch, const void *f, void *lambda, double
  * consecutive points; block b holds sorted points [64 b, min(64 b + 64, n)).
  *
  * Block-Jacobi: y_b = (A_bb + reg I)^{-1} v_b for every block, A_bb the exact kernel
- * matrix of the block's points (built in FP64 by Gauss-Jordan elimination in LDS, stored
- * as one explicit 64 x 64 FP64 inverse per block: 32 KiB per block).
+ * matrix of the block's points (built in FP64 by Gauss-Jordan elimination with partial
+ * pivoting in LDS, since the multiquadric's blocks are indefinite and Wendland's function
+ * is positive definite in one dimension only; stored as one explicit 64 x 64 FP64 inverse
+ * per block: 32 KiB per block).
  *
  * Learned: z_b = y_b + s_b g(y_b / s_b), y the block solve of v with the feature
  * regularisation (rbf_pc_learned_features), s_b = ||y_b||_2 (z_b = 0 if s_b = 0), with g the
@@ -343,10 +346,11 @@ enum { RBF_MLP_BF16 = 0, RBF_MLP_F32 = 1 };
 
 /* Build (or rebuild) the block-Jacobi inverses with regularisation reg >= 0 (reg < 0: the
  * default, reg = 1e-2 Phi(0)).  Synchronous.  RBF_EINVAL if a block is numerically
- * singular at this reg (a pivot <= 0).  Kernels with positive definite blocks only: the
- * Gaussian, the inverse multiquadric and Wendland's function; RBF_EUNSUPPORTED for the
- * multiquadric, the thin-plate spline and r^5.  The learned preconditioner, its features, pairs and harvest are
- * Gaussian-only (RBF_EUNSUPPORTED otherwise). */
+ * singular at this reg (a zero pivot after row exchanges).  Kernels: the Gaussian, the
+ * multiquadric (Phi(0) = c), the inverse multiquadric (Phi(0) = 1/c) and Wendland's function;
+ * RBF_EUNSUPPORTED for the thin-plate spline and r^5.  The learned preconditioner, its
+ * features, pairs and harvest take the Gaussian and the multiquadric kernels
+ * (RBF_EUNSUPPORTED otherwise); the feature regularisation defaults to 1e-6 Phi(0). */
 int rbf_pc_block_jacobi(rbf_plan *plan, double reg);
 /* Build the block inverses that form the learned map's features y (and those of
  * rbf_pc_pairs / rbf_pc_harvest) with their own regularisation (reg < 0: the default,

@@ -19,7 +19,8 @@ evaluator and its second derivative reproduce the left column of the paper's
 Table "RMS errors" (tests/golden/tab_rms_left.txt).  The inverse multiquadric is pinned
 to the paper's Fourier-transform table (a Bessel-K transform, by numerical integration) and
 Wendland's function to its expanded polynomial, its C^2 joint at the support radius and
-the positive definiteness of its matrices in three dimensions.  The thin-plate spline and r^5
+the sign of its radial Fourier transform by dimension (positive in 1-D, negative somewhere in
+2-D and 3-D: the function is Wendland's phi_{1,1}, positive definite in one dimension only).  The thin-plate spline and r^5
 are pinned by finite-difference Laplacians (4 log r + 4 in 2-D, 30 r^3 in 3-D).
 """
 from __future__ import annotations

@@ -3,11 +3,14 @@
 //
 // Block factorisation (k_bj_setup): one wave per block.  The block's kernel matrix
 // A_bb + reg I is formed in FP64 in LDS (column-major, lane i owns row i) and inverted in
-// place by Gauss-Jordan elimination without pivoting, which is stable for a symmetric
-// positive definite matrix: at step k the pivot row is read by every lane as a broadcast,
-// each lane updates its own row, then row and column k are rescaled.  Rows beyond a short
-// last block are padded with the identity.  The inverse is stored column-major, so the
-// apply (lane i forms row i of the product) reads each column with one coalesced load.
+// place by Gauss-Jordan elimination with partial pivoting (the blocks of the multiquadric are
+// indefinite, and Wendland's function is positive definite only in one dimension): at step k
+// the wave finds the row of largest |a_ik|, i >= k, swaps it with row k (lane j swaps the
+// two entries of column j), every lane updates its own row with row k read as a broadcast,
+// then row and column k are rescaled; at the end the columns are swapped back in reverse
+// order of the row swaps.  Rows beyond a short last block are padded with the identity.  The
+// inverse is stored column-major, so the apply (lane i forms row i of the product) reads each
+// column with one coalesced load.
 //
 // Apply (k_bj_rows): four waves per workgroup, one block per wave.  The block's entries of
 // v are gathered through the permutation into LDS, y_b = inv_b v_b, and either written back
@@ -32,10 +35,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// The kernels whose block matrices are positive definite: the Gaussian exp(-r^2/(2 s^2)), the
-// inverse multiquadric 1/sqrt(r^2 + c^2) and Wendland's (1 - e r)_+^3 (3 e r + 1), in FP64.
+// The kernels with block preconditioners, in FP64: the Gaussian exp(-r^2/(2 s^2)), the
+// multiquadric sqrt(r^2 + c^2), the inverse multiquadric 1/sqrt(r^2 + c^2) and Wendland's
+// (1 - e r)_+^3 (3 e r + 1).
 __device__ double block_phi(int kernel, double r2, double shape) {
     if (kernel == RBF_GAUSSIAN) return exp(-r2 / (2.0 * shape * shape));
+    if (kernel == RBF_MULTIQUADRIC) return sqrt(r2 + shape * shape);
     if (kernel == RBF_INVERSE_MULTIQUADRIC) return 1.0 / sqrt(r2 + shape * shape);
     const double er = shape * sqrt(r2);
     const double t = fmax(1.0 - er, 0.0);
@@ -67,9 +72,26 @@ __global__ void __launch_bounds__(BS) k_bj_setup(const T *__restrict__ xs, int64
         L[j * BS + i] = a;
     }
     __syncthreads();
+    __shared__ int ipiv[BS];
     for (int k = 0; k < BS; ++k) {
+        // pivot: the row of largest |a_ik| among i >= k (lowest index on ties)
+        double best = i >= k ? fabs(L[k * BS + i]) : -1.0;
+        int bi = i;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (i == 0) ipiv[k] = bi;
+        if (bi != k) {   // uniform over the wave: lane j swaps rows k and bi of column j
+            const double t = L[i * BS + k];
+            L[i * BS + k] = L[i * BS + bi];
+            L[i * BS + bi] = t;
+        }
+        __syncthreads();
         const double piv = L[k * BS + k];
-        if (!(piv > 0.0) || !isfinite(piv)) {   // uniform over the wave
+        if (!(fabs(piv) > 0.0) || !isfinite(piv)) {   // uniform over the wave
             if (i == 0) flag[0] = 1;
             return;
         }
@@ -87,6 +109,16 @@ __global__ void __launch_bounds__(BS) k_bj_setup(const T *__restrict__ xs, int64
             L[k * BS + i] = -aik * p;    // column k
         } else {
             L[k * BS + k] = p;
+        }
+        __syncthreads();
+    }
+    // the row swaps of the factorisation become column swaps of the inverse, in reverse order
+    for (int k = BS - 1; k >= 0; --k) {
+        const int q = ipiv[k];
+        if (q != k) {
+            const double t = L[k * BS + i];
+            L[k * BS + i] = L[q * BS + i];
+            L[q * BS + i] = t;
         }
         __syncthreads();
     }
@@ -226,33 +258,39 @@ int factor_blocks(rbf_plan *p, double reg, double *inv) {
     RBF_HIP(hipMemcpyAsync(&flag, p->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
     if (flag) {
-        set_error("block factorisation: a block is numerically singular at reg = %g (increase reg)", reg);
+        set_error("block factorisation: a block is numerically singular at reg = %g (a property of the kernel "
+                  "and the points: coincident points, or an eigenvalue of a block at -reg)", reg);
         return RBF_EINVAL;
     }
     return RBF_OK;
 }
 
-// Block-Jacobi needs positive definite blocks (not those of the multiquadric, the thin-plate spline
-// or r^5); the network's features and training pairs are those of the Gaussian.
+// Block preconditioners for the Gaussian, the multiquadric kernels and Wendland's function (the
+// thin-plate spline and r^5 need the polynomial terms of the augmented solve, which has none);
+// the network's features and training pairs for the Gaussian and the multiquadric kernels.
 int check_bj_kernel(const rbf_plan *p) {
-    if (p->kernel != RBF_GAUSSIAN && p->kernel != RBF_INVERSE_MULTIQUADRIC && p->kernel != RBF_WENDLAND) {
-        set_error("block-Jacobi: the blocks of this kernel are not positive definite (Gaussian, inverse "
-                  "multiquadric and Wendland kernels are supported)");
+    if (p->kernel != RBF_GAUSSIAN && p->kernel != RBF_MULTIQUADRIC && p->kernel != RBF_INVERSE_MULTIQUADRIC &&
+        p->kernel != RBF_WENDLAND) {
+        set_error("block-Jacobi: Gaussian, multiquadric, inverse multiquadric and Wendland kernels are supported");
         return RBF_EUNSUPPORTED;
     }
     return RBF_OK;
 }
 
 int check_learned_kernel(const rbf_plan *p) {
-    if (p->kernel != RBF_GAUSSIAN) {
-        set_error("learned preconditioner: only the Gaussian kernel is supported");
+    if (p->kernel != RBF_GAUSSIAN && p->kernel != RBF_MULTIQUADRIC && p->kernel != RBF_INVERSE_MULTIQUADRIC) {
+        set_error("learned preconditioner: the Gaussian and the multiquadric kernels are supported");
         return RBF_EUNSUPPORTED;
     }
     return RBF_OK;
 }
 
 // Phi(0), the scale of the default regularisations
-double phi_zero(const rbf_plan *p) { return p->kernel == RBF_INVERSE_MULTIQUADRIC ? 1.0 / p->shape : 1.0; }
+double phi_zero(const rbf_plan *p) {
+    if (p->kernel == RBF_INVERSE_MULTIQUADRIC) return 1.0 / p->shape;
+    if (p->kernel == RBF_MULTIQUADRIC) return p->shape;
+    return 1.0;
+}
 
 int build_lp(rbf_plan *p, double reg);
 
@@ -323,7 +361,7 @@ int pc_ready(rbf_plan *p, int kind) {
             set_error("learned preconditioner: no network attached (rbf_pc_set_learned)");
             return RBF_ESTATE;
         }
-        if (p->lp_reg < 0) RBF_TRY(build_lp(p, kDefaultLpReg));
+        if (p->lp_reg < 0) RBF_TRY(build_lp(p, kDefaultLpReg * phi_zero(p)));
     }
     return RBF_OK;
 }
@@ -363,7 +401,7 @@ extern "C" int rbf_pc_learned_features(rbf_plan *plan, double reg) {
     if (!plan) { set_error("rbf_pc_learned_features: null plan"); return RBF_EINVAL; }
     RBF_TRY(reject_eval_plan(plan, "rbf_pc_learned_features"));
     if (!std::isfinite(reg)) { set_error("rbf_pc_learned_features: reg must be finite"); return RBF_EINVAL; }
-    return build_lp(plan, reg < 0 ? kDefaultLpReg : reg);
+    return build_lp(plan, reg < 0 ? kDefaultLpReg * phi_zero(plan) : reg);
 }
 
 extern "C" int rbf_pc_apply(rbf_plan *plan, int kind, const double *v, double *z) {
@@ -386,7 +424,7 @@ extern "C" int rbf_pc_set_learned(rbf_plan *plan, rbf_mlp *mlp) {
 extern "C" int rbf_pc_pairs(rbf_plan *plan, const double *r, const double *e, float *x, float *t, float *w) {
     if (!plan || !r || !e || !x || !t || !w) { set_error("rbf_pc_pairs: null argument"); return RBF_EINVAL; }
     RBF_TRY(reject_eval_plan(plan, "rbf_pc_pairs"));
-    if (plan->lp_reg < 0) RBF_TRY(build_lp(plan, kDefaultLpReg));
+    if (plan->lp_reg < 0) RBF_TRY(build_lp(plan, kDefaultLpReg * phi_zero(plan)));
     hipStream_t s = plan->stream;
     k_dot_self<<<1, kT, 0, s>>>(e, plan->n, plan->pc_scal);
     const unsigned nb = (unsigned)((plan->nblk + kT / BS - 1) / (kT / BS));
@@ -409,7 +447,7 @@ extern "C" int rbf_pc_harvest(rbf_plan *plan, const void *f, double rtol, int ma
     for (int c = 0; c < ncaps; ++c)
         if (caps[c] < 0) { set_error("rbf_pc_harvest: caps must be >= 0"); return RBF_EINVAL; }
     RBF_TRY(pc_ready(plan, precond));
-    if (plan->lp_reg < 0) RBF_TRY(build_lp(plan, kDefaultLpReg));
+    if (plan->lp_reg < 0) RBF_TRY(build_lp(plan, kDefaultLpReg * phi_zero(plan)));
     const int64_t n = plan->n;
     const size_t tsz = plan->dtype == RBF_F32 ? 4 : 8;
     hipStream_t s = plan->stream;

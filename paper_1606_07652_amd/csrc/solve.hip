@@ -270,6 +270,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     S.fd = base + 3 * na;
     S.rd = base + 4 * na;
     S.wd = base + 5 * na;
+    double *const xbest = base + 6 * na;   // the iterate with the lowest true residual so far
     const unsigned nb = (unsigned)((na + kThreads - 1) / kThreads);   // grid over the Krylov length
     const size_t tsz = p->dtype == RBF_F64 ? 8 : 4;
     // x0 and f in FP64: [lambda; c] and [f; 0]
@@ -313,7 +314,10 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         RBF_TRY(S.norm(S.rd, &beta));
         double rel = beta / bnorm;
         if (inf.nhistory < 256) inf.history[inf.nhistory++] = rel;
-        best = std::min(best, rel);
+        if (rel < best) {
+            best = rel;
+            RBF_HIP(hipMemcpyAsync(xbest, S.xd, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
+        }
         double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         if (!(rel > rtol) || its >= maxit || (tlim > 0 && el >= tlim) || !std::isfinite(rel)) break;
         if (cur != RBF_PC_NONE && fallback && restarts > 0 && rel > 0.999 * last_cycle_res)
@@ -400,6 +404,9 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         }
         ++restarts;
     }
+    // the best iterate (a cycle after a preconditioner fallback can raise the true residual)
+    if (bnorm > 0.0 && std::isfinite(best))
+        RBF_HIP(hipMemcpyAsync(S.xd, xbest, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
     // write the solution (and the polynomial coefficients) in the plan's dtype
     if (p->dtype == RBF_F64) {
         RBF_HIP(hipMemcpyAsync(lambda, S.xd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -412,7 +419,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     RBF_HIP(hipStreamSynchronize(s));
     inf.iters = its;
     inf.restarts = restarts;
-    inf.true_res = (inf.nhistory > 0) ? inf.history[inf.nhistory - 1] : 0.0;
+    inf.true_res = (bnorm > 0.0 && std::isfinite(best)) ? best : 0.0;
     if (bnorm == 0.0) inf.true_res = 0.0;
     inf.converged = inf.true_res <= rtol;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

@@ -206,19 +206,38 @@ def test_wendland_solve_with_block_jacobi():
 
 
 def test_preconditioner_kernel_errors():
-    """Block-Jacobi rejects the multiquadric (blocks not positive definite); the learned
-    preconditioner's features are Gaussian-only."""
+    """The learned map's features take the Gaussian and the multiquadric kernels only;
+    block-Jacobi takes the multiquadric (pivoted factorisation)."""
     from paper_1606_07652_amd import pc
     from paper_1606_07652_amd._lib import RBF_EUNSUPPORTED, RbfError
     x = uniform_points(500, 3, 390)
     pm = plan(x, "multiquadric", 0.05, torch.float64)
+    pc.block_jacobi(pm)
+    pc.learned_features(pm)
+    pw = plan(x, "wendland", 4.0, torch.float64)
     with pytest.raises(RbfError) as e:
-        pc.block_jacobi(pm)
+        pc.learned_features(pw)
     assert e.value.code == RBF_EUNSUPPORTED
-    pi = plan(x, "inverse_multiquadric", 0.05, torch.float64)
-    with pytest.raises(RbfError) as e:
-        pc.learned_features(pi)
-    assert e.value.code == RBF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kind,c", [("uniform", 0.05), ("mixed", 0.02)])
+def test_block_jacobi_multiquadric_pivoted(kind, c):
+    """Multiquadric blocks are indefinite: the pivoted factorisation matches the oracle's
+    block solves to the blocks' condition number times the FP64 unit roundoff."""
+    from oracle import precond as P
+    from paper_1606_07652_amd import pc
+    x = (uniform_points if kind == "uniform" else mixed_points)(2500, 3, 385)
+    v = normal_weights(2500, 386)
+    p = plan(x, "multiquadric", c, torch.float64)
+    reg = 1e-2 * c
+    pc.block_jacobi(p, reg)
+    z = pc.apply(p, "block_jacobi", dev(v)).cpu().numpy()
+    inv, perm = P.block_inverses(x, "multiquadric", c, reg)
+    ref = P.bj_apply(inv, perm, v)
+    cond = max(np.linalg.cond(b) for b in inv)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    print(f"[mq bj {kind}] max block cond {cond:.2e}, rel diff {err:.2e}", flush=True)
+    assert err <= 1e-13 * cond
 
 
 @pytest.mark.parametrize("kernel", ["thin_plate", "r5"])

@@ -254,7 +254,11 @@ def test_nan_network_falls_back():
 
 def test_learned_preconditioner_gain(tmp_path):
     """Train on harvested pairs of plain solves of four 10^4-point problems, then solve a
-    fifth problem of the same family with identical caps: plain, block-Jacobi, learned."""
+    fifth problem of the same family with identical caps: plain, block-Jacobi, the same
+    cycle with an untrained network (zero output: the block solve alone) and with the trained
+    one.  Measured result: no gain from the network.  The trained network's held-out loss
+    falls tenfold, yet its solve ends within 10% of the untrained network's; the gain over
+    plain GMRES comes from the block solves.  The test asserts exactly that."""
     from paper_1606_07652_amd import FmmPlan
     from paper_1606_07652_amd import pc
     from workloads import bumps_rhs
@@ -275,13 +279,16 @@ def test_learned_preconditioner_gain(tmp_path):
     path = str(tmp_path / "pc.bin")
     m.save(path)
     m2 = pc.Mlp.load(path)                   # the solve below runs on the reloaded weights
+    m0 = pc.Mlp(seed=0)                      # untrained: zero output layer
     x = jittered_grid(100, 2, 200)
     f = dev(bumps_rhs(x, 200))
     plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
-    pc.set_learned(plan, m2)
     res = {}
-    for kind in ("none", "block_jacobi", "learned"):
-        lam, inf = plan.solve(f, rtol=1e-8, restart=50, max_iters=300, precond=kind)
+    for kind, net in (("none", None), ("block_jacobi", None), ("untrained", m0), ("learned", m2)):
+        if net is not None:
+            pc.set_learned(plan, net)
+        lam, inf = plan.solve(f, rtol=1e-8, restart=50, max_iters=300,
+                              precond="learned" if net is not None else kind)
         u = plan.matvec(lam).cpu().numpy()
         fh = f.cpu().numpy()
         true_res = np.linalg.norm(fh - u) / np.linalg.norm(fh)
@@ -290,4 +297,4 @@ def test_learned_preconditioner_gain(tmp_path):
         print(f"[gain] {kind}: iters={inf['iters']} true residual {true_res:.3e} fallback={inf['fallback_used']}",
               flush=True)
     assert res["learned"] <= 0.5 * res["none"]
-    assert res["learned"] <= 1.5 * res["block_jacobi"]
+    assert 0.9 * res["untrained"] <= res["learned"] <= 1.1 * res["untrained"]

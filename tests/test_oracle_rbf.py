@@ -64,14 +64,38 @@ def test_wendland_c2_joint():
         assert abs(v / h ** 3 - e ** 3 * (4.0 - 3.0 * e * h)) < 1e-6 * e ** 3
 
 
-def test_wendland_matrix_positive_definite_3d():
-    """Wendland's C^2 function of this form is positive definite in up to three dimensions:
-    its matrix on distinct points has a positive smallest eigenvalue."""
-    rng = np.random.default_rng(5)
-    x = rng.random((300, 3))
-    r2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
-    a = rbf.phi_of_r2("wendland", r2, 2.0)
-    assert np.min(np.linalg.eigvalsh(a)) > 0.0
+def _radial_transform(f, d, w):
+    """d-dimensional Fourier transform of a radial function supported in [0, 1] at |xi| = w:
+    2 int f(r) cos(w r) dr (d = 1), 2 pi int f(r) r J0(w r) dr (d = 2),
+    4 pi / w int f(r) r sin(w r) dr (d = 3)."""
+    from scipy.integrate import quad
+    from scipy.special import j0
+    if d == 1:
+        g = lambda r: 2.0 * f(r) * math.cos(w * r)
+    elif d == 2:
+        g = lambda r: 2.0 * math.pi * f(r) * r * j0(w * r)
+    else:
+        g = lambda r: 4.0 * math.pi * f(r) * r * math.sin(w * r) / w
+    return quad(g, 0.0, 1.0, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+
+
+def test_wendland_transform_sign_by_dimension():
+    """(1 - r)_+^3 (3 r + 1) is Wendland's phi_{1,1}: positive definite in one dimension only.
+    Its radial Fourier transform is positive in 1-D but dips below zero in 2-D and 3-D, while
+    (1 - r)_+^4 (4 r + 1) (phi_{3,1}, positive definite up to three dimensions) stays
+    non-negative in 3-D.  So kernel matrices of the paper's Wendland function in 2-D and 3-D
+    may be indefinite (the block preconditioner factors with pivoting)."""
+    phi = lambda r: float(rbf.phi_of_r2("wendland", r * r, 1.0))
+    phi31 = lambda r: (1.0 - r) ** 4 * (4.0 * r + 1.0)
+    ws = np.linspace(0.5, 40.0, 160)
+    t1 = np.array([_radial_transform(phi, 1, w) for w in ws])
+    t2 = np.array([_radial_transform(phi, 2, w) for w in ws])
+    t3 = np.array([_radial_transform(phi, 3, w) for w in ws])
+    t3b = np.array([_radial_transform(phi31, 3, w) for w in ws])
+    assert t1.min() > 0.0
+    assert t2.min() < -1e-7 * t2.max()
+    assert t3.min() < -1e-6 * t3.max()
+    assert t3b.min() > -1e-12 * t3b.max()
 
 
 def laplacian_fd(f, p, h):
