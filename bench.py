@@ -1,11 +1,19 @@
-"""Benchmark: band-limited FMM matrix-vector product throughput (points/s) on one MI355X.
+"""Benchmark: band-limited FMM matrix-vector product throughput (points/s) on one MI355X,
+and GMRES time to a true residual of 1e-8 with and without the learned preconditioner.
 
 Workload (default): 3-D, N = 2^20 points, half uniform in [0,1]^3 and half from 32
-Gaussian blobs (standard deviation 0.01), stored as float32; Gaussian kernel
-exp(-r^2/(2 * 0.03^2)); lambda ~ N(0,1).  The headline path computes in FP64 with
-tolerance 1e-6 (relative 2-norm error against the exact sum); the FP32 path (tol 1e-4)
-is reported beside it.  A step is one full product (permute, near field, aggregation,
-upward sum, coarse and leaf translation, disaggregation) with inputs resident in HBM.
+Gaussian blobs (standard deviation 0.01), stored as float32; lambda ~ N(0,1).
+* Headline: the Gaussian kernel exp(-r^2/(2 * 0.03^2)) in FP64 with tolerance 1e-6 (relative
+  2-norm error against the exact sum); the FP32 path (tol 1e-4) beside it.  A step is one full
+  product (permute, near field, aggregation, upward sum, coarse and leaf translation,
+  disaggregation) with inputs resident in HBM.
+* The same points with the multiquadric sqrt(r^2 + 0.02^2) (banded far field), FP64 at 1e-6
+  and FP32 at 1e-4, each checked on 2048 sampled targets against the oracle's direct sum.
+* GMRES(50) on the learned-preconditioner workload's recipe (3-D mixed points, multiquadric
+  c = 0.02, f = 16 Gaussian bumps of width 0.1) at 2^18 points, FP64 product at tol 1e-8, to a
+  true residual of 1e-8 or 200 iterations: plain, block-Jacobi and learned (network trained
+  here on pairs from solves of four 10^4-point problems of the family).  The full 2^21-point
+  solve is ``--workload solve``.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the bench measures one GPU.
 """
@@ -45,11 +53,7 @@ def phase_model(info, dtype_bytes, n):
         # (kind, amount): flops for phases bound by the vector ALUs ("alu") or the matrix cores
         # ("mfma"), bytes for memory-bound ones ("hbm"); the FP64 aggregation runs on the vector
         # ALUs and the disaggregation on the matrix cores
-        # per near pair: d differences, d multiply-adds for r^2, one scaling and one
-        # multiply-add into the sum (3d + 3 flops), plus the FP64 exponential, which has no
-        # hardware instruction: counted as a fixed 22 flops (its degree-11 Taylor evaluation),
-        # whatever method the kernel uses, so that faster exponentials show as a higher fraction
-        "p2p": ("alu", pairs * (3 * d + 3 + 22)),
+        "p2p": ("alu", pairs * gauss_pair_flops(d, dtype_bytes)),
         "p2m": ("alu", 8.0 * n * P),
         "l2p": ("mfma", 8.0 * n * P),
         "m2m": ("hbm", (nl + nc) * P * cb),
@@ -60,6 +64,24 @@ def phase_model(info, dtype_bytes, n):
         "m2l_leaf": ("hbm", (2.0 * nl + nc) * P * cb),
         "permute": ("hbm", n * (2 * dtype_bytes + 4)),
     }
+
+
+def gauss_pair_flops(d, dtype_bytes):
+    """Floating-point operations the near-field kernel executes per Gaussian pair (a fused
+    multiply-add counts 2): d differences and d multiply-adds for r^2, the scaling of r^2 and
+    the multiply-add into the sum (3 d + 3), plus the exponential as built.  FP64: the table
+    method of the kernel (round to nearest, the reduced argument, a degree-4 polynomial in 4
+    multiply-adds, the product with the table entry and the exponent scaling: 12).  FP32: the
+    hardware exp2 instruction, counted as 1."""
+    return 3 * d + 3 + (12 if dtype_bytes == 8 else 1)
+
+
+def residual_pair_flops(d):
+    """Per near pair of a banded plan (multiquadric kernels), as the kernel executes it: the
+    distance and the accumulation (3 d + 3), b = sqrt(r^2 + c^2) through the reciprocal square
+    root and two Newton steps (14), the table index and local variable (3) and the degree-5
+    polynomial (10)."""
+    return 3 * d + 3 + 14 + 3 + 10
 
 
 def measured_traffic(phase):
@@ -213,62 +235,133 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
-def run_solve(args):
-    """GMRES(50) on the 3-D mixed 2^21-point Gaussian system (s = 0.03, f = 16 bumps of width
-    0.1), FP64 product at tol 1e-6, to a true residual of 1e-8 or the iteration cap: plain,
-    block-Jacobi and learned (network trained here on pairs harvested from plain solves of
-    four 10^4-point problems of the same family)."""
-    import torch
-
-    from paper_1606_07652_amd import FmmPlan
-    from paper_1606_07652_amd import pc
+def solve_family(torch, FmmPlan, pc, kernel, shape, n, rtol, cap, n_train=10000, harvest_iters=500):
+    """GMRES(50) on the learned-preconditioner recipe (3-D mixed points, f = 16 Gaussian bumps of
+    width 0.1) at n points: plain, block-Jacobi and learned, each to the true residual rtol or
+    `cap` iterations.  The network is trained here on pairs harvested from solves of four
+    n_train-point problems of the same family (seeds 100-103)."""
     from workloads import bumps_rhs, c5, mixed_points
 
     def dev(a):
         return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
 
-    s = 0.03
     t0 = time.perf_counter()
     rows = [[], [], []]
     for sd in (100, 101, 102, 103):
-        x = mixed_points(10000, 3, sd)
-        plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
-        for k, a in enumerate(pc.harvest(plan, dev(bumps_rhs(x, sd)), rtol=1e-10, max_iters=1000)):
+        x = mixed_points(n_train, 3, sd)
+        plan = FmmPlan(dev(x), kernel=kernel, shape=shape, tol=1e-8)
+        for k, a in enumerate(pc.harvest(plan, dev(bumps_rhs(x, sd)), rtol=1e-10, max_iters=harvest_iters)):
             rows[k].append(a)
         plan.close()
     X, T, W = (torch.cat(r) for r in rows)
     harvest_s = time.perf_counter() - t0
     m = pc.Mlp(seed=0)
     tinfo = m.train(X, T, W, epochs=150, batch=256, lr=1e-3, val_frac=0.25, patience=30, seed=1)
-    log(f"[bench] harvest {harvest_s:.1f} s ({X.shape[0]} rows), training {tinfo['seconds']:.1f} s, "
+    log(f"[bench] {kernel}: harvest {harvest_s:.1f} s ({X.shape[0]} rows), training {tinfo['seconds']:.1f} s, "
         f"held-out loss {tinfo['init_val_loss']:.3f} -> {tinfo['best_val_loss']:.3f}")
-    w = c5(n=args.n_solve, kernel="gaussian")
-    plan = FmmPlan(dev(w.points), kernel="gaussian", shape=s, tol=1e-6, n_max=args.n_max)
+    w = c5(n=n, kernel=kernel)
+    plan = FmmPlan(dev(w.points), kernel=kernel, shape=shape, tol=1e-8)
     pc.set_learned(plan, m)
     f = dev(w.f)
-    fh = w.f.astype(np.float64)
     out = {}
     for kind in ("none", "block_jacobi", "learned"):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        lam, inf = plan.solve(f, rtol=1e-8, restart=50, max_iters=args.solve_iters, precond=kind)
+        lam, inf = plan.solve(f, rtol=rtol, restart=50, max_iters=cap, precond=kind)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t1
-        out[kind] = {"iters": inf["iters"], "true_res": inf["true_res"], "converged": inf["converged"],
-                     "seconds": secs, "fallback_used": inf["fallback_used"], "history": inf["history"]}
-        log(f"[bench] {kind}: {inf['iters']} iterations, true residual {inf['true_res']:.3e}, {secs:.2f} s")
-    n = w.points.shape[0]
+        out[kind] = {"seconds": secs, "time_to_rtol": secs if inf["converged"] else None,
+                     "iters": inf["iters"], "true_res": inf["true_res"], "converged": bool(inf["converged"]),
+                     "fallback_used": inf["fallback_used"], "history": inf["history"][:16]}
+        log(f"[bench] {kernel} {kind}: {inf['iters']} iterations, true residual {inf['true_res']:.3e}, "
+            f"{secs:.2f} s")
+    plan.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"3d_mixed_{kernel}_c{shape}_bumps_rhs", "n": int(w.points.shape[0]), "restart": 50,
+            "rtol": rtol, "cap_iters": cap, "product_tol": 1e-8, "solves": out,
+            "training": {"rows": int(X.shape[0]), "problems": f"4 x {n_train} points (seeds 100-103)",
+                         "harvest_seconds": harvest_s, "train_seconds": tinfo["seconds"],
+                         "init_val_loss": tinfo["init_val_loss"], "best_val_loss": tinfo["best_val_loss"]}}
+
+
+def run_solve(args):
+    """GMRES(50) on the learned-preconditioner workload as specified: 3-D mixed points (2^21),
+    multiquadric c = 0.02, f = 16 bumps of width 0.1, FP64 banded product at tol 1e-8, to a true
+    residual of 1e-8 or the iteration cap: plain, block-Jacobi and learned."""
+    import torch
+
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+
+    res = solve_family(torch, FmmPlan, pc, "multiquadric", 0.02, args.n_solve, 1e-8, args.solve_iters)
+    lr = res["solves"]["learned"]
     result = {"metric": "GMRES(50) time to true residual 1e-8 (or the residual at the cap)",
-              "value": out["learned"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
-              "ms_per_step": out["learned"]["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+              "value": lr["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+              "ms_per_step": lr["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-              "config": {"workload": "3d_mixed_gaussian_s0.03_bumps_rhs", "n": n, "restart": 50, "rtol": 1e-8,
-                         "max_iters": args.solve_iters, "tol": 1e-6, "n_max": args.n_max},
-              "solves": out, "training": {"rows": int(X.shape[0]), "harvest_seconds": harvest_s,
-                                          "train_seconds": tinfo["seconds"],
-                                          "init_val_loss": tinfo["init_val_loss"],
-                                          "best_val_loss": tinfo["best_val_loss"]}}
+              "config": {k: v for k, v in res.items() if k not in ("solves", "training")},
+              "solves": res["solves"], "training": res["training"]}
     print(json.dumps(result), flush=True)
+
+
+def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None):
+    """The banded product of a multiquadric kernel on the workload's points, FP64 (tol 1e-6)
+    and FP32 (tol 1e-4): time per product, phase times and roofline fractions, and the
+    sampled error against the oracle's direct sum when given."""
+    n = w.points.shape[0]
+    out = {}
+    for name, dt, tol, bytes_ in (("f64", torch.float64, 1e-6, 8), ("f32", torch.float32, 1e-4, 4)):
+        X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
+        lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = FmmPlan(X, kernel=kernel, shape=w.shape, tol=tol)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        info = plan.info()
+        bands = plan.bands()
+        sum_p = sum(b["half_nodes"] for b in bands)
+        u = torch.empty_like(lam)
+        for _ in range(warmup):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        plan.set_profiling(True)
+        for _ in range(3):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        ph = plan.phase_times()
+        plan.set_profiling(False)
+        calls = max(ph.pop("calls"), 1)
+        phase_ms = {k: v / calls for k, v in ph.items()}
+        fp_peak = FP64_VEC_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
+        mfma_peak = FP64_MFMA_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
+        model = {"p2p": ("alu", info["near_pairs"] * residual_pair_flops(info["d"])),
+                 "p2m": ("alu" if bytes_ == 8 else "mfma", 8.0 * n * sum_p),
+                 "l2p": ("mfma", 8.0 * n * sum_p)}
+        roofs = {k: roofline_of(*model[k], phase_ms[k], fp_peak, mfma_peak) for k in model if phase_ms.get(k, 0) > 0}
+        dom = max(roofs, key=lambda k: phase_ms[k])
+        roof = dict(roofs[dom], kernel=dom, traffic=None)
+        out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "tol": tol, "plan_ms": plan_ms,
+                     "bands": len(bands), "sum_half_nodes": sum_p, "near_level": info["coarse_level"],
+                     "near_pairs": info["near_pairs"], "residual_width": info["residual_width"],
+                     "phase_ms": phase_ms, "roofline": roof,
+                     "phase_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4),
+                                            "achieved": round(v["achieved"], 3), "unit": v["unit"]}
+                                        for k, v in roofs.items()}}
+        if ref is not None:
+            from oracle import direct
+            out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
+        log(f"[bench] {kernel} {name}: {ms:.2f} ms per product, {len(bands)} bands, "
+            f"err {out[name].get('rel_l2_sampled', float('nan')):.2e}")
+        plan.close()
+        del X, lam, u
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_c4(args):
@@ -352,9 +445,9 @@ def run_c4(args):
 
 def run_c2mq(args):
     """3-D mixed points (as the default workload), multiquadric (or, with --mq-kernel, inverse
-    multiquadric) c = 0.02: the plan holds one leaf and the product is the exact sum through
-    the tiled direct kernel (no band-limited far field for these kernels in this library).  FP64
-    and FP32; the oracle checks 2048 targets."""
+    multiquadric) c = 0.02: the banded far field, FP64 at tol 1e-6 and FP32 at 1e-4 (with
+    --mq-kernel thin_plate or r5: the exact sum, the only product those kernels have).  The
+    oracle checks 2048 targets."""
     import torch
 
     from paper_1606_07652_amd import FmmPlan
@@ -363,7 +456,6 @@ def run_c2mq(args):
     kern = args.mq_kernel
     w = c2("multiquadric", n=args.n)
     n = w.points.shape[0]
-    out = {}
     rng = np.random.default_rng(123)
     idx = np.sort(rng.choice(n, 2048, replace=False))
     ref = None
@@ -373,30 +465,39 @@ def run_c2mq(args):
         t1 = time.perf_counter()
         ref = direct.direct_sum(xs, w.lam.astype(np.float64), kern, w.shape, targets=xs[idx])
         tcpu = time.perf_counter() - t1
-    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
-        lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
-        plan = FmmPlan(X, kernel=kern, shape=w.shape, tol=1e-6)
-        u = torch.empty_like(lam)
-        plan.matvec(lam, u)
-        torch.cuda.synchronize()
-        steps = max(2, args.steps // 4)
-        t0 = time.perf_counter()
-        for _ in range(steps):
+    if kern in ("multiquadric", "inverse_multiquadric"):
+        out = banded_leg(torch, FmmPlan, w, kern, max(2, args.steps // 2), 2, idx, ref)
+        metric = f"RBF-FMM matvec points/s @ rel-L2<=1e-6, {kern.replace('_', ' ')} (banded far field)"
+    else:
+        out = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
+            lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
+            plan = FmmPlan(X, kernel=kern, shape=w.shape, tol=1e-6)
+            u = torch.empty_like(lam)
             plan.matvec(lam, u)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "pairs_per_s": float(n) * n / (ms * 1e-3)}
-        if ref is not None:
-            out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
-        log(f"[bench] {kern} {name}: {ms:.1f} ms per product")
-        plan.close()
-    result = {"metric": f"RBF matvec points/s, {kern.replace('_', ' ')} (exact sum)", "value": out["f64"]["points_per_s"],
-              "unit": "points/s", "n_gpus": 1, "steps": max(2, args.steps // 4), "warmup": 1,
+            torch.cuda.synchronize()
+            steps = max(2, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.matvec(lam, u)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3),
+                         "pairs_per_s": float(n) * n / (ms * 1e-3)}
+            if ref is not None:
+                out[name]["rel_l2_sampled"] = direct.rel_l2(u.double().cpu().numpy()[idx], ref)
+            log(f"[bench] {kern} {name}: {ms:.1f} ms per product")
+            plan.close()
+        metric = f"RBF matvec points/s, {kern.replace('_', ' ')} (exact sum)"
+    result = {"metric": metric, "value": out["f64"]["points_per_s"],
+              "unit": "points/s", "n_gpus": 1, "steps": max(2, args.steps // 2), "warmup": 2,
               "ms_per_step": out["f64"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
               "config": {"workload": f"3d_mixed_uniform_blobs_{kern}_c0.02", "n": n, "kernel": kern,
                          "shape": w.shape}, "paths": out}
+    if "roofline" in out["f64"]:
+        result["roofline"] = out["f64"]["roofline"]
     if ref is not None:
         result["cpu_baseline"] = {"value": 2048 / tcpu, "unit": "points/s", "cores": direct.threads(),
                                   "kind": "oracle", "sample": f"2048 seeded targets x all {n} sources ({tcpu:.1f} s)"}
@@ -582,6 +683,12 @@ def main():
     ap.add_argument("--n-c4", type=int, default=1 << 18)
     ap.add_argument("--n-solve", type=int, default=1 << 21)
     ap.add_argument("--solve-iters", type=int, default=300)
+    ap.add_argument("--no-mq", action="store_true", help="skip the multiquadric leg of the default run")
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES leg of the default run")
+    ap.add_argument("--n-solve-default", type=int, default=1 << 18,
+                    help="points of the GMRES leg of the default run")
+    ap.add_argument("--solve-cap-default", type=int, default=200,
+                    help="iteration cap of the GMRES leg of the default run")
     ap.add_argument("--nprob", type=int, default=512)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batched-solve", action="store_true",
@@ -639,10 +746,13 @@ def main():
     roof = roofline_of(*model[dom], ph[dom], FP64_VEC_TFLOPS)
     roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
+    if dom == "p2p":
+        roof["pairs_per_s"] = info["near_pairs"] / (ph[dom] * 1e-3)
+        roof["flops_per_pair"] = gauss_pair_flops(info["d"], 8)
     phase_roof = {k: roofline_of(*model[k], ph[k], FP64_VEC_TFLOPS) for k in model if ph.get(k, 0) > 0}
 
     result = {
-        "metric": "RBF-FMM matvec points/s @ rel-L2<=1e-6",
+        "metric": "RBF-FMM matvec points/s @ rel-L2<=1e-6; GMRES time-to-1e-8 learned-PC vs plain",
         "value": n / (main_run["ms_per_step"] * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
@@ -668,6 +778,24 @@ def main():
         result["fp32_path"] = {"value": n / (f32_run["ms_per_step"] * 1e-3), "unit": "points/s", "tol": 1e-4,
                                "ms_per_step": f32_run["ms_per_step"], "nodes": f32_run["info"]["nodes"],
                                "phase_ms": f32_run["phase_ms"]}
+
+    if not args.no_mq:
+        # the multiquadric half of the workload: same points and weights, c = 0.02
+        wm = c2("multiquadric", n=args.n)
+        idx_m, ref_m = None, None
+        if not args.no_cpu:
+            from oracle import direct
+            rng = np.random.default_rng(124)
+            idx_m = np.sort(rng.choice(n, 2048, replace=False))
+            xs = wm.points.astype(np.float64)
+            ref_m = direct.direct_sum(xs, wm.lam.astype(np.float64), "multiquadric", wm.shape, targets=xs[idx_m])
+        legs = banded_leg(torch, FmmPlan, wm, "multiquadric", max(2, args.steps // 2), 2, idx_m, ref_m)
+        result["multiquadric"] = {"value": legs["f64"]["points_per_s"], "unit": "points/s", "shape": wm.shape,
+                                  "tol": 1e-6, "ms_per_step": legs["f64"]["ms_per_step"], "paths": legs}
+    if not args.no_solve:
+        from paper_1606_07652_amd import pc
+        result["solve"] = solve_family(torch, FmmPlan, pc, "multiquadric", 0.02, args.n_solve_default, 1e-8,
+                                       args.solve_cap_default)
 
     if not args.no_cpu:
         # cpu_baseline leg: the oracle's direct sum on a bounded sample of targets; the same
