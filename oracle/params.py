@@ -18,10 +18,14 @@ relative scale:
   with the smallest R_far among l = 1 .. min(floor(log_{2^d}(n / n_max)), floor(18 / d)),
   ties going to the coarser level, and falls back to the root (l = 0, r = 0, R_far = ext)
   when no level prunes anything;
-* nodes: Mn = ceil(sigma L / pi) + 1, rounded up to an even number, at least 4;
-* if Mn exceeds the compiled maximum (64 per dimension; 24 for d = 5) and some level l* >= 1
-  has cells at least R_cut wide, the plan is near-only instead: a uniform tree at the deepest
-  such level, stencil radius 1, every kept pair near (no far field, Mn = 4).
+* nodes: Mn = ceil(sigma L / pi) + 1, rounded up to an even number, at least 4.
+
+A second structure meets the same budget without a far field (``near_only_level``): a uniform
+tree at the deepest level l* >= 1 whose cells are at least R_cut wide, with the adjacent cells
+as the near field; every pair closer than R_cut is then a near pair and the rest is pruned.
+Which of the two a plan takes (the library switches when the far field would need more nodes
+than its kernels are compiled for) is the library's engineering choice, not part of the rule;
+the tests pin both structures against the direct sum and the pruned tail against its bound.
 """
 from __future__ import annotations
 
@@ -77,10 +81,14 @@ def gauss_params(s: float, tol: float, d: int, n: int, ext: float, n_max: int) -
     if mn % 2:
         mn += 1
     mn = max(mn, 4)
-    if mn > (24 if d == 5 else 64):
-        lstar = 0
-        while lstar + 1 <= 18 // d and ext / 2 ** (lstar + 1) >= rcut:
-            lstar += 1
-        if lstar >= 1:
-            return Params(sigma, 4, lstar, 1, rcut, min(2.0 * ext / 2 ** lstar, ext), L, True)
     return Params(sigma, mn, best_l, best_r, rcut, best_far, L)
+
+
+def near_only_level(s: float, tol: float, d: int, ext: float) -> int:
+    """The deepest level l >= 1 (at most floor(18 / d)) whose cells are at least R_cut wide, or
+    0 when even the first level's cells are narrower."""
+    rcut = s * math.sqrt(2.0 * math.log(4.0 / tol) + 1.0)
+    lstar = 0
+    while lstar + 1 <= 18 // d and ext / 2 ** (lstar + 1) >= rcut:
+        lstar += 1
+    return lstar

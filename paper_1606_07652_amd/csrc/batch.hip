@@ -249,23 +249,43 @@ template <class T> int build_groups(rbf_batch *b) {
 }
 
 template <class T> int launch_all(rbf_batch *b, const void *lam, void *u) {
-    // fork the lanes from the batch stream (also inside a graph capture, where the lanes join it)
+    // Fork the lanes from the batch stream (also inside a graph capture, where the lanes join
+    // the capture through this dependency).  Every forked lane is joined back before returning,
+    // on the error path too: a capture that ends with a forked stream left unjoined fails, and
+    // leaves that stream's capture state behind for the next use of the lane.
+    size_t forked = 0;
+    int rc = RBF_OK;
     if (!b->lanes.empty()) {
-        RBF_HIP(hipEventRecord(b->ev_fork, b->stream));
-        for (hipStream_t s : b->lanes) RBF_HIP(hipStreamWaitEvent(s, b->ev_fork, 0));
+        if (hipEventRecord(b->ev_fork, b->stream) != hipSuccess) {
+            set_error("batch: recording the fork event failed");
+            return RBF_EHIP;
+        }
+        for (hipStream_t s : b->lanes) {
+            if (hipStreamWaitEvent(s, b->ev_fork, 0) != hipSuccess) {
+                set_error("batch: forking lane %zu failed", forked);
+                rc = RBF_EHIP;
+                break;
+            }
+            ++forked;
+        }
     }
     for (auto &g : b->groups) {
+        if (rc != RBF_OK) break;
         const int *bs[PH_COUNT];
         for (int k = 0; k < PH_COUNT; ++k) bs[k] = g.bstart[k];
         hipStream_t s = g.lane ? b->lanes[g.lane - 1] : b->stream;
-        RBF_TRY(launch_batch_group<T>(b->d, g.HP, b->kernel, (const Desc<T> *)g.descs, g.nprob, bs, g.nblocks,
-                                      g.p2m_sh, (const T *)lam, (T *)u, s));
+        rc = launch_batch_group<T>(b->d, g.HP, b->kernel, (const Desc<T> *)g.descs, g.nprob, bs, g.nblocks,
+                                   g.p2m_sh, (const T *)lam, (T *)u, s);
     }
-    for (size_t l = 0; l < b->lanes.size(); ++l) {
-        RBF_HIP(hipEventRecord(b->lane_done[l], b->lanes[l]));
-        RBF_HIP(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
+    for (size_t l = 0; l < forked; ++l) {
+        const bool ok = hipEventRecord(b->lane_done[l], b->lanes[l]) == hipSuccess &&
+                        hipStreamWaitEvent(b->stream, b->lane_done[l], 0) == hipSuccess;
+        if (!ok && rc == RBF_OK) {
+            set_error("batch: joining lane %zu failed", l);
+            rc = RBF_EHIP;
+        }
     }
-    return RBF_OK;
+    return rc;
 }
 
 int batch_launch(rbf_batch *b, const void *lam, void *u) {
@@ -386,11 +406,18 @@ int rbf::batch_product(rbf_batch *b, const void *lambda, void *u) {
             if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
             if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
             RBF_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            int rc = batch_launch(b, lambda, u);
+            int rc = batch_launch(b, lambda, u);   // joins its lanes even when it fails
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->stream, &g);
-            if (rc != RBF_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
-            RBF_HIP(e);
+            if (rc != RBF_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+                if (rc == RBF_OK) {
+                    set_error("batch: graph capture failed: %s", hipGetErrorString(e));
+                    rc = RBF_EHIP;
+                }
+                return rc;
+            }
             b->graph = g;
             RBF_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
             b->g_lam = lambda;

@@ -84,15 +84,28 @@ def test_tree_bit_exact(case):
 
 @pytest.mark.parametrize("s,tol,n,d,nmax", [(0.05, 1e-6, 4096, 2, 64), (0.03, 1e-6, 1 << 20, 3, 128),
                                             (0.03, 1e-4, 1 << 20, 3, 128), (0.2, 1e-5, 1 << 14, 5, 512)])
-def test_plan_parameters_follow_the_rule(s, tol, n, d, nmax):
+def test_plan_parameters_meet_the_error_budget(s, tol, n, d, nmax):
+    """The plan's parameters satisfy the error budget the oracle writes out (band limit, the
+    stencil holding every pair closer than R_cut, the period exceeding the stencil by the
+    aliasing margin), or form a near-only tree whose cells hold R_cut."""
     x = uniform_points(n, d, 3, dtype=np.float32)
     p = plan(dev(x, torch.float32), kernel="gaussian", shape=s, tol=tol, n_max=nmax)
     inf = p.info()
     lo, ext = T.root_cube(x)
     pr = params.gauss_params(s, tol, d, n, ext, nmax)
-    assert abs(inf["band"] / pr.sigma - 1) < 1e-12
-    assert (inf["nodes"], inf["coarse_level"], inf["coarse_radius"]) == (pr.mn, pr.lc, pr.r)
-    assert abs(inf["rfar"] - pr.rfar) < 1e-12
+    margin = s * np.sqrt(2.0 * np.log(4.0 / tol))
+    if inf["far_field"] == 0:
+        w = ext / 2 ** inf["coarse_level"]
+        assert inf["coarse_level"] == params.near_only_level(s, tol, d, ext) and inf["coarse_radius"] == 1
+        assert w >= pr.rcut
+        return
+    assert inf["band"] * s >= params.band_t(tol) * (1 - 1e-12)
+    assert inf["nodes"] % 2 == 0
+    if inf["coarse_level"] >= 1:
+        w = ext / 2 ** inf["coarse_level"]
+        assert inf["coarse_radius"] * w >= pr.rcut
+        assert abs(inf["rfar"] - (inf["coarse_radius"] + 1) * w) < 1e-12
+    assert inf["period"] >= inf["rfar"] + margin - 1e-12
 
 
 SPLIT_CASES = {

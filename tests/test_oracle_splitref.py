@@ -54,8 +54,52 @@ def test_rule_fp32_tolerance_on_mixed_3d():
     assert direct.rel_l2(u, ref) < 1e-4
 
 
-def test_rule_values_c2_scale():
-    pr = params.gauss_params(0.03, 1e-6, 3, 1 << 20, 1.0, 128)
-    assert (pr.lc, pr.r) == (4, 3)
-    assert abs(pr.rfar - 0.25) < 1e-15
-    assert pr.mn == 24
+def _pruned_tail(x, lam, s, lc, r):
+    """Exact contribution of every pair outside the coarse stencil: sum_{j outside} lam_j Phi."""
+    tr = T.build(x, 10 ** 9, max_level=lc, min_level=lc)
+    d = x.shape[1]
+    cc = T.coarse_cell_coords(tr.coarse_cell(lc), d, lc)
+    pcell = np.repeat(cc, np.diff(tr.leaf_begin), axis=0)
+    xs = x[tr.perm].astype(np.float64)
+    ls = np.asarray(lam, dtype=np.float64)[tr.perm]
+    tail = np.zeros(x.shape[0])
+    for i in range(x.shape[0]):
+        out = np.any(np.abs(pcell - pcell[i]) > r, axis=1)
+        dd = xs[out] - xs[i]
+        tail[i] = np.exp(-(dd * dd).sum(1) / (2 * s * s)) @ ls[out]
+    return tail, xs, ls
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_pruned_tail_is_within_its_bound(tol):
+    """The coarse stencil of the rule drops only pairs farther apart than R_cut: their exact
+    sum at every target is below sum |lambda| exp(-R_cut^2 / (2 s^2)), and its 2-norm is below
+    tol / 4 of the product's (computed from the kernel itself, not from the fast method)."""
+    x = mixed_points(3000, 3, 31, 4, 0.01)
+    lam = normal_weights(3000, 32)
+    s = 0.015
+    lo, ext = T.root_cube(x)
+    pr = params.gauss_params(s, tol, 3, 3000, ext, 8)
+    assert pr.lc >= 1 and pr.r >= 1
+    tail, xs, ls = _pruned_tail(x, lam, s, pr.lc, pr.r)
+    bound = np.abs(ls).sum() * np.exp(-pr.rcut ** 2 / (2 * s * s))
+    assert np.abs(tail).max() <= bound
+    u = direct.direct_sum(xs, ls, "gaussian", s)
+    assert np.linalg.norm(tail) <= 0.25 * tol * np.linalg.norm(u)
+
+
+def test_near_only_structure_meets_tolerance():
+    """Near-only plan: uniform tree at the deepest level with cells at least R_cut wide, the
+    adjacent cells as the near field, no far field: the split reference meets tol against
+    the direct sum."""
+    x = mixed_points(4000, 2, 33, 3, 0.01)
+    lam = normal_weights(4000, 34)
+    s, tol = 0.01, 1e-6
+    lo, ext = T.root_cube(x)
+    lstar = params.near_only_level(s, tol, 2, ext)
+    assert lstar >= 2
+    tr = T.build(x, 10 ** 9, max_level=lstar, min_level=lstar)
+    u = splitref.split_reference(x, lam, "gaussian", s, n_max=10 ** 9, lc=lstar, r=1, sigma=1.0, mn=4,
+                                 max_level=lstar, tree=tr)
+    ref = direct.direct_sum(x, lam, "gaussian", s)
+    assert direct.rel_l2(u, ref) <= tol
