@@ -55,6 +55,20 @@
    half period.  (The paper does not window; reading: the periodic extension of a growing
    kernel needs it.)
 
+4. Anti-periodic fold (reading).  With Mn even the trapezoid nodes are the odd multiples of
+   half the node spacing, so every term e^{i xi_m t} changes sign under t -> t + L: the
+   quadrature kernel is anti-periodic with period L along each axis, and it interpolates the
+   samples of its own anti-periodic extension.  A band that has not decayed at the half period
+   L / 2 but is negligible beyond L - ext is therefore sampled as
+
+       K_fold(r) = sum_{n in Z^d} prod_k (-1)^{n_k} K(r + n L),
+
+   which equals K on the bounding cube (every image term there is at distance >= L - ext) and
+   is smooth and anti-periodic, so its trigonometric interpolant converges; sampling K alone
+   (a jump at the period's end) or its plain periodic sum (the wrong parity) converges only to
+   the size of K at L / 2 (pinned: the folded samples reproduce a band inside the cube, the
+   other two do not).
+
 Parity: the closed forms are pinned against numerical integration of the definitions; the
 sample-based C against the analytic Gaussian C and against lattice reproduction; bands
 against the numerical transform of a Gaussian mixture.  The product built on them is judged
@@ -182,3 +196,20 @@ def quad_kernel(C, sigma: float, mn: int, r):
 def radial(kfun_b, c: float):
     """Wrap a function of b into a function of the difference vector r."""
     return lambda r: kfun_b(np.sqrt(np.sum(np.asarray(r) ** 2, axis=-1) + c * c))
+
+
+def fold_antiperiodic(kfun, L: float, reach: float, d: int):
+    """K_fold of item 4: the images of kfun within ``reach`` of the origin cell, signed by the
+    parity of their lattice offsets."""
+    import itertools
+    nmax = int(math.ceil(reach / L)) + 1
+    offs = [np.array(n, dtype=np.float64) for n in itertools.product(range(-nmax, nmax + 1), repeat=d)]
+
+    def f(r):
+        r = np.asarray(r, dtype=np.float64)
+        out = np.zeros(r.shape[:-1])
+        for n in offs:
+            sign = -1.0 if int(np.abs(n).sum()) % 2 else 1.0
+            out = out + sign * kfun(r + n * L)
+        return out
+    return f

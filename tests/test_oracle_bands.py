@@ -137,3 +137,28 @@ def test_windowed_top_is_reproduced_inside_the_cube():
     r = np.random.default_rng(3).uniform(-ext, ext, (500, d))
     ref = B.top(B.MQ, np.sqrt(np.sum(r * r, -1) + C_MQ ** 2), st)
     assert np.abs(B.quad_kernel(C, sigma, mn, r) - ref).max() < 1e-6
+
+
+def test_antiperiodic_fold_reproduces_a_band_wider_than_half_the_period():
+    """A band not negligible at L / 2 (4e-6 of its peak) but negligible beyond L - ext: the
+    quadrature kernel (even Mn) built from folded samples matches the band on the whole
+    bounding cube to 1e-8 of its peak; from plain samples, or from the periodic sum, it
+    misses by more than ten times that (item 4 of the module)."""
+    d, lo, ext, L = 2, 0.2, 1.0, 2.6
+    hi = lo * math.sqrt(2)
+    band = B.radial(lambda b: B.band(B.MQ, b, lo, hi), C_MQ)
+    peak = abs(band(np.zeros((1, d)))[0])
+    assert abs(band(np.array([[L / 2, 0.0]]))[0]) > 1e-6 * peak
+    r = np.random.default_rng(8).uniform(-ext, ext, (400, d))
+    ref = band(r)
+    mn = 34
+    sigma = math.pi * (mn - 1) / L
+    periodic = lambda x: sum(band(np.asarray(x) + np.array([i, j]) * L)
+                             for i in range(-3, 4) for j in range(-3, 4))
+    errs = {}
+    for name, k in (("fold", B.fold_antiperiodic(band, L, 8 * hi, d)), ("plain", band),
+                    ("periodic", periodic)):
+        C = B.sample_c(k, sigma, mn, d)
+        errs[name] = np.abs(B.quad_kernel(C, sigma, mn, r) - ref).max() / peak
+    assert errs["fold"] <= 1e-8
+    assert errs["plain"] > 10 * errs["fold"] and errs["periodic"] > 10 * errs["fold"]
