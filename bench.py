@@ -85,8 +85,9 @@ def residual_pair_flops(d):
 
 
 def measured_traffic(phase):
-    """HBM bytes per launch of a phase from the committed counter table, if that table was taken
-    on the current kernel source (else None)."""
+    """HBM bytes of a phase per product (its launches summed: one for every phase but the three
+    axis passes of the coarse translation) from the committed counter table, if that table was
+    taken on the current kernel source (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_3d_mixed_gauss_n1m.json")
     src = os.path.join(ROOT, "paper_1606_07652_amd", "csrc", "fmm.hip")
@@ -95,7 +96,75 @@ def measured_traffic(phase):
     tab = json.load(open(path))
     if tab.get("fmm_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    return tab.get("bytes_per_launch", {}).get(phase)
+    return tab.get("bytes_per_product", {}).get(phase)
+
+
+# kernel name prefix (as the profiler prints it, template arguments stripped) -> phase
+TRAFFIC_PHASES = {"k_gather": "permute", "k_phase_dl": "p2m_phase", "k_p2m": "p2m", "k_p2p": "p2p",
+                  "k_m2m": "m2m", "k_m2l_axis": "m2l_coarse", "k_m2l_leaf": "m2l_leaf", "k_l2p": "l2p"}
+
+
+def write_traffic_table(fetch_dir, write_dir, out_path, workload):
+    """Turn two rocprofv3 counter runs of the FP64 default workload (``--pmc FETCH_SIZE`` and
+    ``--pmc WRITE_SIZE``, each with ``--copy-check``) into the HBM byte table that the bench
+    reads: per phase, bytes per product.  Counter values are KiB per dispatch; each counter is
+    scaled by what it reads for the 1 GiB copy of ``--copy-check`` (the largest
+    ``__amd_rocclr_copyBuffer`` dispatch), and the number of products is the number of
+    ``k_l2p<double`` dispatches (one per product)."""
+    import csv
+    import glob
+    import hashlib
+    import re
+
+    def load(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        per = {}
+        for fn in files:
+            for row in csv.DictReader(open(fn)):
+                if row["Counter_Name"] != counter:
+                    continue
+                key = (fn, row["Dispatch_Id"])
+                name = row["Kernel_Name"]
+                per.setdefault(key, [name, 0.0])[1] += float(row["Counter_Value"])
+        return list(per.values())
+
+    def phase_of(name):
+        m = re.search(r"\b(k_[A-Za-z0-9_]+)", name)
+        return TRAFFIC_PHASES.get(m.group(1)) if m else None
+
+    tab = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = load(d, counter)
+        copies = [v for n, v in rows if n.startswith("__amd_rocclr_copyBuffer")]
+        if not copies:
+            raise SystemExit(f"{counter}: no copy dispatch (run with --copy-check)")
+        factor = (1 << 20) / max(copies)            # 1 GiB in KiB over what the counter read
+        products = sum(1 for n, _ in rows if "k_l2p<double" in n)
+        sums = {}
+        for n, v in rows:
+            if "<float" in n:
+                continue
+            ph = phase_of(n)
+            if ph is not None:
+                sums[ph] = sums.get(ph, 0.0) + v
+        tab[key] = {"factor": factor, "products": products,
+                    "bytes": {ph: v * 1024.0 * factor / max(products, 1) for ph, v in sums.items()}}
+    src = os.path.join(ROOT, "paper_1606_07652_amd", "csrc", "fmm.hip")
+    phases = sorted(set(tab["fetch"]["bytes"]) | set(tab["write"]["bytes"]))
+    out = {"workload": workload,
+           "fmm_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "fetch_factor": tab["fetch"]["factor"], "write_factor": tab["write"]["factor"],
+           "products": tab["fetch"]["products"],
+           "fetch_bytes_per_product": {p: tab["fetch"]["bytes"].get(p, 0.0) for p in phases},
+           "write_bytes_per_product": {p: tab["write"]["bytes"].get(p, 0.0) for p in phases},
+           "bytes_per_product": {p: tab["fetch"]["bytes"].get(p, 0.0) + tab["write"]["bytes"].get(p, 0.0)
+                                for p in phases}}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
 
 
 def roofline_of(kind, amount, ms, fp_peak, mfma_peak=FP64_MFMA_TFLOPS):
@@ -697,7 +766,13 @@ def main():
     ap.add_argument("--mq-kernel", default="multiquadric",
                     choices=["multiquadric", "inverse_multiquadric", "thin_plate", "r5"],
                     help="with --workload c2mq: the kernel of the exact sum")
+    ap.add_argument("--traffic-table", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="write the HBM byte table from two rocprofv3 counter runs (no GPU work)")
     args = ap.parse_args()
+    if args.traffic_table:
+        return write_traffic_table(*args.traffic_table,
+                                   workload="3-D mixed uniform/blob points, N=2^20, Gaussian s=0.03, "
+                                            "FP64 tol 1e-6 (leaf capacity 256)")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs "
               "is not built", file=sys.stderr)
