@@ -308,7 +308,11 @@ int rbf_fmm_batch_destroy(rbf_batch *batch);
  * recomputed at every restart; a problem that stops early takes zero directions).
  *   f, lambda  device, concatenated like the points, batch dtype; lambda is the initial
  *              guess (unless opts->zero_init) and the solution.
- *   opts       as for rbf_interp_solve; precond must be RBF_PC_NONE (else RBF_EUNSUPPORTED).
+ *   opts       as for rbf_interp_solve; precond RBF_PC_NONE or RBF_PC_BLOCK_JACOBI (else
+ *              RBF_EUNSUPPORTED).  Block-Jacobi makes the solve flexible GMRES with every
+ *              problem's own 64-point blocks (below) as its right preconditioner, applied to
+ *              all problems by one launch per direction; blocks missing at the first call are
+ *              built with the default regularisation; m more vectors of n doubles are held.
  *   info       host array of nprob rbf_solve_info (may be NULL).
  * Work is ordered on the batch's stream argument.  Returns RBF_OK if every problem
  * converged, RBF_ENOCONV otherwise.  Synchronous. */

@@ -223,5 +223,20 @@ int plan_bands(rbf_plan *p);                                         // bands.hi
 bool banded_kernel(int kernel, int d);                               // bands.hip
 int pc_ready(rbf_plan *p, int kind);                                 // pc.hip
 int pc_apply(rbf_plan *p, int kind, const double *v, double *z);     // pc.hip
+// Block-Jacobi over the problems of a batch (pc.hip): problem q's vector entries sit at
+// [off[q], off[q + 1]) in caller order, its blocks are global blocks [bfirst[q], bfirst[q + 1]).
+// All arrays are device arrays of nprob (+ 1) entries.
+struct BatchBj {
+    const double *const *inv;   // problem q's block inverses (its plan's)
+    const int *const *perm;     // problem q's permutation, sorted -> caller order
+    const int64_t *off;
+    const int64_t *bfirst;
+    int nprob;
+    int64_t nblk;
+};
+// builds every plan's block inverses (default regularisation) when missing and fills bj
+int batch_bj_prepare(const std::vector<rbf_plan *> &plans, const std::vector<int64_t> &offsets, Arena &ar,
+                     hipStream_t s, BatchBj *bj);
+int batch_bj_apply(const BatchBj &bj, const double *v, double *z, hipStream_t s);
 int mlp_infer_bf16(rbf_mlp *m, const float *x, int64_t rows, float *y, hipStream_t s);   // mlp.hip
 }  // namespace rbf

@@ -155,6 +155,36 @@ __global__ void __launch_bounds__(kT) k_bj_rows(const double *__restrict__ inv, 
     x_out[b * BS + lane] = s > 0.0 ? (float)(y / s) : 0.f;
 }
 
+// Block-Jacobi over a batch: wave = one global block; its problem by binary search over the
+// first-block table, then as k_bj_rows<0> on that problem's slice of v and z.
+__global__ void __launch_bounds__(kT) k_bj_rows_batch(BatchBj bj, const double *__restrict__ v,
+                                                      double *__restrict__ z) {
+    __shared__ double vs[kT / BS][BS];
+    const int lane = threadIdx.x & (BS - 1), w = threadIdx.x / BS;
+    const int64_t b = blockIdx.x * (int64_t)(kT / BS) + w;
+    int q = 0;
+    if (b < bj.nblk) {
+        int lo = 0, hi = bj.nprob;   // largest q with bfirst[q] <= b
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bj.bfirst[mid] <= b) lo = mid; else hi = mid;
+        }
+        q = lo;
+    }
+    const int64_t lb = b - bj.bfirst[q], off = bj.off[q], nq = bj.off[q + 1] - off;
+    const int64_t g = lb * BS + lane;
+    const bool valid = b < bj.nblk && g < nq;
+    const int *perm = bj.perm[q];
+    vs[w][lane] = valid ? v[off + perm[g]] : 0.0;
+    __syncthreads();
+    if (b >= bj.nblk) return;
+    const double *col = bj.inv[q] + lb * BS * BS + lane;
+    double y = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < BS; ++j) y = fma(col[j * BS], vs[w][j], y);
+    if (valid) z[off + perm[g]] = y;
+}
+
 // z[perm[g]] = y_g + s_b G[b][g - 64 b]   (0 when s_b = 0)
 __global__ void k_pc_combine(const double *__restrict__ y, const double *__restrict__ s, const float *__restrict__ G,
                              const int *__restrict__ perm, int64_t n, double *__restrict__ z) {
@@ -384,6 +414,49 @@ int pc_apply(rbf_plan *p, int kind, const double *v, double *z) {
     }
     set_error("pc_apply: preconditioner %d cannot be applied", kind);
     return RBF_EINVAL;
+}
+
+int batch_bj_prepare(const std::vector<rbf_plan *> &plans, const std::vector<int64_t> &offsets, Arena &ar,
+                     hipStream_t s, BatchBj *bj) {
+    const int P = (int)plans.size();
+    std::vector<const double *> inv(P);
+    std::vector<const int *> perm(P);
+    std::vector<int64_t> bfirst(P + 1, 0);
+    for (int q = 0; q < P; ++q) {
+        rbf_plan *p = plans[q];
+        if (p->n != offsets[q + 1] - offsets[q]) {
+            set_error("batched block-Jacobi: problem %d has %lld points, its plan %lld", q,
+                      (long long)(offsets[q + 1] - offsets[q]), (long long)p->n);
+            return RBF_EINVAL;
+        }
+        RBF_TRY(check_bj_kernel(p));
+        if (p->bj_reg < 0) RBF_TRY(build_bj(p, kDefaultBjReg * phi_zero(p)));
+        inv[q] = p->bj_inv;
+        perm[q] = p->perm;
+        bfirst[q + 1] = bfirst[q] + p->nblk;
+    }
+    const double **dinv = nullptr;
+    const int **dperm = nullptr;
+    int64_t *doff = nullptr, *dbf = nullptr;
+    RBF_TRY(ar.alloc((void **)&dinv, sizeof(double *) * P));
+    RBF_TRY(ar.alloc((void **)&dperm, sizeof(int *) * P));
+    RBF_TRY(ar.alloc((void **)&doff, sizeof(int64_t) * (P + 1)));
+    RBF_TRY(ar.alloc((void **)&dbf, sizeof(int64_t) * (P + 1)));
+    RBF_HIP(hipMemcpyAsync(dinv, inv.data(), sizeof(double *) * P, hipMemcpyHostToDevice, s));
+    RBF_HIP(hipMemcpyAsync(dperm, perm.data(), sizeof(int *) * P, hipMemcpyHostToDevice, s));
+    RBF_HIP(hipMemcpyAsync(doff, offsets.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, s));
+    RBF_HIP(hipMemcpyAsync(dbf, bfirst.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, s));
+    RBF_HIP(hipStreamSynchronize(s));   // the host tables above go out of scope
+    *bj = BatchBj{dinv, dperm, doff, dbf, P, bfirst[P]};
+    return RBF_OK;
+}
+
+int batch_bj_apply(const BatchBj &bj, const double *v, double *z, hipStream_t s) {
+    if (bj.nblk <= 0) return RBF_OK;
+    const unsigned nb = (unsigned)((bj.nblk + kT / BS - 1) / (kT / BS));
+    k_bj_rows_batch<<<nb, kT, 0, s>>>(bj, v, z);
+    RBF_HIP(hipGetLastError());
+    return RBF_OK;
 }
 
 }  // namespace rbf

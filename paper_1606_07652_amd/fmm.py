@@ -93,14 +93,16 @@ class BatchPlan:
         return out
 
     def solve(self, f: torch.Tensor, lam: Optional[torch.Tensor] = None, rtol: float = 1e-8, restart: int = 50,
-              max_iters: int = 1000, time_limit_s: float = 0.0):
-        """Restarted GMRES for every problem (rbf_interp_solve_batch); returns (lambda, [info per problem])."""
+              max_iters: int = 1000, time_limit_s: float = 0.0, precond: str = "none"):
+        """Restarted GMRES for every problem (rbf_interp_solve_batch), precond "none" or
+        "block_jacobi"; returns (lambda, [info per problem])."""
         if f.shape != (self.n,) or f.dtype != self.dtype:
             raise ValueError("f must be the concatenated right-hand side of all problems")
+        pk = {"none": L.RBF_PC_NONE, "block_jacobi": L.RBF_PC_BLOCK_JACOBI}[precond]
         zero = lam is None
         if lam is None:
             lam = torch.zeros_like(f)
-        o = L.RbfSolveOpts(restart, max_iters, L.RBF_PC_NONE, 1 if zero else 0, 1, float(time_limit_s))
+        o = L.RbfSolveOpts(restart, max_iters, pk, 1 if zero else 0, 1, float(time_limit_s))
         infos = (L.RbfSolveInfo * self.nprob)()
         code = L.load().rbf_interp_solve_batch(self._h, _ptr(f), _ptr(lam), float(rtol), ctypes.byref(o), infos)
         L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
