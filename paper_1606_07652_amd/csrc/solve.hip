@@ -38,6 +38,14 @@ __global__ void k_scale(const double *__restrict__ src, double a, double *__rest
     if (i < n) dst[i] = a * src[i];
 }
 
+// dst = src / sqrt(*nrm2): the next Arnoldi vector, normalised on the device so that the host
+// reads the step's scalars once
+__global__ void k_scale_rsqrt(const double *__restrict__ src, const double *__restrict__ nrm2,
+                              double *__restrict__ dst, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) dst[i] = (1.0 / sqrt(*nrm2)) * src[i];
+}
+
 __device__ double block_sum(double v, double *sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
@@ -215,6 +223,16 @@ struct Solver {
         return RBF_OK;
     }
 
+    // the k dots into device memory, no host read
+    int dots_dev(const double *V, int k, const double *w, double *out) {
+        hipStream_t s = p->stream;
+        k_multidot<<<kDotBlocks, kThreads, 0, s>>>(V, na, k, w, part);
+        RBF_HIP(hipGetLastError());
+        k_reduce_parts<<<k, kThreads, 0, s>>>(part, kDotBlocks, k, out);
+        RBF_HIP(hipGetLastError());
+        return RBF_OK;
+    }
+
     int norm(const double *w, double *out) {
         double v = 0;
         RBF_TRY(dots(w, 1, w, &v));
@@ -264,7 +282,8 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     const int kp = std::max(m + 2, kMaxPolyTerms);
     S.part = p->sv;
     S.hdev = p->sv + (size_t)kDotBlocks * kp;
-    S.flag = (int *)(S.hdev + 2 * (m + 2));
+    // hdev: h1 [m + 2], h2 [m + 2], ||w||^2, the preconditioner's status word (one double slot)
+    S.flag = (int *)(S.hdev + 2 * (m + 2) + 1);
     double *base = (double *)p->tvec;
     S.xd = base + 2 * na;  // tvec[0..2n) holds the float in/out pair for F32 plans
     S.fd = base + 3 * na;
@@ -294,7 +313,7 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
     RBF_TRY(S.norm(S.fd, &bnorm));
     rbf_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(m + 2), hh2(m + 2);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hstep(2 * (m + 2) + 1);
     int its = 0, restarts = 0;
     int cur = pck;   // active preconditioner: steps down learned -> block-Jacobi -> none
     auto step_down = [&]() {
@@ -356,16 +375,22 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
                 if (hf) { pc_failed = true; break; }
             }
             RBF_TRY(S.product(zj, S.wd));
-            // CGS2
-            RBF_TRY(S.dots(p->V, j + 1, S.wd, hh.data()));
-            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, S.hdev, -1.0);
+            // CGS2 with the projections and the norm on the device, and the next vector
+            // normalised there; one read of the step's scalars
+            double *h1 = S.hdev, *h2 = S.hdev + (m + 2), *nrm2 = S.hdev + 2 * (m + 2);
+            RBF_TRY(S.dots_dev(p->V, j + 1, S.wd, h1));
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, h1, -1.0);
             RBF_HIP(hipGetLastError());
-            RBF_TRY(S.dots(p->V, j + 1, S.wd, hh2.data()));
-            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, S.hdev, -1.0);
+            RBF_TRY(S.dots_dev(p->V, j + 1, S.wd, h2));
+            k_multiaxpy<<<nb, kThreads, 0, s>>>(S.wd, p->V, na, j + 1, h2, -1.0);
             RBF_HIP(hipGetLastError());
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh2[i];
-            double hn = 0;
-            RBF_TRY(S.norm(S.wd, &hn));
+            RBF_TRY(S.dots_dev(S.wd, 1, S.wd, nrm2));
+            k_scale_rsqrt<<<nb, kThreads, 0, s>>>(S.wd, nrm2, p->V + (size_t)(j + 1) * na, na);
+            RBF_HIP(hipGetLastError());
+            RBF_HIP(hipMemcpyAsync(hstep.data(), S.hdev, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
+            RBF_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hstep[i] + hstep[(size_t)(m + 2) + i];
+            const double hn = std::sqrt(hstep[2 * (size_t)(m + 2)]);
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
                 double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
@@ -382,8 +407,6 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
             k = j + 1;
             if (!std::isfinite(hn)) { pc_failed = use_pc; k = j; break; }
             if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || its >= maxit) break;
-            k_scale<<<nb, kThreads, 0, s>>>(S.wd, 1.0 / hn, p->V + (size_t)(j + 1) * na, na);
-            RBF_HIP(hipGetLastError());
         }
         if (pc_failed) {
             if (!fallback) { set_error("rbf_interp_solve: preconditioner produced non-finite values"); return RBF_EINVAL; }

@@ -142,14 +142,27 @@ struct BatchSolver {
 
     // out (host) [nprob][k] = per-problem dots of V_0..V_{k-1} with w
     int dots(const double *V, int k, const double *w, double *host_out) {
-        k_seg_dots<<<nblk, kT, 0, s>>>(seg, V, n, k, w, part);
-        RBF_HIP(hipGetLastError());
-        k_seg_reduce<<<nprob, kT, 0, s>>>(seg, part, k, hdev);
-        RBF_HIP(hipGetLastError());
+        RBF_TRY(dots_dev(V, k, w, hdev));
         if (host_out) {
             RBF_HIP(hipMemcpyAsync(host_out, hdev, sizeof(double) * nprob * k, hipMemcpyDeviceToHost, s));
             RBF_HIP(hipStreamSynchronize(s));
         }
+        return RBF_OK;
+    }
+
+    // the same dots into device memory out [nprob][k], no host read
+    int dots_dev(const double *V, int k, const double *w, double *out) {
+        k_seg_dots<<<nblk, kT, 0, s>>>(seg, V, n, k, w, part);
+        RBF_HIP(hipGetLastError());
+        k_seg_reduce<<<nprob, kT, 0, s>>>(seg, part, k, out);
+        RBF_HIP(hipGetLastError());
+        return RBF_OK;
+    }
+
+    // w += sign * V h with h already on the device
+    int axpy_dev(double *w, const double *V, int k, const double *h, double sign) {
+        k_seg_axpy<<<nblk, kT, 0, s>>>(seg, w, V, n, k, h, sign);
+        RBF_HIP(hipGetLastError());
         return RBF_OK;
     }
 
@@ -204,7 +217,7 @@ int solve_batch_impl(rbf_batch *b, const void *f, void *lambda, double rtol, con
         (rc = ar.alloc((void **)&w, sizeof(double) * n)) != RBF_OK ||
         (rc = ar.alloc(&S.tin, tsz * n)) != RBF_OK || (rc = ar.alloc(&S.tout, tsz * n)) != RBF_OK ||
         (rc = ar.alloc((void **)&S.part, sizeof(double) * (size_t)S.nblk * (m + 1))) != RBF_OK ||
-        (rc = ar.alloc((void **)&S.hdev, sizeof(double) * (size_t)P * (m + 1))) != RBF_OK ||
+        (rc = ar.alloc((void **)&S.hdev, sizeof(double) * (size_t)P * (2 * (m + 1) + 1))) != RBF_OK ||
         (rc = ar.alloc((void **)&offd, sizeof(int64_t) * (P + 1))) != RBF_OK ||
         (rc = ar.alloc((void **)&bstd, sizeof(int) * (P + 1))) != RBF_OK)
         return fail(rc);
@@ -238,6 +251,7 @@ int solve_batch_impl(rbf_batch *b, const void *f, void *lambda, double rtol, con
     std::memset(inf.data(), 0, sizeof(rbf_solve_info) * P);
     std::vector<double> H((size_t)P * (m + 1) * m), cs((size_t)P * m), sn((size_t)P * m), g((size_t)P * (m + 1));
     std::vector<double> h1((size_t)P * (m + 1)), h2((size_t)P * (m + 1)), hn(P), sc(P), coef;
+    std::vector<double> hstep((size_t)P * (2 * (m + 1) + 1));
     std::vector<int> its(P, 0), kq(P, 0), done(P, 0);
     std::vector<double> rel(P, 0.0);
     auto Hq = [&](int q, int i, int j) -> double & { return H[((size_t)q * (m + 1) + i) * m + j]; };
@@ -272,14 +286,25 @@ int solve_batch_impl(rbf_batch *b, const void *f, void *lambda, double rtol, con
             }
             if ((rc = S.product(vj, w)) != RBF_OK) return fail(rc);
             const int k = j + 1;
-            // CGS2 per problem
-            if ((rc = S.dots(V, k, w, tmp.data())) != RBF_OK) return fail(rc);
-            for (size_t e = 0; e < (size_t)P * k; ++e) h1[e] = tmp[e];
-            if ((rc = S.axpy(w, V, k, h1, -1.0)) != RBF_OK) return fail(rc);
-            if ((rc = S.dots(V, k, w, tmp.data())) != RBF_OK) return fail(rc);
-            for (size_t e = 0; e < (size_t)P * k; ++e) h2[e] = tmp[e];
-            if ((rc = S.axpy(w, V, k, h2, -1.0)) != RBF_OK) return fail(rc);
-            if ((rc = S.dots(w, 1, w, tmp.data())) != RBF_OK) return fail(rc);
+            // CGS2 per problem, projections and norms on the device; one read of the step's
+            // scalars: h1 [P][k], h2 [P][k], ||w_q||^2 [P]
+            double *d1 = S.hdev, *d2 = S.hdev + (size_t)P * k, *dn = S.hdev + 2 * (size_t)P * k;
+            if ((rc = S.dots_dev(V, k, w, d1)) != RBF_OK) return fail(rc);
+            if ((rc = S.axpy_dev(w, V, k, d1, -1.0)) != RBF_OK) return fail(rc);
+            if ((rc = S.dots_dev(V, k, w, d2)) != RBF_OK) return fail(rc);
+            if ((rc = S.axpy_dev(w, V, k, d2, -1.0)) != RBF_OK) return fail(rc);
+            if ((rc = S.dots_dev(w, 1, w, dn)) != RBF_OK) return fail(rc);
+            if (hipMemcpyAsync(hstep.data(), S.hdev, sizeof(double) * (size_t)P * (2 * k + 1), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("rbf_interp_solve_batch: device error");
+                return fail(RBF_EHIP);
+            }
+            for (size_t e = 0; e < (size_t)P * k; ++e) {
+                h1[e] = hstep[e];
+                h2[e] = hstep[(size_t)P * k + e];
+            }
+            for (int q = 0; q < P; ++q) tmp[q] = hstep[2 * (size_t)P * k + q];
             int nlive = 0;
             for (int q = 0; q < P; ++q) {
                 hn[q] = std::sqrt(tmp[q]);
