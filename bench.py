@@ -76,12 +76,13 @@ def gauss_pair_flops(d, dtype_bytes):
     return 3 * d + 3 + (12 if dtype_bytes == 8 else 1)
 
 
-def residual_pair_flops(d):
-    """Per near pair of a banded plan (multiquadric kernels), as the kernel executes it: the
-    distance and the accumulation (3 d + 3), b = sqrt(r^2 + c^2) through the reciprocal square
-    root and two Newton steps (14), the table index and local variable (3) and the degree-5
-    polynomial (10)."""
-    return 3 * d + 3 + 14 + 3 + 10
+def residual_pair_flops(d, dtype_bytes=8):
+    """Per near pair of a banded plan (multiquadric kernels), as the kernel executes it (a fused
+    multiply-add counts 2): the distance and the accumulation (3 d + 3); q = r^2 + c^2, its
+    reciprocal square root and b = q / sqrt q (3, and in FP64 two Newton steps on the root and
+    the half of q: 9 more); the table index and local variable (3); the degree-5 polynomial
+    (10).  The inverse multiquadric's product with 1 / b is not counted."""
+    return 3 * d + 3 + (12 if dtype_bytes == 8 else 3) + 3 + 10
 
 
 def measured_traffic(phase):
@@ -375,7 +376,7 @@ def run_solve(args):
     print(json.dumps(result), flush=True)
 
 
-def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None):
+def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None, level=-1):
     """The banded product of a multiquadric kernel on the workload's points, FP64 (tol 1e-6)
     and FP32 (tol 1e-4): time per product, phase times and roofline fractions, and the
     sampled error against the oracle's direct sum when given."""
@@ -386,12 +387,14 @@ def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None):
         lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = FmmPlan(X, kernel=kernel, shape=w.shape, tol=tol)
+        plan = FmmPlan(X, kernel=kernel, shape=w.shape, tol=tol, coarse_level=level)
         torch.cuda.synchronize()
         plan_ms = (time.perf_counter() - t0) * 1e3
         info = plan.info()
         bands = plan.bands()
-        sum_p = sum(b["half_nodes"] for b in bands)
+        # aggregation and disaggregation run on the bands that are not transferred
+        sum_p = sum(b["half_nodes"] for b in bands if not b["transfer"])
+        moved = sum(1 for b in bands if b["transfer"])
         u = torch.empty_like(lam)
         for _ in range(warmup):
             plan.matvec(lam, u)
@@ -411,14 +414,14 @@ def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None):
         phase_ms = {k: v / calls for k, v in ph.items()}
         fp_peak = FP64_VEC_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
         mfma_peak = FP64_MFMA_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
-        model = {"p2p": ("alu", info["near_pairs"] * residual_pair_flops(info["d"])),
+        model = {"p2p": ("alu", info["near_pairs"] * residual_pair_flops(info["d"], bytes_)),
                  "p2m": ("alu" if bytes_ == 8 else "mfma", 8.0 * n * sum_p),
                  "l2p": ("mfma", 8.0 * n * sum_p)}
         roofs = {k: roofline_of(*model[k], phase_ms[k], fp_peak, mfma_peak) for k in model if phase_ms.get(k, 0) > 0}
         dom = max(roofs, key=lambda k: phase_ms[k])
         roof = dict(roofs[dom], kernel=dom, traffic=None)
         out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "tol": tol, "plan_ms": plan_ms,
-                     "bands": len(bands), "sum_half_nodes": sum_p, "near_level": info["coarse_level"],
+                     "bands": len(bands), "transferred_bands": moved, "sum_half_nodes": sum_p, "near_level": info["coarse_level"],
                      "near_pairs": info["near_pairs"], "residual_width": info["residual_width"],
                      "phase_ms": phase_ms, "roofline": roof,
                      "phase_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4),
@@ -537,7 +540,7 @@ def run_c2mq(args):
         ref = direct.direct_sum(xs, w.lam.astype(np.float64), kern, w.shape, targets=xs[idx])
         tcpu = time.perf_counter() - t1
     if kern in ("multiquadric", "inverse_multiquadric"):
-        out = banded_leg(torch, FmmPlan, w, kern, max(2, args.steps // 2), 2, idx, ref)
+        out = banded_leg(torch, FmmPlan, w, kern, max(2, args.steps // 2), 2, idx, ref, args.mq_level)
         metric = f"RBF-FMM matvec points/s @ rel-L2<=1e-6, {kern.replace('_', ' ')} (banded far field)"
     else:
         out = {}
@@ -765,6 +768,8 @@ def main():
     ap.add_argument("--batched-solve", action="store_true",
                     help="with --workload batched: also run GMRES on all problems at once")
     ap.add_argument("--m2l-schedule", type=int, default=0)
+    ap.add_argument("--mq-level", type=int, default=-1,
+                    help="with --workload c2mq: level of the near field's uniform tree (-1: the plan's default)")
     ap.add_argument("--mq-kernel", default="multiquadric",
                     choices=["multiquadric", "inverse_multiquadric", "thin_plate", "r5"],
                     help="with --workload c2mq: the kernel of the exact sum")

@@ -80,7 +80,10 @@ typedef struct rbf_opts {
                             XCD (default), 2 = leaf-major over the whole grid */
     int    exact;        /* multiquadric and inverse multiquadric: 1 = exact sum (one leaf, the
                             tiled direct kernel) instead of the banded far field */
-    int    reserved[6];
+    int    band_transfer;/* banded far field: the coarsest bands take their expansions from the
+                            source band by interpolation (section 4.1): 0 = when it saves work
+                            (n >= 64 transfer cells), 1 = always, -1 = never */
+    int    reserved[5];
 } rbf_opts;
 
 typedef struct rbf_plan rbf_plan;
@@ -228,7 +231,13 @@ typedef struct rbf_band_info {
     double  width_lo, width_hi; /* Gaussian widths of the band (top: width_hi = window width) */
     double  tol;              /* tolerance relative to the band's largest value */
     double  band, period, reach, rfar, scale;
-    int     reserved[4];
+    int     transfer;         /* 1: the band's expansions come from the source band's cells by
+                                 Lagrange interpolation, and go back to them by the transposed
+                                 map (section 4.1); its own aggregation and disaggregation do
+                                 not run.  The source band is the band whose coarse level is
+                                 the transfer level with a stencil over the whole grid */
+    int     transfer_order;   /* points of the Lagrange stencil per axis (0 without transfer) */
+    int     reserved[2];
 } rbf_band_info;
 int rbf_fmm_band_info(const rbf_plan *plan, int j, rbf_band_info *info);
 

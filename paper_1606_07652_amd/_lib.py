@@ -22,7 +22,7 @@ class RbfOpts(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int), ("max_level", ctypes.c_int), ("min_level", ctypes.c_int),
                 ("coarse_level", ctypes.c_int), ("coarse_radius", ctypes.c_int), ("nodes", ctypes.c_int),
                 ("band", ctypes.c_double), ("m2l_schedule", ctypes.c_int), ("exact", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("band_transfer", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class RbfSolveOpts(ctypes.Structure):
@@ -55,7 +55,7 @@ class RbfBandInfo(ctypes.Structure):
                 ("nchunks", ctypes.c_int), ("width_lo", ctypes.c_double), ("width_hi", ctypes.c_double),
                 ("tol", ctypes.c_double), ("band", ctypes.c_double), ("period", ctypes.c_double),
                 ("reach", ctypes.c_double), ("rfar", ctypes.c_double), ("scale", ctypes.c_double),
-                ("reserved", ctypes.c_int * 4)]
+                ("transfer", ctypes.c_int), ("transfer_order", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class RbfBatchInfo(ctypes.Structure):

@@ -53,12 +53,10 @@ double band_limit_t(double tol) {
 
 namespace {
 
-// Multiquadric, inverse multiquadric, thin-plate spline and r^5: this library has no band-limited
-// far field for them (a kernel that grows or decays like a power of r cannot be pruned, and one
-// frequency grid for all levels would have to resolve the finest near-zone width over the whole
-// domain).  Every
-// pair is a near pair of a single leaf: the product is the exact sum, evaluated by the tiled
-// direct kernel.
+// Exact-sum plans: the thin-plate spline and r^5 (no far field: their transforms are singular
+// at the origin), the multiquadric kernels with opts.exact or outside the dimensions of their
+// banded far field, and the base of the Wendland plan below.  Every pair is a near pair of a
+// single leaf: the product is the exact sum, evaluated by the tiled direct kernel.
 void multiquadric_params(rbf_plan *p) {
     p->sigma = 1.0;
     p->rcut = p->rfar = p->ext;
@@ -242,6 +240,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
             rc = RBF_EUNSUPPORTED;
         }
     }
+    p->band_xfer = opts ? opts->band_transfer : 0;
     if (rc == RBF_OK && banded_kernel(kernel, d) && !(opts && opts->exact)) rc = plan_bands(p);
     const int64_t fboxes = p->far ? 1 : 0;   // expansions are allocated only with a far field
     if (rc == RBF_OK) {
@@ -511,6 +510,8 @@ int rbf_fmm_band_info(const rbf_plan *p, int j, rbf_band_info *info) {
     info->reach = b.reach;
     info->rfar = b.rfar;
     info->scale = b.scale;
+    info->transfer = b.xfer;
+    info->transfer_order = b.xk;
     return RBF_OK;
 }
 

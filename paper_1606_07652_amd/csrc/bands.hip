@@ -25,6 +25,13 @@
 // function the quadrature kernel reproduces.
 // The sum of the pieces is the kernel exactly; each piece is approximated to a tolerance
 // that splits the requested relative error over the pieces by their size.
+// Interpolating transfers (section 4.1): the coarsest bands (the whole domain as one cell)
+// would each aggregate and disaggregate every point on their own grid.  Instead the first of
+// them (the source) aggregates over the cells of a transfer level, and the others take their
+// expansions from its cell expansions by K-point Lagrange interpolation in the frequency
+// variable and return their local expansions by the transposed map (xfer.hip); K per band is
+// the smallest whose interpolation error, evaluated here on the host over the cells' extent,
+// is below the band's tolerance / (20 d).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -296,8 +303,12 @@ bool choose_grid(const rbf_plan *p, Band &b, double margin) {
         if (mn == 0) continue;
         int64_t P = mn / 2;
         for (int k = 0; k < d - 1; ++k) P *= mn;
+        // per point: aggregation and disaggregation; per cell: upward pass and translation,
+        // the stencil passes reading each cell once per axis on grids of at most 16 cells a
+        // side and 2 r + 1 times on larger ones
         const double cells = std::ldexp(1.0, d * l);
-        const double cost = (double)P * ((double)p->n + 8.0 * cells);
+        const double reads = (l >= 1 && (1 << l) > 16) ? (double)d * (2 * r + 1) : (double)d;
+        const double cost = (double)P * ((double)p->n + (8.0 + reads) * cells);
         if (cost < best) {
             best = cost;
             b.lc = l;
@@ -307,6 +318,218 @@ bool choose_grid(const rbf_plan *p, Band &b, double margin) {
         }
     }
     return best < INFINITY;
+}
+
+// Lagrange stencil of node t on the grid xs (spacing dx, n nodes): K consecutive nodes around
+// t, clamped to the grid, and their weights
+void lagrange_stencil(double x0, double dx, int n, int K, double t, int *first, double *w) {
+    int j = (int)std::floor((t - x0) / dx) - K / 2 + 1;
+    j = std::max(0, std::min(n - K, j));
+    *first = j;
+    for (int k = 0; k < K; ++k) {
+        double v = 1.0;
+        const double xk = x0 + (j + k) * dx;
+        for (int l = 0; l < K; ++l)
+            if (l != k) v *= (t - (x0 + (j + l) * dx)) / (xk - (x0 + (j + l) * dx));
+        w[k] = v;
+    }
+}
+
+// largest |sum_k w_k e^{i xi_k y} - e^{i eta y}| over the target nodes eta and |y| <= a
+double transfer_error(const Band &S, const Band &Tb, double a, int K) {
+    const double dxs = 2.0 * S.sigma / (S.mn - 1), dxt = 2.0 * Tb.sigma / (Tb.mn - 1);
+    double worst = 0.0, w[32];
+    for (int i = 0; i < Tb.mn; ++i) {
+        const double eta = -Tb.sigma + i * dxt;
+        int j0;
+        lagrange_stencil(-S.sigma, dxs, S.mn, K, eta, &j0, w);
+        for (int q = 0; q <= 128; ++q) {
+            const double y = a * (2.0 * q / 128.0 - 1.0);
+            double re = -std::cos(eta * y), im = -std::sin(eta * y);
+            for (int k = 0; k < K; ++k) {
+                const double xi = -S.sigma + (j0 + k) * dxs;
+                re += w[k] * std::cos(xi * y);
+                im += w[k] * std::sin(xi * y);
+            }
+            worst = std::max(worst, std::hypot(re, im));
+        }
+    }
+    return worst;
+}
+
+// Choose the source band and the transferred bands (flags, stencil lengths; the source moves
+// to the transfer level with a stencil over the whole grid, which is its level-0 far field).
+// The transfer level trades cells for stencil length: a level finer by one has 2^d times the
+// cells but half their width, so shorter stencils reach the same error.  Each level from 1 to
+// min(l_n, 3) is costed as cells x sum over the moved bands of K x (the largest per-cell
+// tensor of the band's passes), bands that no stencil of at most 16 points serves staying on
+// their own, and the cheapest level is taken.
+void plan_transfers(rbf_plan *p, std::vector<Band> &bands) {
+    p->xfer_src = -1;
+    if (p->band_xfer < 0) return;
+    const int d = p->d;
+    int src = -1;
+    for (int j = 0; j < (int)bands.size(); ++j)
+        if (bands[j].lc == 0 && !bands[j].top) { src = j; break; }
+    if (src < 0) return;
+    Band &S = bands[src];
+    const int nb = (int)bands.size();
+    int best_l = 0;
+    double best_cost = INFINITY;
+    std::vector<int> best_k(nb, 0);
+    for (int li = 1; li <= std::min(p->lc, 3); ++li) {
+        const int64_t ncell = (int64_t)1 << (d * li);
+        if (p->band_xfer == 0 && p->n < 64 * ncell) break;
+        const double a = 0.5 * p->ext / std::ldexp(1.0, li) * (1.0 + 1e-6);
+        std::vector<int> ks(nb, 0);
+        double cost = 0.0, saved = 0.0;
+        for (int j = src + 1; j < nb; ++j) {
+            const Band &b = bands[j];
+            if (b.lc != 0 || b.sigma > S.sigma) continue;
+            for (int K = 4; K <= std::min(16, S.mn); K += 2)
+                if (transfer_error(S, b, a, K) <= b.tau / (20.0 * d)) {
+                    ks[j] = K;
+                    double big = b.mn / 2;
+                    for (int k = 0; k < d - 1; ++k) big *= std::max(S.mn, b.mn);
+                    cost += (double)ncell * K * big * 2.0 * d;                  // up and down passes
+                    saved += (double)p->n * (b.mn / 2) * std::pow((double)b.mn, d - 1) * 2.0;   // P2M + L2P
+                    break;
+                }
+        }
+        if (saved > 0 && (p->band_xfer == 1 || cost < saved) && cost < best_cost) {
+            best_cost = cost;
+            best_l = li;
+            best_k = ks;
+        }
+    }
+    if (best_l == 0) return;
+    for (int j = 0; j < nb; ++j)
+        if (best_k[j]) {
+            bands[j].xfer = 1;
+            bands[j].xk = best_k[j];
+        }
+    p->xfer_src = src;
+    p->xfer_level = best_l;
+    p->xfer_ncell = 1 << (d * best_l);
+    S.lc = best_l;
+    S.r = (1 << best_l) - 1;   // every cell: the whole domain, as at level 0
+}
+
+// CSR tables of one 1-D map (outputs [nout], entries (input, weight))
+struct Csr {
+    std::vector<int> ptr, idx;
+    std::vector<double> w;
+};
+
+int upload_csr(Arena &ar, const Csr &c, int **ptr, int **idx, double **w) {
+    RBF_TRY(upload(ar, (void **)ptr, c.ptr.data(), sizeof(int) * c.ptr.size()));
+    RBF_TRY(upload(ar, (void **)idx, c.idx.data(), sizeof(int) * std::max<size_t>(c.idx.size(), 1)));
+    RBF_TRY(upload(ar, (void **)w, c.w.data(), sizeof(double) * std::max<size_t>(c.w.size(), 1)));
+    return RBF_OK;
+}
+
+// per-axis phase tables e^{i xi_m c_k} at the centres of the dense transfer cells (Morton order)
+std::vector<double2> cell_phases(const rbf_plan *p, const Band &b) {
+    const int d = p->d, li = p->xfer_level, nc = p->xfer_ncell;
+    const double w = p->ext / std::ldexp(1.0, li), dxi = 2.0 * b.sigma / (b.mn - 1);
+    std::vector<double2> E((size_t)nc * d * b.mn);
+    for (int c = 0; c < nc; ++c)
+        for (int k = 0; k < d; ++k) {
+            int ik = 0;
+            for (int bit = 0; bit < li; ++bit) ik |= ((c >> (bit * d + k)) & 1) << bit;
+            const double ck = p->lo[k] + (ik + 0.5) * w;
+            for (int m = 0; m < b.mn; ++m) {
+                const double ph = (-b.sigma + m * dxi) * ck;
+                E[((size_t)c * d + k) * b.mn + m] = double2{std::cos(ph), std::sin(ph)};
+            }
+        }
+    return E;
+}
+
+// the tables of every transferred band, the source's cell phases and unit map, and buffers
+int build_transfers(rbf_plan *p, const std::vector<int> &src_ucell, size_t csz) {
+    if (p->xfer_src < 0) return RBF_OK;
+    Arena &ar = p->arena;
+    const int d = p->d, nc = p->xfer_ncell;
+    const Band &S = p->bands[p->xfer_src];
+    const double dxs = 2.0 * S.sigma / (S.mn - 1);
+    int64_t rs = 1;
+    for (int k = 0; k < d - 1; ++k) rs *= S.mn;
+    int64_t xmax = rs * S.H, lmax = 0;
+    const double a = 0.5 * p->ext / std::ldexp(1.0, p->xfer_level) * (1.0 + 1e-6);
+    for (int j = 0; j < (int)p->bands.size(); ++j) {
+        Band &b = p->bands[j];
+        if (!b.xfer) continue;
+        Xfer x;
+        x.band = j;
+        x.K = b.xk;
+        x.err = transfer_error(S, b, a, b.xk);
+        const int K = b.xk, mnt = b.mn, Ht = b.H;
+        const double dxt = 2.0 * b.sigma / (mnt - 1);
+        // stencils of every target node (full grid)
+        std::vector<int> first(mnt);
+        std::vector<double> wts((size_t)mnt * K);
+        for (int i = 0; i < mnt; ++i)
+            lagrange_stencil(-S.sigma, dxs, S.mn, K, -b.sigma + i * dxt, &first[i], &wts[(size_t)i * K]);
+        Csr up, upl, dn, dnl;
+        up.ptr.push_back(0);
+        for (int i = 0; i < mnt; ++i) {
+            for (int k = 0; k < K; ++k) {
+                up.idx.push_back(first[i] + k);
+                up.w.push_back(wts[(size_t)i * K + k]);
+            }
+            up.ptr.push_back((int)up.idx.size());
+        }
+        upl.ptr.push_back(0);
+        for (int h = 0; h < Ht; ++h) {
+            const int i = Ht + h;
+            for (int k = 0; k < K; ++k) {
+                upl.idx.push_back(first[i] + k);
+                upl.w.push_back(wts[(size_t)i * K + k]);
+            }
+            upl.ptr.push_back((int)upl.idx.size());
+        }
+        // transposes: source node j collects (target node i, weight of j in i's stencil)
+        for (Csr *t : {&dn, &dnl}) t->ptr.push_back(0);
+        for (int j2 = 0; j2 < S.mn; ++j2) {
+            for (int i = 0; i < mnt; ++i)
+                if (j2 >= first[i] && j2 < first[i] + K) {
+                    dn.idx.push_back(i);
+                    dn.w.push_back(wts[(size_t)i * K + (j2 - first[i])]);
+                }
+            dn.ptr.push_back((int)dn.idx.size());
+        }
+        for (int h = 0; h < S.H; ++h) {
+            const int j2 = S.H + h;
+            for (int i = 0; i < mnt; ++i)
+                if (j2 >= first[i] && j2 < first[i] + K) {
+                    dnl.idx.push_back(i);
+                    dnl.w.push_back(wts[(size_t)i * K + (j2 - first[i])]);
+                }
+            dnl.ptr.push_back((int)dnl.idx.size());
+        }
+        RBF_TRY(upload_csr(ar, up, &x.up_ptr, &x.up_idx, &x.up_w));
+        RBF_TRY(upload_csr(ar, upl, &x.upl_ptr, &x.upl_idx, &x.upl_w));
+        RBF_TRY(upload_csr(ar, dn, &x.dn_ptr, &x.dn_idx, &x.dn_w));
+        RBF_TRY(upload_csr(ar, dnl, &x.dnl_ptr, &x.dnl_idx, &x.dnl_w));
+        const std::vector<double2> Et = cell_phases(p, b);
+        RBF_TRY(upload(ar, (void **)&x.phase_t, Et.data(), sizeof(double2) * Et.size()));
+        p->xfers.push_back(x);
+        int64_t big = Ht;
+        for (int k = 0; k < d - 1; ++k) big *= std::max(S.mn, mnt);
+        xmax = std::max(xmax, big);
+        lmax = std::max(lmax, b.P);
+    }
+    const std::vector<double2> Es = cell_phases(p, S);
+    RBF_TRY(upload(ar, (void **)&p->xfer_phase_s, Es.data(), sizeof(double2) * Es.size()));
+    std::vector<int> cu(nc, -1);
+    for (int u = 0; u < (int)src_ucell.size(); ++u) cu[src_ucell[u]] = u;
+    RBF_TRY(upload(ar, (void **)&p->xfer_cell_unit, cu.data(), sizeof(int) * cu.size()));
+    RBF_TRY(ar.alloc(&p->xfer_keep, csz * (size_t)nc * S.P));
+    RBF_TRY(ar.alloc(&p->xfer_x1, csz * (size_t)nc * xmax));
+    RBF_TRY(ar.alloc(&p->xfer_x2, csz * (size_t)nc * xmax));
+    RBF_TRY(ar.alloc(&p->xfer_l, csz * (size_t)lmax));
+    return RBF_OK;
 }
 
 }  // namespace
@@ -387,6 +610,7 @@ int plan_bands(rbf_plan *p) {
         b.rfar = ext;
         bands.push_back(b);
     }
+    plan_transfers(p, bands);
     // units, chunks and tasks per band from the uniform leaves (all at level p->lc)
     const int nl = p->nleaves;
     std::vector<int> lb(nl + 1);
@@ -395,12 +619,19 @@ int plan_bands(rbf_plan *p) {
     RBF_HIP(hipMemcpy(pre.data(), p->leaf_prefix, sizeof(uint64_t) * nl, hipMemcpyDeviceToHost));
     Arena &ar = p->arena;
     int64_t maxW = 0, maxLx = 0, maxC = 0, maxHP = 0;
-    for (Band &b : bands) {
+    std::vector<int> src_ucell;
+    for (int jb = 0; jb < (int)bands.size(); ++jb) {
+        Band &b = bands[jb];
         b.H = b.mn / 2;
         b.HP = b.H;
         b.R = 1;
         for (int k = 0; k < d - 1; ++k) b.R *= b.mn;
         b.P = b.R * b.H;
+        if (b.xfer) {   // no units of its own: its expansions come from the source band
+            const std::vector<double> wt = band_table(p, b);
+            RBF_TRY(upload(ar, (void **)&b.wtab, wt.data(), sizeof(double) * wt.size()));
+            continue;
+        }
         b.ncells = (int64_t)1 << (d * b.lc);
         const int sh = d * (p->lc - b.lc);
         std::vector<int> ub, ucell, cb, ccell, cellb(b.ncells + 1, 0);
@@ -425,6 +656,7 @@ int plan_bands(rbf_plan *p) {
         ub.push_back(lb[nl]);
         b.nunits = (int)ucell.size();
         b.nchunks = (int)cb.size();
+        if (jb == p->xfer_src) src_ucell = ucell;
         cb.push_back(lb[nl]);
         b.ntasks = (int)(task.size() / 2);
         // chunk range of every dense cell (chunks are in cell order)
@@ -463,6 +695,7 @@ int plan_bands(rbf_plan *p) {
     RBF_TRY(ar.alloc(&p->bTmp, csz * maxC));
     RBF_TRY(ar.alloc(&p->bdl, csz * maxHP * p->n));
     p->bands = std::move(bands);
+    RBF_TRY(build_transfers(p, src_ucell, csz));
     return RBF_OK;
 }
 

@@ -22,6 +22,7 @@
 // binary search over the per-problem block counts.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 
 #include "fmm_desc.h"
 #include "internal.h"
@@ -263,7 +264,14 @@ template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && size
 template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
 // The residual kernel of a banded plan reads its polynomial pieces from tab.
 template <int KER> constexpr bool kRes = KER == kResTab;
-template <class T, int KER> constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab : kRes<KER> ? kResCoefs + 4 : kExpTab;
+// residual pieces in LDS: kResStride entries per piece (the coefficients, then padding, so that
+// a piece starts on a 32-byte boundary), then 4 parameters; FP32 products hold them as floats
+constexpr int kResStride = 8;
+constexpr int kResLds = kResIntervals * kResStride + 4;
+template <class T, int KER>
+constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab
+                        : kRes<KER>     ? (sizeof(T) == 8 ? kResLds : (kResLds + 1) / 2)
+                                        : kExpTab;
 // fills the LDS table of the kernel (stride: the workgroup size); a barrier must follow
 template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab, int stride) {
     if constexpr (kTabExp<T, KER>) {
@@ -278,19 +286,33 @@ template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab
 
 // Residual of the scale split of the multiquadric kernels (every Gaussian width below s0) at
 // squared distance r2: with b = sqrt(r2 + c^2), piece i = floor((b - c) inv) of the table, a
-// polynomial of degree kResDegree in v = (b - c) inv - i (tab[kResCoefs] = inv,
-// tab[kResCoefs + 1] = qmax, tab[kResCoefs + 2] = c; zero from r2 = qmax on).
-template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab) {
-    const T b = KFun<T>::mq(r2, c2);
-    const T s = (b - (T)tab[kResCoefs + 2]) * (T)tab[kResCoefs];
+// polynomial of degree kResDegree in v = (b - c) inv - i (after the pieces: inv, qmax, c and
+// the flag of the division by b; zero from r2 = qmax on).
+template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab_raw) {
+    const T *tab = reinterpret_cast<const T *>(tab_raw);   // entries in the product's precision
+    constexpr int kP = kResIntervals * kResStride;          // parameters after the pieces
+    // 1/b from the hardware reciprocal square root (FP64: two Newton steps, each squaring the
+    // relative error), b = q / b; the inverse multiquadric's division becomes a product
+    const T q = r2 + c2;
+    T rb;
+    if constexpr (sizeof(T) == 8) {
+        rb = __builtin_amdgcn_rsq(q);
+        const T h = T(0.5) * q;
+        rb = rb * fma(-h * rb, rb, T(1.5));
+        rb = rb * fma(-h * rb, rb, T(1.5));
+    } else {
+        rb = __builtin_amdgcn_rsqf(q);
+    }
+    const T b = q * rb;
+    const T s = (b - tab[kP + 2]) * tab[kP];
     const int i = max(0, min((int)s, kResIntervals - 1));
     const T v = s - (T)i;
-    const double *c = tab + i * (kResDegree + 1);
-    T y = (T)c[kResDegree];
+    const T *c = tab + i * kResStride;
+    T y = c[kResDegree];
 #pragma unroll
-    for (int k = kResDegree - 1; k >= 0; --k) y = fma(y, v, (T)c[k]);
-    if (tab[kResCoefs + 3] != 0.0) y = y / b;   // inverse multiquadric: the table holds b * residual
-    return r2 < (T)tab[kResCoefs + 1] ? y : T(0);
+    for (int k = kResDegree - 1; k >= 0; --k) y = fma(y, v, c[k]);
+    if (tab[kP + 3] != T(0)) y = y * rb;   // inverse multiquadric: the table holds b * residual
+    return r2 < tab[kP + 1] ? y : T(0);
 }
 
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
@@ -451,19 +473,25 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = d.xs[k * n + (act ? ti : t0)];
     const int r0 = sp[a], r1 = sp[a + 1];
-    __shared__ double tab[kTabLen<T, KER>];   // FP64 Gaussian: 2^(j/256); FP64 thin-plate: log tables
+    // FP64 Gaussian: 2^(j/256); FP64 thin-plate: log tables; banded plans: residual pieces
+    __shared__ __align__(32) double tab[kTabLen<T, KER>];
     T coef = d.coef;
     if constexpr (kTabExp<T, KER> || kTabLog<T, KER>) {
         fill_tab<T, KER>(tab, kWave);
         __syncthreads();
     }
     if constexpr (kRes<KER>) {
-        for (int j = threadIdx.x; j < kResCoefs; j += kWave) tab[j] = d.res_tab[j];
+        T *rt = reinterpret_cast<T *>(tab);
+        constexpr int kP = kResIntervals * kResStride;
+        for (int j = threadIdx.x; j < kP; j += kWave) {
+            const int piece = j / kResStride, k = j - piece * kResStride;
+            rt[j] = k <= kResDegree ? (T)d.res_tab[piece * (kResDegree + 1) + k] : T(0);
+        }
         if (threadIdx.x == 0) {
-            tab[kResCoefs] = d.res_inv;
-            tab[kResCoefs + 1] = d.res_cut2;
-            tab[kResCoefs + 2] = sqrt((double)d.coef);   // c (coef = c^2)
-            tab[kResCoefs + 3] = d.res_div_b;
+            rt[kP] = (T)d.res_inv;
+            rt[kP + 1] = (T)d.res_cut2;
+            rt[kP + 2] = (T)sqrt((double)d.coef);   // c (coef = c^2)
+            rt[kP + 3] = (T)d.res_div_b;
         }
         __syncthreads();
     }
@@ -1480,8 +1508,14 @@ struct BandTimer {
     hipError_t end() { return p ? hipEventRecord(p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2 + 1], st) : hipSuccess; }
 };
 
+// Hooks of the source band of the interpolating transfers: after its upward pass (its cell
+// expansions are complete) and after its leaf translation (before its disaggregation).
+struct BandHooks {
+    std::function<int()> after_m2m, after_leaf;
+};
+
 template <class T, int D, int HMAX>
-int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
+int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt, const BandHooks *hk) {
     int64_t nb[PH_COUNT];
     for (int k = 0; k < PH_COUNT; ++k) nb[k] = phase_blocks<T>(w.one, k);
     const size_t sh = p2m_shmem<T>(w.one, D);
@@ -1492,6 +1526,7 @@ int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
     RBF_HIP(bt.end());
     RBF_HIP(bt.begin(3, s));
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2M, nb[PH_M2M], s, 0, 0, kernel)));
+    if (hk) RBF_TRY(hk->after_m2m());
     RBF_HIP(bt.end());
     RBF_HIP(bt.begin(4, s));
     for (int ax = 0; ax < D; ++ax)
@@ -1499,6 +1534,7 @@ int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
     RBF_HIP(bt.end());
     RBF_HIP(bt.begin(5, s));
     RBF_TRY((launch_phase<T, D, HMAX>(w, PH_M2L_LEAF, nb[PH_M2L_LEAF], s, 0, 0, kernel)));
+    if (hk) RBF_TRY(hk->after_leaf());
     RBF_HIP(bt.end());
     if (join) RBF_HIP(hipStreamWaitEvent(s, join, 0));   // u_s holds the near field from here on
     RBF_HIP(bt.begin(6, s));
@@ -1508,19 +1544,19 @@ int run_band(const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
 }
 
 template <class T, int D>
-int run_band_hp(int HP, const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt) {
+int run_band_hp(int HP, const Work<T> &w, hipStream_t s, hipEvent_t join, BandTimer &bt, const BandHooks *hk) {
     switch (HP) {
-        case 4: return run_band<T, D, 4>(w, s, join, bt);
-        case 6: return run_band<T, D, 6>(w, s, join, bt);
-        case 8: return run_band<T, D, 8>(w, s, join, bt);
-        case 10: return run_band<T, D, 10>(w, s, join, bt);
-        case 12: return run_band<T, D, 12>(w, s, join, bt);
-        case 14: return run_band<T, D, 14>(w, s, join, bt);
-        case 16: return run_band<T, D, 16>(w, s, join, bt);
-        case 20: return run_band<T, D, 20>(w, s, join, bt);
-        case 24: return run_band<T, D, 24>(w, s, join, bt);
-        case 28: return run_band<T, D, 28>(w, s, join, bt);
-        case 32: return run_band<T, D, 32>(w, s, join, bt);
+        case 4: return run_band<T, D, 4>(w, s, join, bt, hk);
+        case 6: return run_band<T, D, 6>(w, s, join, bt, hk);
+        case 8: return run_band<T, D, 8>(w, s, join, bt, hk);
+        case 10: return run_band<T, D, 10>(w, s, join, bt, hk);
+        case 12: return run_band<T, D, 12>(w, s, join, bt, hk);
+        case 14: return run_band<T, D, 14>(w, s, join, bt, hk);
+        case 16: return run_band<T, D, 16>(w, s, join, bt, hk);
+        case 20: return run_band<T, D, 20>(w, s, join, bt, hk);
+        case 24: return run_band<T, D, 24>(w, s, join, bt, hk);
+        case 28: return run_band<T, D, 28>(w, s, join, bt, hk);
+        case 32: return run_band<T, D, 32>(w, s, join, bt, hk);
     }
     set_error("padded half grid %d not compiled for banded products", HP);
     return RBF_EUNSUPPORTED;
@@ -1556,17 +1592,39 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
     RBF_HIP(pt.end());
     if (pt.side) RBF_HIP(hipEventRecord(pt.join, sn));
     const int nbands = (int)p->bands.size();
+    int last = -1;   // the last band with a run of its own writes u through the permutation
+    for (int j = 0; j < nbands; ++j)
+        if (!p->bands[j].xfer) last = j;
+    BandHooks hooks;
+    if (p->xfer_src >= 0) {
+        const Band &S = p->bands[p->xfer_src];
+        const size_t csz = sizeof(typename cplx<T>::type);
+        hooks.after_m2m = [p, &S, s, csz]() -> int {
+            // the source's cell expansions, before the stencil passes reuse the buffer
+            RBF_HIP(hipMemcpyAsync(p->xfer_keep, p->bWc, csz * (size_t)S.ncells * S.P, hipMemcpyDeviceToDevice, s));
+            return RBF_OK;
+        };
+        hooks.after_leaf = [p, &S, s]() -> int {
+            for (const Xfer &x : p->xfers)
+                RBF_TRY(xfer_band<T>(p, x, S, p->bands[x.band], p->xfer_keep, p->bLx, s));
+            return RBF_OK;
+        };
+    }
+    bool first = true;
     for (int j = 0; j < nbands; ++j) {
+        if (p->bands[j].xfer) continue;
         Work<T> wb{};
-        fill_band_desc<T>(p, p->bands[j], j + 1 < nbands, &wb.one);
+        fill_band_desc<T>(p, p->bands[j], j != last, &wb.one);
         wb.lam = lam;
         wb.u = u;
         bt.j = j;
-        RBF_TRY((run_band_hp<T, D>(p->bands[j].HP, wb, s, (j == 0 && pt.side) ? pt.join : nullptr, bt)));
+        RBF_TRY((run_band_hp<T, D>(p->bands[j].HP, wb, s, (first && pt.side) ? pt.join : nullptr, bt,
+                                   j == p->xfer_src ? &hooks : nullptr)));
+        first = false;
     }
     if (p->profiling) {
         // phases 0 and 1 from the plan's events, 2..6 summed over the bands
-        RBF_HIP(hipEventSynchronize(p->band_ev.back()));
+        RBF_HIP(hipStreamSynchronize(s));   // every recorded event (transferred bands record none)
         RBF_HIP(hipEventSynchronize(p->ev[3]));
         for (int k = 0; k < 2; ++k) {
             float ms = 0.f;
@@ -1574,7 +1632,7 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
             p->phase_ms[k] += ms;
         }
         for (int j = 0; j < nbands; ++j)
-            for (int k = 2; k < RBF_NPHASES; ++k) {
+            for (int k = 2; k < RBF_NPHASES && !p->bands[j].xfer; ++k) {
                 float ms = 0.f;
                 RBF_HIP(hipEventElapsedTime(&ms, p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2],
                                             p->band_ev[(size_t)(j * RBF_NPHASES + k) * 2 + 1]));

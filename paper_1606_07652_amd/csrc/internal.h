@@ -87,8 +87,25 @@ struct Band {
     int *uni_ptr = nullptr;      // empty near lists [ngroups + 1]
     int *uni_pad = nullptr;      // zero entries the leaf translation reads ahead [16]
     double *wtab = nullptr;      // [P]
+    int xfer = 0;                // 1: expansions transferred from the source band (no aggregation,
+                                 //    translation or disaggregation of its own)
+    int xk = 0;                  // Lagrange stencil length of the transfer
 };
 constexpr int kBandChunk = 256;
+
+// Interpolating transfer of one target band's expansions from and to the source band's cell
+// expansions (xfer.hip): CSR maps of the 1-D Lagrange stencils (output index -> input index,
+// weight), device arrays, and the target grid's phases at the transfer cells.
+struct Xfer {
+    int band = -1;                                                  // the target band
+    int K = 0;
+    double err = 0;                                                 // predicted 1-D error
+    int *up_ptr = nullptr, *up_idx = nullptr;   double *up_w = nullptr;    // S full -> T full [mnt]
+    int *upl_ptr = nullptr, *upl_idx = nullptr; double *upl_w = nullptr;   // S full -> T half [Ht]
+    int *dn_ptr = nullptr, *dn_idx = nullptr;   double *dn_w = nullptr;    // T full -> S full [mns]
+    int *dnl_ptr = nullptr, *dnl_idx = nullptr; double *dnl_w = nullptr;   // T full -> S half [Hs]
+    double2 *phase_t = nullptr;                                     // [cell][d][mnt] e^{i eta_m c_k}
+};
 
 }  // namespace rbf
 
@@ -168,6 +185,14 @@ struct rbf_plan {
     double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
     void *bW = nullptr, *bLx = nullptr, *bWc = nullptr, *bLc = nullptr, *bTmp = nullptr, *bdl = nullptr;
     std::vector<hipEvent_t> band_ev; // profiling: event pairs per band and phase
+    // interpolating transfers (the coarsest bands take their expansions from the source band's
+    // cells at the transfer level, section 4.1): option, source band, cells and buffers
+    int band_xfer = 0;               // opts.band_transfer: 0 auto, 1 on, -1 off
+    int xfer_src = -1, xfer_level = 0, xfer_ncell = 0;
+    std::vector<rbf::Xfer> xfers;
+    double2 *xfer_phase_s = nullptr; // [cell][d][mns] e^{i xi_m c_k} of the source grid
+    int *xfer_cell_unit = nullptr;   // [cell] the source band's unit of a dense cell, or -1
+    void *xfer_keep = nullptr, *xfer_x1 = nullptr, *xfer_x2 = nullptr, *xfer_l = nullptr;
 
     // the near field of a product runs on a second stream of default priority, forked after the
     // permutation and joined before the disaggregation (it reads nothing the far-field chain
@@ -220,6 +245,9 @@ int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u);
 int reject_eval_plan(const rbf_plan *p, const char *fn);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);
 int plan_bands(rbf_plan *p);                                         // bands.hip
+template <class T>
+int xfer_band(const rbf_plan *p, const Xfer &x, const Band &S, const Band &Tb, const void *wc_keep, void *lx_s,
+              hipStream_t s);                                          // xfer.hip
 bool banded_kernel(int kernel, int d);                               // bands.hip
 int pc_ready(rbf_plan *p, int kind);                                 // pc.hip
 int pc_apply(rbf_plan *p, int kind, const double *v, double *z);     // pc.hip

@@ -36,15 +36,15 @@ def _ptr(t: torch.Tensor) -> int:
 
 
 def _opts(n_max=0, max_level=0, min_level=0, coarse_level=-1, coarse_radius=-1, nodes=0, band=0.0,
-          m2l_schedule=0, exact=0):
+          m2l_schedule=0, exact=0, band_transfer=0):
     return L.RbfOpts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule,
-                     1 if exact else 0)
+                     1 if exact else 0, int(band_transfer))
 
 
 def _opts_dict(o: "L.RbfOpts") -> dict:
     return {"n_max": o.n_max, "max_level": o.max_level, "min_level": o.min_level, "coarse_level": o.coarse_level,
             "coarse_radius": o.coarse_radius, "nodes": o.nodes, "band": o.band, "m2l_schedule": o.m2l_schedule,
-            "exact": o.exact}
+            "exact": o.exact, "band_transfer": o.band_transfer}
 
 
 def autotune(points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05, tol: float = 1e-6,
@@ -140,7 +140,8 @@ class FmmPlan:
     def __init__(self, points: torch.Tensor, kernel: str = "gaussian", shape: float = 0.05,
                  tol: float = 1e-6, n_max: int = 0, max_level: int = 0, min_level: int = 0,
                  coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0, band: float = 0.0,
-                 m2l_schedule: int = 0, exact: bool = False, stream: Optional[torch.cuda.Stream] = None):
+                 m2l_schedule: int = 0, exact: bool = False, band_transfer: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         if points.dim() != 2:
             raise ValueError("points must be (n, d)")
@@ -148,7 +149,8 @@ class FmmPlan:
         self.dtype = points.dtype
         self.device = points.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
-        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact,
+                     band_transfer)
         h = ctypes.c_void_p()
         L.check(lib.rbf_fmm_plan(_ptr(points), self.n, self.d, _dtype_code(points), _KERNELS[kernel],
                                  float(shape), float(tol), ctypes.byref(opts),
@@ -281,7 +283,7 @@ class EvalPlan(FmmPlan):
     def __init__(self, sources: torch.Tensor, targets: torch.Tensor, kernel: str = "gaussian",
                  shape: float = 0.05, tol: float = 1e-6, n_max: int = 0, max_level: int = 0,
                  min_level: int = 0, coarse_level: int = -1, coarse_radius: int = -1, nodes: int = 0,
-                 band: float = 0.0, m2l_schedule: int = 0, exact: bool = False,
+                 band: float = 0.0, m2l_schedule: int = 0, exact: bool = False, band_transfer: int = 0,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = L.load()
         if sources.dim() != 2 or targets.dim() != 2 or targets.shape[1] != sources.shape[1]:
@@ -294,7 +296,8 @@ class EvalPlan(FmmPlan):
         self.dtype = sources.dtype
         self.device = sources.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(sources.device)
-        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact)
+        opts = _opts(n_max, max_level, min_level, coarse_level, coarse_radius, nodes, band, m2l_schedule, exact,
+                     band_transfer)
         h = ctypes.c_void_p()
         tp = _ptr(targets) if self.m > 0 else None
         L.check(lib.rbf_fmm_plan_eval(_ptr(sources), self.n_src, tp, self.m, self.d, _dtype_code(sources),

@@ -159,3 +159,40 @@ def test_banded_full_size_sampled_targets():
             assert err <= tol
             p.close()
             torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-6), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("d,n,kernel,lev", [(3, 20000, "multiquadric", 3), (3, 12001, "inverse_multiquadric", 3),
+                                            (2, 6000, "multiquadric", 4)])
+def test_banded_transfers_match_direct_sum(d, n, kernel, lev, dtype, tol):
+    """Interpolating transfers (section 4.1) forced on: the coarsest bands take their expansions
+    from the source band's cells by Lagrange interpolation and return their local expansions by
+    the transposed map.  The plan reports them (stencil lengths 4..16; the source at the
+    transfer level with a stencil over the whole grid); the product meets the tolerance against
+    the direct sum, agrees with the plan without transfers, and repeats bit for bit."""
+    x = mixed_points(n, d, 750 + n % 89)
+    lam = normal_weights(n, 751)
+    X, L = dev(x, dtype), dev(lam, dtype)
+    ref = direct.direct_sum(X.double().cpu().numpy(), L.double().cpu().numpy(), kernel, 0.02)
+    p = banded(x, kernel, 0.02, dtype, tol, coarse_level=lev, band_transfer=1)
+    bands = p.bands()
+    moved = [b for b in bands if b["transfer"]]
+    srcs = [b for b in bands if not b["transfer"] and not b["top"] and b["coarse_level"] >= 1
+            and b["coarse_radius"] == (1 << b["coarse_level"]) - 1]
+    print(f"  transferred {len(moved)} of {len(bands)} bands, orders {[b['transfer_order'] for b in moved]}, "
+          f"nodes {[b['nodes'] for b in moved]}, source level {[b['coarse_level'] for b in srcs]}", flush=True)
+    assert len(moved) >= 2 and len(srcs) == 1
+    assert all(4 <= b["transfer_order"] <= 16 and b["nunits"] == 0 for b in moved)
+    assert bands[-1]["top"] == 1 and bands[-1]["transfer"] == 1
+    u = p.matvec(L).double().cpu().numpy()
+    err = direct.rel_l2(u, ref)
+    print(f"  rel-L2 vs direct sum with transfers = {err:.3e}", flush=True)
+    assert err <= tol
+    assert np.array_equal(u, p.matvec(L).double().cpu().numpy())
+    p.close()
+    q = banded(x, kernel, 0.02, dtype, tol, coarse_level=lev, band_transfer=-1)
+    assert not any(b["transfer"] for b in q.bands())
+    u0 = q.matvec(L).double().cpu().numpy()
+    print(f"  without transfers {direct.rel_l2(u0, ref):.3e}; between the two {direct.rel_l2(u, u0):.3e}", flush=True)
+    assert direct.rel_l2(u, u0) <= tol
+    q.close()

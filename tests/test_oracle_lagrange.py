@@ -51,3 +51,39 @@ def test_table_between_sampled_and_continuous_maxima():
         lo = lagrange.halfwave_error(K, nxi=21)
         hi = lagrange.halfwave_error(K, nxi=10001)
         assert lo - half <= v <= hi + half, (K, lo, v, hi)
+
+
+def test_transfer_of_a_centred_expansion_matches_its_definition():
+    """A cell's expansion W(xi) = sum_j lam_j e^{-i xi.(x_j - c)} (points within half a cell
+    width a of the centre c) known at one grid's nodes, moved to another grid's nodes by
+    K-point stencils per axis: equals the expansion evaluated at the new nodes directly, to
+    sum |lam| times d times the 1-D error of the stencils (largest |sum_k w_k e^{i xi_k y} -
+    e^{i eta y}| over |y| <= a), and that error falls with K.  Grids as the banded far field
+    has them: even node counts on [-sigma, sigma], target band limit below the source's."""
+    rng = np.random.default_rng(4)
+    d, a = 3, 0.0645
+    src = np.linspace(-37.6, 37.6, 24)
+    tgt = np.linspace(-27.0, 27.0, 24)
+    x = rng.uniform(-a, a, (40, d))
+    lam = rng.normal(0, 1, 40)
+
+    def expansion(nodes):
+        g = np.stack(np.meshgrid(*([nodes] * d), indexing="ij"), -1)
+        return np.exp(-1j * (g @ x.T)) @ lam
+
+    def err1(K):
+        y = np.linspace(-a, a, 257)
+        worst = 0.0
+        for t in tgt:
+            j, w = lagrange.stencil(src, t, K)
+            worst = max(worst, np.abs(np.exp(1j * np.outer(y, src[j:j + K])) @ w - np.exp(1j * t * y)).max())
+        return worst
+
+    prev = np.inf
+    for K in (6, 8, 10):
+        got = lagrange.transfer(expansion(src), src, tgt, K)
+        e1 = err1(K)
+        assert e1 < prev
+        prev = e1
+        assert np.abs(got - expansion(tgt)).max() <= d * e1 * np.abs(lam).sum() * 1.01
+    assert prev < 1e-9
