@@ -269,7 +269,11 @@ int rbf_fmm_phase_times(const rbf_plan *plan, double *ms, int64_t *calls);
  * least the pruning radius wide, so that every kept pair is a near pair; and, when the
  * pruning radius is at least half the extent and n <= 2^19, a single leaf holding every
  * point, which is the direct sum), times `reps`
- * products of each with HIP events on `stream`, and writes the fastest configuration to
+ * products of each with HIP events on `stream`; for a Gaussian with a far field it then times
+ * the coarse levels next to the best candidate's (their stencils and so their node counts per
+ * dimension differ) and the other leaf-translation block order (m2l_schedule) with the best
+ * leaf capacity.  Multiquadric kernels: the near-field tree's level around the default (and
+ * the exact sum for n <= 2^17).  It writes the fastest configuration to
  * *best (host) and its time per product to *best_ms (host, may be NULL).  Arguments as in
  * rbf_fmm_plan; base may be NULL.  Synchronous; allocates and frees temporary plans. */
 int rbf_fmm_autotune(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,

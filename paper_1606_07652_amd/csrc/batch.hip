@@ -11,7 +11,9 @@
 // The autotuner plans each candidate configuration (leaf capacity 64..512, a near-only
 // tree whose cells are at least the pruning radius wide, and -- when nothing can be pruned
 // -- a single leaf, i.e. the direct sum), times a few products with HIP events and keeps
-// the fastest.
+// the fastest; for a Gaussian far field it then times the coarse levels next to the rule's
+// with the best leaf capacity (each level has its own stencil reach and so its own node
+// count per dimension) and the other leaf-translation block order.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -146,18 +148,41 @@ int autotune_impl(const void *points, int64_t n, int d, int dtype, int kernel, d
     k_fill_one<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lam, n, dtype);
     double bms = INFINITY;
     int found = 0;
-    for (const rbf_opts &c : cands) {
+    int best_lc = -1, best_far = 0;   // coarse level and far-field flag of the best plan
+    auto try_candidate = [&](const rbf_opts &c) {
         rbf_plan *p = nullptr;
-        if (plan_create(points, n, d, dtype, kernel, shape, tol, &c, s, &p) != RBF_OK) continue;
+        if (plan_create(points, n, d, dtype, kernel, shape, tol, &c, s, &p) != RBF_OK) return;
         double ms = INFINITY;
         int rc = time_plan(p, lam, u, reps, for_batch, &ms);
+        const int lc = p->lc, far = p->far && p->bands.empty();
         rbf_fmm_destroy(p);
-        if (rc != RBF_OK) continue;
+        if (rc != RBF_OK) return;
         if (ms < bms) {
             bms = ms;
             *best = c;
             found = 1;
+            best_lc = lc;
+            best_far = far;
         }
+    };
+    for (const rbf_opts &c : cands) try_candidate(c);
+    // Second stage (Gaussian far field): the quadrature order follows the coarse level through
+    // the stencil's reach, so the levels next to the rule's (their node counts differ) and the
+    // other leaf-translation block order are timed with the best leaf capacity.
+    if (found && best_far && kernel == RBF_GAUSSIAN && best->coarse_level < 0 && best_lc >= 1) {
+        const rbf_opts b0 = *best;
+        std::vector<rbf_opts> more;
+        for (int l : {best_lc - 1, best_lc + 1}) {
+            if (l < 1 || l > 18 / d) continue;
+            rbf_opts c = b0;
+            c.coarse_level = l;
+            c.coarse_radius = -1;
+            more.push_back(c);
+        }
+        rbf_opts c = b0;
+        c.m2l_schedule = b0.m2l_schedule == 2 ? 0 : 2;
+        more.push_back(c);
+        for (const rbf_opts &m : more) try_candidate(m);
     }
     (void)hipFree(lam);
     (void)hipFree(u);
