@@ -461,6 +461,21 @@ int rbf_pc_pairs(rbf_plan *plan, const double *r, const double *e, float *x, flo
  * x + c nblk 64, t + c nblk 64, w + c nblk (device, sized ncaps nblk rows).  Synchronous. */
 int rbf_pc_harvest(rbf_plan *plan, const void *f, double rtol, int max_iters, int precond, const int *caps,
                    int ncaps, float *x, float *t, float *w);
+/* The training of the learned preconditioner in one call: rows from solves of
+ * A_p lambda = f_p for every plan (rbf_pc_harvest, no preconditioner; caps host int[ncaps],
+ * NULL for 0, 1, 2, 5, 10, 20, 50, 100, 200), all rows in plan order and cap order, a network
+ * created from `seed` (rbf_mlp_create), minibatch Adam on the rows (rbf_mlp_train with opts,
+ * on the first plan's stream; info may be NULL), written to out_path as the versioned weight
+ * file (rbf_mlp_save).  plans host array of nplans plans, fs host array of nplans device
+ * right-hand sides (each plan's dtype and length).  Device memory for the rows
+ * (ncaps * ceil(n_p / 64) * 516 bytes per plan) is allocated for the call.  Synchronous. */
+int rbf_pc_train(rbf_plan *const *plans, const void *const *fs, int nplans, double rtol, int max_iters,
+                 const int *caps, int ncaps, uint64_t seed, const rbf_train_opts *opts, const char *out_path,
+                 rbf_train_info *info);
+/* Load a weight file (rbf_mlp_load: RBF_EINVAL for any other layout or version) and attach the
+ * network to the plan for RBF_PC_LEARNED (rbf_pc_set_learned).  *out receives the network;
+ * the caller destroys it (rbf_mlp_destroy) after the plan's last use of it. */
+int rbf_pc_load(rbf_plan *plan, const char *path, rbf_mlp **out);
 
 #ifdef __cplusplus
 }

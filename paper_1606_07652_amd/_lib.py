@@ -134,6 +134,10 @@ SIGNATURES = {
     "rbf_pc_pairs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "rbf_pc_harvest": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P, _P,
                                       _P]),
+    "rbf_pc_train": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, ctypes.c_int,
+                                    ctypes.c_uint64, ctypes.POINTER(RbfTrainOpts), ctypes.c_char_p,
+                                    ctypes.POINTER(RbfTrainInfo)]),
+    "rbf_pc_load": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
 }
 
 _lib = None

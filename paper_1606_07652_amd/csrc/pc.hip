@@ -576,3 +576,61 @@ extern "C" int rbf_pc_harvest(rbf_plan *plan, const void *f, double rtol, int ma
     tmp.release();
     return rc;
 }
+
+extern "C" int rbf_pc_train(rbf_plan *const *plans, const void *const *fs, int nplans, double rtol, int max_iters,
+                            const int *caps, int ncaps, uint64_t seed, const rbf_train_opts *opts,
+                            const char *out_path, rbf_train_info *info) {
+    if (!plans || !fs || nplans <= 0 || !out_path) {
+        set_error("rbf_pc_train: bad arguments");
+        return RBF_EINVAL;
+    }
+    static const int kCaps[] = {0, 1, 2, 5, 10, 20, 50, 100, 200};
+    if (!caps) {
+        caps = kCaps;
+        ncaps = (int)(sizeof(kCaps) / sizeof(kCaps[0]));
+    }
+    if (ncaps <= 0) { set_error("rbf_pc_train: ncaps must be positive"); return RBF_EINVAL; }
+    int64_t rows = 0;
+    for (int q = 0; q < nplans; ++q) {
+        if (!plans[q] || !fs[q]) { set_error("rbf_pc_train: null plan or right-hand side %d", q); return RBF_EINVAL; }
+        rows += (int64_t)ncaps * ((plans[q]->n + BS - 1) / BS);
+    }
+    // every plan's rows, one after the other (plan order, then cap order), in one buffer
+    Arena tmp;
+    float *x = nullptr, *t = nullptr, *w = nullptr;
+    int rc = RBF_OK;
+    if ((rc = tmp.alloc((void **)&x, sizeof(float) * rows * BS)) != RBF_OK ||
+        (rc = tmp.alloc((void **)&t, sizeof(float) * rows * BS)) != RBF_OK ||
+        (rc = tmp.alloc((void **)&w, sizeof(float) * rows)) != RBF_OK) {
+        tmp.release();
+        return rc;
+    }
+    int64_t at = 0;
+    for (int q = 0; q < nplans && rc == RBF_OK; ++q) {
+        rc = rbf_pc_harvest(plans[q], fs[q], rtol, max_iters, RBF_PC_NONE, caps, ncaps, x + at * BS, t + at * BS,
+                            w + at);
+        at += (int64_t)ncaps * ((plans[q]->n + BS - 1) / BS);
+    }
+    rbf_mlp *m = nullptr;
+    if (rc == RBF_OK) rc = rbf_mlp_create(nullptr, seed, &m);
+    if (rc == RBF_OK) rc = rbf_mlp_train(m, x, t, w, rows, opts, plans[0]->stream, info);
+    if (rc == RBF_OK) rc = rbf_mlp_save(m, out_path);
+    if (m) (void)rbf_mlp_destroy(m);
+    tmp.release();
+    return rc;
+}
+
+extern "C" int rbf_pc_load(rbf_plan *plan, const char *path, rbf_mlp **out) {
+    if (!plan || !path || !out) { set_error("rbf_pc_load: null argument"); return RBF_EINVAL; }
+    RBF_TRY(reject_eval_plan(plan, "rbf_pc_load"));
+    RBF_TRY(check_learned_kernel(plan));
+    rbf_mlp *m = nullptr;
+    RBF_TRY(rbf_mlp_load(path, &m));
+    const int rc = rbf_pc_set_learned(plan, m);
+    if (rc != RBF_OK) {
+        (void)rbf_mlp_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return RBF_OK;
+}

@@ -170,3 +170,35 @@ def harvest(plan: FmmPlan, f: torch.Tensor, caps=(0, 1, 2, 5, 10, 20, 50, 100, 2
     L.check(L.load().rbf_pc_harvest(plan._h, _ptr(f), float(rtol), int(max_iters), kind, c.ctypes.data, len(c),
                                     _ptr(x), _ptr(t), _ptr(w)))
     return x, t, w
+
+
+def train_file(plans, fs, path: str, caps=None, rtol: float = 1e-10, max_iters: int = 1000, seed: int = 0,
+               epochs: int = 100, batch: int = 512, lr: float = 1e-3, val_frac: float = 0.1, patience: int = 0,
+               shuffle_seed: int = 0) -> dict:
+    """The whole training in one library call (rbf_pc_train): rows harvested from solves of every
+    plan with its right-hand side, a network from `seed` trained on them, written to `path`."""
+    if len(plans) != len(fs) or not plans:
+        raise ValueError("one right-hand side per plan")
+    for p_, f_ in zip(plans, fs):
+        p_._check_vec(f_)
+    hp = (ctypes.c_void_p * len(plans))(*[p_._h.value for p_ in plans])
+    hf = (ctypes.c_void_p * len(fs))(*[f_.data_ptr() for f_ in fs])
+    c = None if caps is None else np.ascontiguousarray(caps, dtype=np.int32)
+    o = L.RbfTrainOpts(epochs, batch, patience, 0, lr, 0.9, 0.999, 1e-8, val_frac, shuffle_seed)
+    inf = L.RbfTrainInfo()
+    L.check(L.load().rbf_pc_train(hp, hf, len(plans), float(rtol), int(max_iters),
+                                  None if c is None else c.ctypes.data, 0 if c is None else len(c), int(seed),
+                                  ctypes.byref(o), str(path).encode(), ctypes.byref(inf)))
+    k = inf.nhist
+    return {"epochs_run": inf.epochs_run, "best_epoch": inf.best_epoch, "init_val_loss": inf.init_val_loss,
+            "best_val_loss": inf.best_val_loss, "seconds": inf.seconds, "val_loss": list(inf.val_loss[:k])}
+
+
+def load_into(plan: FmmPlan, path: str) -> Mlp:
+    """Load a weight file and attach it to the plan (rbf_pc_load); returns the network, which the
+    plan keeps alive."""
+    h = ctypes.c_void_p()
+    L.check(L.load().rbf_pc_load(plan._h, str(path).encode(), ctypes.byref(h)))
+    m = Mlp(_handle=h)
+    plan._mlp_ref = m
+    return m

@@ -298,3 +298,40 @@ def test_learned_preconditioner_gain(tmp_path):
               flush=True)
     assert res["learned"] <= 0.5 * res["none"]
     assert 0.9 * res["untrained"] <= res["learned"] <= 1.1 * res["untrained"]
+
+
+def test_pc_train_and_load_match_the_step_by_step_pipeline(tmp_path):
+    """rbf_pc_train (harvest on every plan, create, train, save in one call) writes the same
+    weight file as the step-by-step calls on the same problems and settings (training is
+    deterministic), and rbf_pc_load attaches that network to another plan, whose learned
+    solve then converges."""
+    from paper_1606_07652_amd import FmmPlan
+    from paper_1606_07652_amd import pc
+    from workloads import bumps_rhs, jittered_grid
+    caps = (0, 1, 2, 5, 10)
+    plans, fs = [], []
+    for sd in (601, 602):
+        x = jittered_grid(40, 2, sd)
+        plans.append(FmmPlan(dev(x), kernel="gaussian", shape=0.03, tol=1e-8))
+        fs.append(dev(bumps_rhs(x, sd)))
+    a = str(tmp_path / "one_call.bin")
+    info = pc.train_file(plans, fs, a, caps=caps, seed=3, epochs=5, batch=256, val_frac=0.25, shuffle_seed=1)
+    print(f"[pc_train] val loss {info['init_val_loss']:.3f} -> {info['best_val_loss']:.3f}", flush=True)
+    assert info["best_val_loss"] <= info["init_val_loss"]
+    rows = [pc.harvest(p_, f_, caps=caps) for p_, f_ in zip(plans, fs)]
+    X, T, W = (torch.cat([r[k] for r in rows]) for k in range(3))
+    m = pc.Mlp(seed=3)
+    m.train(X, T, W, epochs=5, batch=256, val_frac=0.25, seed=1)
+    b = str(tmp_path / "steps.bin")
+    m.save(b)
+    assert open(a, "rb").read() == open(b, "rb").read()
+    x3 = jittered_grid(40, 2, 603)
+    p3 = FmmPlan(dev(x3), kernel="gaussian", shape=0.03, tol=1e-8)
+    net = pc.load_into(p3, a)
+    assert np.array_equal(net.params(), m.params())
+    lam, inf = p3.solve(dev(bumps_rhs(x3, 603)), rtol=1e-6, restart=50, max_iters=600, precond="learned")
+    print(f"[pc_load] learned solve: iters={inf['iters']} true_res={inf['true_res']:.2e}", flush=True)
+    assert inf["converged"] and inf["true_res"] <= 1e-6
+    for p_ in plans + [p3]:
+        p_.close()
+    m.close()
