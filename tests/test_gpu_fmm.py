@@ -227,7 +227,8 @@ def test_full_size_mixed_sampled_targets():
 
 @pytest.mark.parametrize("dtype,bound", [(torch.float64, 1e-13), (torch.float32, 1e-5)])
 def test_multiquadric_plan_is_the_exact_sum(dtype, bound):
-    """Multiquadric plans hold one leaf: the product is the exact sum (no far field)."""
+    """Multiquadric plans with opts.exact hold one leaf: the product is the exact sum (no far
+    field; the banded far field is tested in test_gpu_banded.py)."""
     from paper_1606_07652_amd import FmmPlan
     from workloads import mixed_points
     x = mixed_points(3000, 3, 71)

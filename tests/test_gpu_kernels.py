@@ -2,7 +2,8 @@
 kernels of the paper's numerical examples, section 5) against the oracle's direct sum of eq. 1,
 through the C ABI.
 
-* inverse multiquadric: single-leaf plans, the exact sum by the tiled direct kernel;
+* inverse multiquadric: single-leaf plans with opts.exact, the exact sum by the tiled direct
+  kernel (its banded far field is tested in test_gpu_banded.py);
 * Wendland: a uniform tree at the deepest level whose cells are at least the support radius
   wide, the adjacent cells as near field and no far field, so the product is exact; deep and
   single-leaf cases, 2-D, 3-D and 5-D, ragged sizes, blobs that crowd single cells;
