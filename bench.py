@@ -180,6 +180,51 @@ def roofline_of(kind, amount, ms, fp_peak, mfma_peak=FP64_MFMA_TFLOPS):
     return r
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy rate (GB/s counting the bytes read and written), the
+    memory bound of the whole-product roofline."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def product_roofline(model, t_meas_ms, fp_peak, mfma_peak, bw_gbs):
+    """Whole-product roofline: t_roof = sum over the phases of their algorithmic work at the
+    bound that limits them (flops at the vector or matrix peak, compulsory bytes at the measured
+    copy rate), against the measured time per product."""
+    per = {}
+    for k, (kind, amount) in model.items():
+        if kind == "hbm":
+            per[k] = amount / (bw_gbs * 1e9) * 1e3
+        elif kind == "mfma":
+            per[k] = amount / (mfma_peak * 1e12) * 1e3
+        else:
+            per[k] = amount / (fp_peak * 1e12) * 1e3
+    t_roof = sum(per.values())
+    return {"t_roof_ms": t_roof, "t_meas_ms": t_meas_ms, "frac": t_roof / t_meas_ms, "copy_GBps": bw_gbs,
+            "phase_t_roof_ms": {k: round(v, 4) for k, v in per.items()}}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def run_path(torch, FmmPlan, w, dtype, tol, steps, warmup, n_max, m2l_schedule=0):
     dev = torch.device("cuda:0")
     x = torch.as_tensor(w.points, dtype=dtype, device=dev)
@@ -344,7 +389,9 @@ def solve_family(torch, FmmPlan, pc, kernel, shape, n, rtol, cap, n_train=10000,
         secs = time.perf_counter() - t1
         out[kind] = {"seconds": secs, "time_to_rtol": secs if inf["converged"] else None,
                      "iters": inf["iters"], "true_res": inf["true_res"], "converged": bool(inf["converged"]),
-                     "fallback_used": inf["fallback_used"], "history": inf["history"][:16]}
+                     "fallback_used": inf["fallback_used"], "history": inf["history"][:16],
+                     # true relative residual against wall time, at every restart
+                     "curve_s_res": [[round(t_, 4), r_] for t_, r_ in zip(inf["history_s"][:64], inf["history"][:64])]}
         log(f"[bench] {kernel} {kind}: {inf['iters']} iterations, true residual {inf['true_res']:.3e}, "
             f"{secs:.2f} s")
     plan.close()
@@ -832,6 +879,8 @@ def main():
         roof["pairs_per_s"] = info["near_pairs"] / (ph[dom] * 1e-3)
         roof["flops_per_pair"] = gauss_pair_flops(info["d"], 8)
     phase_roof = {k: roofline_of(*model[k], ph[k], FP64_VEC_TFLOPS) for k in model if ph.get(k, 0) > 0}
+    bw = copy_bandwidth(torch)
+    prod_roof = product_roofline(model, main_run["ms_per_step"], FP64_VEC_TFLOPS, FP64_MFMA_TFLOPS, bw)
 
     result = {
         "metric": "RBF-FMM matvec points/s @ rel-L2<=1e-6; GMRES time-to-1e-8 learned-PC vs plain",
@@ -855,11 +904,15 @@ def main():
         "roofline": roof,
         "phase_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4), "achieved": round(v["achieved"], 3),
                                "unit": v["unit"]} for k, v in phase_roof.items()},
+        "product_roofline": prod_roof,
     }
     if f32_run is not None:
         result["fp32_path"] = {"value": n / (f32_run["ms_per_step"] * 1e-3), "unit": "points/s", "tol": 1e-4,
                                "ms_per_step": f32_run["ms_per_step"], "nodes": f32_run["info"]["nodes"],
-                               "phase_ms": f32_run["phase_ms"]}
+                               "phase_ms": f32_run["phase_ms"],
+                               "product_roofline": product_roofline(phase_model(f32_run["info"], 4, n),
+                                                                    f32_run["ms_per_step"], FP32_VEC_TFLOPS,
+                                                                    FP32_VEC_TFLOPS, bw)}
 
     if not args.no_mq:
         # the multiquadric half of the workload: same points and weights, c = 0.02
@@ -892,7 +945,7 @@ def main():
         ref = direct.direct_sum(xs, ls, "gaussian", w.shape, targets=xs[idx])
         tcpu = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": args.cpu_targets / tcpu, "unit": "points/s", "cores": direct.threads(),
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                                   "sample": f"{args.cpu_targets} seeded targets x all {n} sources, FP64 direct sum "
                                             f"({tcpu:.1f} s; points/s = targets / time)"}
         result["rel_l2_sampled"] = direct.rel_l2(main_run["u"][idx], ref)

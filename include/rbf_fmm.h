@@ -162,6 +162,7 @@ typedef struct rbf_solve_info {
     double seconds;      /* wall time of the solve */
     double history[256]; /* true relative residual at each restart (first 256) */
     int    nhistory;
+    double history_s[256];/* wall time from the start of the solve to each history entry */
 } rbf_solve_info;
 
 /* Solve A lambda = f by restarted GMRES with the fast product (section 1).

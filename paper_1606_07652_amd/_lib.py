@@ -34,7 +34,8 @@ class RbfSolveOpts(ctypes.Structure):
 class RbfSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("fallback_used", ctypes.c_int), ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("history", ctypes.c_double * 256), ("nhistory", ctypes.c_int)]
+                ("history", ctypes.c_double * 256), ("nhistory", ctypes.c_int),
+                ("history_s", ctypes.c_double * 256)]
 
 
 class RbfPlanInfo(ctypes.Structure):

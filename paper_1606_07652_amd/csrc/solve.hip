@@ -332,7 +332,11 @@ int solve_impl(rbf_plan *p, const void *f, void *lambda, double rtol, const rbf_
         double beta = 0;
         RBF_TRY(S.norm(S.rd, &beta));
         double rel = beta / bnorm;
-        if (inf.nhistory < 256) inf.history[inf.nhistory++] = rel;
+        if (inf.nhistory < 256) {
+            inf.history_s[inf.nhistory] =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            inf.history[inf.nhistory++] = rel;
+        }
         if (rel < best) {
             best = rel;
             RBF_HIP(hipMemcpyAsync(xbest, S.xd, sizeof(double) * na, hipMemcpyDeviceToDevice, s));

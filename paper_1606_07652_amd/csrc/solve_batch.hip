@@ -265,7 +265,10 @@ int solve_batch_impl(rbf_batch *b, const void *f, void *lambda, double rtol, con
         for (int q = 0; q < P; ++q) {
             const double beta = std::sqrt(tmp[q]);
             rel[q] = fn[q] > 0 ? beta / fn[q] : 0.0;
-            if (inf[q].nhistory < 256) inf[q].history[inf[q].nhistory++] = rel[q];
+            if (inf[q].nhistory < 256) {
+                inf[q].history_s[inf[q].nhistory] = el;
+                inf[q].history[inf[q].nhistory++] = rel[q];
+            }
             const bool act = fn[q] > 0 && rel[q] > rtol && its[q] < maxit && std::isfinite(rel[q]);
             done[q] = act ? 0 : 1;
             sc[q] = act ? 1.0 / beta : 0.0;

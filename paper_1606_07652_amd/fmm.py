@@ -107,7 +107,8 @@ class BatchPlan:
         code = L.load().rbf_interp_solve_batch(self._h, _ptr(f), _ptr(lam), float(rtol), ctypes.byref(o), infos)
         L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
         out = [{"iters": i.iters, "restarts": i.restarts, "converged": bool(i.converged), "true_res": i.true_res,
-                "seconds": i.seconds, "history": list(i.history[:i.nhistory])} for i in infos]
+                "seconds": i.seconds, "history": list(i.history[:i.nhistory]),
+                "history_s": list(i.history_s[:i.nhistory])} for i in infos]
         return lam, out
 
     def set_graph(self, on: bool):
@@ -195,7 +196,8 @@ class FmmPlan:
         L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
         return lam, {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
                      "fallback_used": int(info.fallback_used), "true_res": info.true_res,
-                     "seconds": info.seconds, "history": list(info.history[:info.nhistory])}
+                     "seconds": info.seconds, "history": list(info.history[:info.nhistory]),
+                "history_s": list(info.history_s[:info.nhistory])}
 
     def poly_terms(self) -> int:
         """Number of polynomial terms of solve_poly (rbf_poly_terms)."""
@@ -222,7 +224,8 @@ class FmmPlan:
         L.check(code, allow=(L.RBF_OK, L.RBF_ENOCONV))
         return lam, coeffs[:q], {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
                                  "true_res": info.true_res, "seconds": info.seconds,
-                                 "history": list(info.history[:info.nhistory])}
+                                 "history": list(info.history[:info.nhistory]),
+                                 "history_s": list(info.history_s[:info.nhistory])}
 
     # -- introspection ---------------------------------------------------------------
     def info(self) -> dict:
