@@ -253,12 +253,13 @@ def test_nan_network_falls_back():
 
 
 def test_learned_preconditioner_gain(tmp_path):
-    """Train on harvested pairs of plain solves of four 10^4-point problems, then solve a
-    fifth problem of the same family with identical caps: plain, block-Jacobi, the same
-    cycle with an untrained network (zero output: the block solve alone) and with the trained
-    one.  Measured result: no gain from the network.  The trained network's held-out loss
-    falls tenfold, yet its solve ends within 10% of the untrained network's; the gain over
-    plain GMRES comes from the block solves.  The test asserts exactly that."""
+    """Train on pairs harvested from block-Jacobi solves of four 10^4-point problems (the
+    residuals the learned direction is applied to come from block-Jacobi cycles), then solve a
+    fifth problem of the same family with identical caps: plain, block-Jacobi, the same cycle
+    with an untrained network (zero output: the block solve alone) and with the trained one.
+    Measured: the trained network ends about 5% below the untrained one (pairs from plain
+    solves gave no gain); most of the gain over plain GMRES comes from the block solves.  The
+    test asserts a gain of at least 2% over the untrained network and of 2x over plain GMRES."""
     from paper_1606_07652_amd import FmmPlan
     from paper_1606_07652_amd import pc
     from workloads import bumps_rhs
@@ -266,8 +267,9 @@ def test_learned_preconditioner_gain(tmp_path):
     rows = [[], [], []]
     for sd in (100, 101, 102, 103):
         x = jittered_grid(100, 2, sd)
-        plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
-        for k, a in enumerate(pc.harvest(plan, dev(bumps_rhs(x, sd)), rtol=1e-10, max_iters=1000)):
+        plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-8)
+        for k, a in enumerate(pc.harvest(plan, dev(bumps_rhs(x, sd)), rtol=1e-10, max_iters=1000,
+                                         precond="block_jacobi")):
             rows[k].append(a)
         plan.close()
     X, T, W = (torch.cat(r) for r in rows)
@@ -282,7 +284,7 @@ def test_learned_preconditioner_gain(tmp_path):
     m0 = pc.Mlp(seed=0)                      # untrained: zero output layer
     x = jittered_grid(100, 2, 200)
     f = dev(bumps_rhs(x, 200))
-    plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-6)
+    plan = FmmPlan(dev(x), kernel="gaussian", shape=s, tol=1e-8)
     res = {}
     for kind, net in (("none", None), ("block_jacobi", None), ("untrained", m0), ("learned", m2)):
         if net is not None:
@@ -297,7 +299,7 @@ def test_learned_preconditioner_gain(tmp_path):
         print(f"[gain] {kind}: iters={inf['iters']} true residual {true_res:.3e} fallback={inf['fallback_used']}",
               flush=True)
     assert res["learned"] <= 0.5 * res["none"]
-    assert 0.9 * res["untrained"] <= res["learned"] <= 1.1 * res["untrained"]
+    assert res["learned"] <= 0.98 * res["untrained"]
 
 
 def test_pc_train_and_load_match_the_step_by_step_pipeline(tmp_path):
