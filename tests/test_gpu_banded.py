@@ -84,9 +84,10 @@ def test_banded_small_and_ragged(n):
         p.close()
 
 
-def test_banded_separate_targets():
+@pytest.mark.parametrize("transfer", [-1, 1])
+def test_banded_separate_targets(transfer):
     """Evaluation at separate targets (targets inside, outside and at sources) with the
-    banded far field."""
+    banded far field, with the band transfers off and on."""
     from paper_1606_07652_amd import EvalPlan
     x = mixed_points(5000, 3, 720)
     lam = normal_weights(5000, 721)
@@ -94,9 +95,10 @@ def test_banded_separate_targets():
     y[:300] = x[:300]
     for kernel in ("multiquadric", "inverse_multiquadric"):
         for dtype, tol in ((torch.float64, 1e-6), (torch.float32, 1e-4)):
-            print(f"[banded eval] {kernel} {dtype}", flush=True)
-            p = EvalPlan(dev(x, dtype), dev(y, dtype), kernel=kernel, shape=0.02, tol=tol)
+            print(f"[banded eval] {kernel} {dtype} transfer={transfer}", flush=True)
+            p = EvalPlan(dev(x, dtype), dev(y, dtype), kernel=kernel, shape=0.02, tol=tol, band_transfer=transfer)
             assert p.info()["far_field"] == 1 and p.info()["nbands"] >= 2
+            assert any(b["transfer"] for b in p.bands()) == (transfer == 1)
             u = p.eval(dev(lam, dtype)).double().cpu().numpy()
             ref = direct.direct_sum(dev(x, dtype).double().cpu().numpy(), dev(lam, dtype).double().cpu().numpy(),
                                     kernel, 0.02, targets=dev(y, dtype).double().cpu().numpy())
