@@ -305,9 +305,9 @@ bool choose_grid(const rbf_plan *p, Band &b, double margin) {
         for (int k = 0; k < d - 1; ++k) P *= mn;
         // per point: aggregation and disaggregation; per cell: upward pass and translation,
         // the stencil passes reading each cell once per axis on grids of at most 16 cells a
-        // side and 2 r + 1 times on larger ones
+        // side and twice (running window) on larger ones
         const double cells = std::ldexp(1.0, d * l);
-        const double reads = (l >= 1 && (1 << l) > 16) ? (double)d * (2 * r + 1) : (double)d;
+        const double reads = (l >= 1 && (1 << l) > 16) ? 2.0 * d : (double)d;
         const double cost = (double)P * ((double)p->n + (8.0 + reads) * cells);
         if (cost < best) {
             best = cost;

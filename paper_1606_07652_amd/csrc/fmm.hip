@@ -793,13 +793,14 @@ __device__ __forceinline__ void m2m_body(DescC<T> &d, int bid) {
 
 // Coarse translation: box sum of radius r along one axis of the dense coarse grid.
 // Pass k reads the output of pass k-1 (the first reads Wc) and the last writes Lc.
-// Grids with at most kLineMax cells per side run one workgroup per (line along the axis,
-// 256-entry chunk): each thread holds the line's values in registers, so every cell is
-// read once per pass; larger grids run one workgroup per (cell, chunk).  Either way each
-// output adds its inputs in increasing order along the axis.
+// Every grid runs one workgroup per (line along the axis, 256-entry chunk).  Grids with at
+// most kLineMax cells per side hold the line's values in registers, so every cell is read
+// once per pass and each output adds its inputs in increasing order along the axis; larger
+// grids walk the line with a running window sum (add the cell entering the window, subtract
+// the one leaving it: two reads per output whatever the radius, in a fixed order).
 constexpr int kLineMax = 16;
 
-__host__ __device__ constexpr bool axis_by_lines(int lc) { return lc >= 1 && (1 << lc) <= kLineMax; }
+__host__ __device__ constexpr bool axis_by_lines(int lc) { return lc >= 1; }
 
 template <int D> __device__ __forceinline__ int64_t axis_bits(int64_t v, int lc, int axis) {
     int64_t ins = 0;
@@ -834,6 +835,30 @@ __device__ __forceinline__ void m2l_axis_body(DescC<T> &d, int axis, int bid) {
             for (int b = 0; b < lc * D; ++b)
                 if (!((mask >> b) & 1)) rest |= ((c >> k++) & 1) << b;
         }
+        if (side > kLineMax) {
+            const int64_t r = d.r;
+            C acc{0, 0};
+            for (int64_t j = 0; j <= min(r, side - 1); ++j) {
+                const C v = in[(rest | axis_bits<D>(j, lc, axis)) * P + p];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            out[(rest | axis_bits<D>(0, lc, axis)) * P + p] = acc;
+            for (int64_t k = 1; k < side; ++k) {
+                if (k + r < side) {
+                    const C v = in[(rest | axis_bits<D>(k + r, lc, axis)) * P + p];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+                if (k - r - 1 >= 0) {
+                    const C v = in[(rest | axis_bits<D>(k - r - 1, lc, axis)) * P + p];
+                    acc.x -= v.x;
+                    acc.y -= v.y;
+                }
+                out[(rest | axis_bits<D>(k, lc, axis)) * P + p] = acc;
+            }
+            return;
+        }
         C v[kLineMax];
 #pragma unroll
         for (int k = 0; k < kLineMax; ++k)
@@ -853,24 +878,6 @@ __device__ __forceinline__ void m2l_axis_body(DescC<T> &d, int axis, int bid) {
         }
         return;
     }
-    int64_t cc = 0;
-    for (int b = 0; b < lc; ++b) cc |= ((c >> (b * D + axis)) & 1) << b;
-    const int64_t lo = max((int64_t)0, cc - d.r), hi = min(side - 1, cc + d.r);
-    const int64_t rest = c & ~mask;
-    C s{0, 0};
-    // eight cells in flight per step, added in order along the axis
-    for (int64_t v0 = lo; v0 <= hi; v0 += 8) {
-        C x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = in[(rest | axis_bits<D>(min(v0 + u, hi), lc, axis)) * P + p];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (v0 + u <= hi) {
-                s.x += x[u].x;
-                s.y += x[u].y;
-            }
-    }
-    out[c * P + p] = s;
 }
 
 // Leaf translation + downward pass.  Blocks (sibling group, kLeafThreads-entry chunk of the
