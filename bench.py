@@ -79,10 +79,10 @@ def gauss_pair_flops(d, dtype_bytes):
 def residual_pair_flops(d, dtype_bytes=8):
     """Per near pair of a banded plan (multiquadric kernels), as the kernel executes it (a fused
     multiply-add counts 2): the distance and the accumulation (3 d + 3); q = r^2 + c^2, its
-    reciprocal square root and b = q / sqrt q (3, and in FP64 two Newton steps on the root and
-    the half of q: 9 more); the table index and local variable (3); the degree-5 polynomial
-    (10).  The inverse multiquadric's product with 1 / b is not counted."""
-    return 3 * d + 3 + (12 if dtype_bytes == 8 else 3) + 3 + 10
+    reciprocal square root and b = q / sqrt q (3, and in FP64 one Newton step on the root: 5
+    more); the table index and local variable (3); the degree-5 polynomial (10).  The inverse
+    multiquadric's product with 1 / b is not counted."""
+    return 3 * d + 3 + (8 if dtype_bytes == 8 else 3) + 3 + 10
 
 
 def measured_traffic(phase):

@@ -263,11 +263,14 @@ template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && size
 // The FP64 thin-plate spline goes through log_tab (tab: its two tables of 256 entries).
 template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
 // The residual kernel of a banded plan reads its polynomial pieces from tab.
-template <int KER> constexpr bool kRes = KER == kResTab;
-// residual pieces in LDS: kResStride entries per piece (the coefficients, then padding, so that
-// a piece starts on a 32-byte boundary), then 4 parameters; FP32 products hold them as floats
-constexpr int kResStride = 8;
-constexpr int kResLds = kResIntervals * kResStride + 4;
+template <int KER> constexpr bool kRes = KER == kResTab || KER == kResTabDiv;
+// residual pieces in LDS: kResStride entries per piece (its coefficients, unpadded), a piece of
+// zeros after the last (b >= bmax, where the residual is negligible, lands on it), then 3
+// parameters; FP32 products hold them as floats.  Unpadded FP64 pieces are 48 bytes apart, so
+// the pieces of 8 consecutive indices start on 8 different groups of 4 banks; 64-byte pieces
+// start on only 2, and the random per-lane piece reads measured six times the bank conflicts
+constexpr int kResStride = kResDegree + 1;
+constexpr int kResLds = (kResIntervals + 1) * kResStride + 4;
 template <class T, int KER>
 constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab
                         : kRes<KER>     ? (sizeof(T) == 8 ? kResLds : (kResLds + 1) / 2)
@@ -285,34 +288,32 @@ template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab
 }
 
 // Residual of the scale split of the multiquadric kernels (every Gaussian width below s0) at
-// squared distance r2: with b = sqrt(r2 + c^2), piece i = floor((b - c) inv) of the table, a
-// polynomial of degree kResDegree in v = (b - c) inv - i (after the pieces: inv, qmax, c and
-// the flag of the division by b; zero from r2 = qmax on).
+// squared distance r2: with b = sqrt(r2 + c^2), piece i = floor((b - c) inv) of the table (the
+// zero piece from b = bmax on, i.e. from r2 = qmax on), a polynomial of degree kResDegree in
+// v = (b - c) inv - i; the inverse multiquadric's table holds b times the residual.
 template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab_raw) {
-    const T *tab = reinterpret_cast<const T *>(tab_raw);   // entries in the product's precision
-    constexpr int kP = kResIntervals * kResStride;          // parameters after the pieces
-    // 1/b from the hardware reciprocal square root (FP64: two Newton steps, each squaring the
-    // relative error), b = q / b; the inverse multiquadric's division becomes a product
+    const T *tab = reinterpret_cast<const T *>(tab_raw);        // entries in the product's precision
+    constexpr int kP = (kResIntervals + 1) * kResStride;         // parameters after the pieces
+    // 1/b from the hardware reciprocal square root (relative error 5e-8 in FP64, measured; one
+    // Newton step: 4e-15), b = q / sqrt q; the inverse multiquadric's division is a product
     const T q = r2 + c2;
     T rb;
     if constexpr (sizeof(T) == 8) {
         rb = __builtin_amdgcn_rsq(q);
-        const T h = T(0.5) * q;
-        rb = rb * fma(-h * rb, rb, T(1.5));
-        rb = rb * fma(-h * rb, rb, T(1.5));
+        rb = rb * fma(T(-0.5) * q * rb, rb, T(1.5));
     } else {
         rb = __builtin_amdgcn_rsqf(q);
     }
     const T b = q * rb;
     const T s = (b - tab[kP + 2]) * tab[kP];
-    const int i = max(0, min((int)s, kResIntervals - 1));
+    const int i = max(0, min((int)s, kResIntervals));
     const T v = s - (T)i;
     const T *c = tab + i * kResStride;
     T y = c[kResDegree];
 #pragma unroll
     for (int k = kResDegree - 1; k >= 0; --k) y = fma(y, v, c[k]);
-    if (tab[kP + 3] != T(0)) y = y * rb;   // inverse multiquadric: the table holds b * residual
-    return r2 < tab[kP + 1] ? y : T(0);
+    if constexpr (KER == kResTabDiv) y = y * rb;
+    return y;
 }
 
 // Phi at squared distance r2 for every kernel of the near field and the direct sum.
@@ -482,16 +483,12 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
     }
     if constexpr (kRes<KER>) {
         T *rt = reinterpret_cast<T *>(tab);
-        constexpr int kP = kResIntervals * kResStride;
-        for (int j = threadIdx.x; j < kP; j += kWave) {
-            const int piece = j / kResStride, k = j - piece * kResStride;
-            rt[j] = k <= kResDegree ? (T)d.res_tab[piece * (kResDegree + 1) + k] : T(0);
-        }
+        constexpr int kP = (kResIntervals + 1) * kResStride;
+        for (int j = threadIdx.x; j < kP; j += kWave) rt[j] = j < kResCoefs ? (T)d.res_tab[j] : T(0);
         if (threadIdx.x == 0) {
             rt[kP] = (T)d.res_inv;
             rt[kP + 1] = (T)d.res_cut2;
             rt[kP + 2] = (T)sqrt((double)d.coef);   // c (coef = c^2)
-            rt[kP + 3] = (T)d.res_div_b;
         }
         __syncthreads();
     }
@@ -1256,6 +1253,7 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_WENDLAND: k_p2p<T, D, RBF_WENDLAND><<<g, kWave, 0, s>>>(w); break;
                 case RBF_THIN_PLATE: k_p2p<T, D, RBF_THIN_PLATE><<<g, kWave, 0, s>>>(w); break;
                 case kResTab: k_p2p<T, D, kResTab><<<g, kWave, 0, s>>>(w); break;
+                case kResTabDiv: k_p2p<T, D, kResTabDiv><<<g, kWave, 0, s>>>(w); break;
                 default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
             }
             break;
@@ -1576,7 +1574,6 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
     w.one.far = 1;   // the near field writes u_s, which the bands complete
     w.one.res_tab = p->res_tab;
     w.one.res_inv = p->res_inv;
-    w.one.res_div_b = p->kernel == RBF_INVERSE_MULTIQUADRIC ? 1.0 : 0.0;
     w.one.res_cut2 = p->res_qmax;
     w.lam = lam;
     w.u = u;
@@ -1593,7 +1590,7 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
         RBF_HIP(hipStreamWaitEvent(pt.side, pt.fork, 0));
         sn = pt.side;
     }
-    const int rk = kResTab;
+    const int rk = p->kernel == RBF_INVERSE_MULTIQUADRIC ? kResTabDiv : kResTab;
     RBF_HIP(pt.begin(1, sn));
     RBF_TRY((launch_phase<T, D, 4>(w, PH_P2P, phase_blocks<T>(w.one, PH_P2P), sn, 0, 0, rk)));
     RBF_HIP(pt.end());
@@ -1740,7 +1737,7 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->p2m_n = p->nleaves;
     d->l2p_acc = 0;
     d->res_tab = nullptr;
-    d->res_inv = d->res_cut2 = d->res_div_b = 0.0;
+    d->res_inv = d->res_cut2 = 0.0;
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);
 template void fill_desc<double>(const rbf_plan *, Desc<double> *);

@@ -54,7 +54,6 @@ template <class T> struct Desc {
     const double *res_tab;  // residual near-field kernel: polynomial pieces in b [kResCoefs]
     double res_inv;         // pieces per unit of b
     double res_cut2;        // r^2 from which the residual is zero (qmax)
-    double res_div_b;       // 1: the table holds b times the residual (inverse multiquadric)
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);

@@ -56,10 +56,11 @@ template <class T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
 
-// Near-field kernel of a banded plan: the residual of the scale split (widths below s0) of the
-// multiquadric kernels, as a piecewise polynomial in b = sqrt(r^2 + c^2) (kResIntervals pieces
-// of degree kResDegree over [c, bmax); zero from r^2 = qmax on).  Internal code, not ABI.
-constexpr int kResTab = 16;
+// Near-field kernels of a banded plan: the residual of the scale split (widths below s0) of
+// the multiquadric (kResTab) and of the inverse multiquadric (kResTabDiv: the table holds b
+// times the residual), as a piecewise polynomial in b = sqrt(r^2 + c^2) (kResIntervals pieces
+// of degree kResDegree over [c, bmax); zero from r^2 = qmax on).  Internal codes, not ABI.
+constexpr int kResTab = 16, kResTabDiv = 17;
 constexpr int kResIntervals = 128, kResDegree = 5;
 constexpr int kResCoefs = kResIntervals * (kResDegree + 1);
 
