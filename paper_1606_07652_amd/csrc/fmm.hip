@@ -547,24 +547,37 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
 }
 
 // Last-dimension phases, weighted by lambda: dl[i][h] = lam_i e^{-i xi_{H+h} x_{i,d}} for
-// h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).
+// h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).  A block
+// builds the rows of its kThreads points in LDS (rows padded by one entry against bank
+// conflicts) and copies them out as one contiguous span: written straight from the
+// recurrence, each store instruction strides by a row and the kernel ran at half the rate.
 template <class T, int D, int HMAX>
 __device__ __forceinline__ void phase_dl_body(DescC<T> &d, int bid) {
     using C = typename cplx<T>::type;
-    const int64_t i = bid * (int64_t)kThreads + threadIdx.x;
-    if (i >= d.n) return;
-    const double x = (double)d.xs[(int64_t)(D - 1) * d.n + i], l = (double)d.lam_s[i];
-    double sb, cb, ss, cs;
-    sincos(-d.xiH * x, &sb, &cb);
-    sincos(-d.dxi * x, &ss, &cs);
-    double er = l * cb, ei = l * sb;
-    C *o = d.dl + i * HMAX;
+    constexpr int ROW = HMAX + 1;
+    __shared__ C st[kThreads * ROW];
+    const int64_t i0 = bid * (int64_t)kThreads, i = i0 + threadIdx.x;
+    if (i < d.n) {
+        const double x = (double)d.xs[(int64_t)(D - 1) * d.n + i], l = (double)d.lam_s[i];
+        double sb, cb, ss, cs;
+        sincos(-d.xiH * x, &sb, &cb);
+        sincos(-d.dxi * x, &ss, &cs);
+        double er = l * cb, ei = l * sb;
+        C *o = st + threadIdx.x * ROW;
 #pragma unroll
-    for (int h = 0; h < HMAX; ++h) {
-        o[h] = (h < d.H) ? C{(T)er, (T)ei} : C{0, 0};
-        double nr = er * cs - ei * ss;
-        ei = er * ss + ei * cs;
-        er = nr;
+        for (int h = 0; h < HMAX; ++h) {
+            o[h] = (h < d.H) ? C{(T)er, (T)ei} : C{0, 0};
+            const double nr = er * cs - ei * ss;
+            ei = er * ss + ei * cs;
+            er = nr;
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kThreads, d.n - i0);
+    C *out = d.dl + i0 * HMAX;
+    for (int e = threadIdx.x; e < cnt * HMAX; e += kThreads) {
+        const int q = e / HMAX;
+        out[e] = st[q * ROW + (e - q * HMAX)];
     }
 }
 
