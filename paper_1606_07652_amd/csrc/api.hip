@@ -255,6 +255,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     Arena &ar = p->arena;
     if (rc == RBF_OK) rc = ar.alloc(&p->lam_s, tsz * n);
     if (rc == RBF_OK) rc = ar.alloc(&p->u_s, tsz * n);
+    if (rc == RBF_OK) rc = ar.alloc((void **)&p->p2p_ctr, sizeof(int) * kXcds * kCtrStride);
     if (rc == RBF_OK) rc = ar.alloc(&p->W, csz * p->P * p->nleaves * fboxes);
     if (rc == RBF_OK) rc = ar.alloc(&p->Lx, csz * p->R * p->HP * p->nleaves * fboxes);
     if (rc == RBF_OK) rc = ar.alloc(&p->dl, csz * p->HP * n * fboxes);

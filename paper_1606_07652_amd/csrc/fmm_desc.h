@@ -54,6 +54,7 @@ template <class T> struct Desc {
     const double *res_tab;  // residual near-field kernel: polynomial pieces in b [kResCoefs]
     double res_inv;         // pieces per unit of b
     double res_cut2;        // r^2 from which the residual is zero (qmax)
+    int *p2p_ctr;           // near-field work queue: per-XCD task counters, kCtrStride ints apart
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);

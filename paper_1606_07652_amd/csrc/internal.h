@@ -52,6 +52,9 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Near-field work queue: one task counter per XCD, each on its own 128-byte line.
+constexpr int kXcds = 8, kCtrStride = 32;
+
 template <class T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
@@ -169,6 +172,7 @@ struct rbf_plan {
     double *wc1 = nullptr;           // w_k C1(xi_k) per dimension (separable kernels) [mn]
     void *lam_s = nullptr;           // sorted coefficients [n]
     void *u_s = nullptr;             // sorted near-field result [n]
+    int *p2p_ctr = nullptr;          // near-field work-queue counters [8 * kCtrStride]
     void *W = nullptr;               // leaf expansions [nleaves][P] complex
     void *Lx = nullptr;              // leaf local expansions, rows padded: [nleaves][R][HP] complex
     void *Wc = nullptr;              // coarse expansions [ncells][P]
