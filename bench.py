@@ -101,7 +101,7 @@ def measured_traffic(phase):
 
 
 # kernel name prefix (as the profiler prints it, template arguments stripped) -> phase
-TRAFFIC_PHASES = {"k_gather": "permute", "k_phase_dl": "p2m_phase", "k_p2m": "p2m", "k_p2p": "p2p",
+TRAFFIC_PHASES = {"k_gather": "permute", "k_phase_dl": "p2m_phase", "k_p2m": "p2m", "k_p2p": "p2p", "k_p2p_queue": "p2p",
                   "k_m2m": "m2m", "k_m2l_axis": "m2l_coarse", "k_m2l_leaf": "m2l_leaf", "k_l2p": "l2p"}
 
 

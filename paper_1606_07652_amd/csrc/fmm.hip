@@ -435,7 +435,7 @@ __device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int
     const cptr<int> rng = uconst((const int *)d.src_rng);
     const T *__restrict__ X = d.xs;
     const T *__restrict__ L = d.lam_s;
-    const int g = (int)threadIdx.x / TP;
+    const int g = ((int)threadIdx.x % kWave) / TP;
     T acc = 0;
     for (int q = r0; q < r1; ++q) {
         const int j0 = rng[2 * q], j1 = rng[2 * q + 1];
@@ -457,8 +457,28 @@ __device__ __forceinline__ T p2p_split(DescC<T> &d, const T (&y)[D], int r0, int
     return acc;
 }
 
+// The near-field kernel's LDS table (FP64 Gaussian: 2^(j/256); FP64 thin-plate: log tables;
+// banded plans: residual pieces), filled by the NT threads of the workgroup; a barrier must
+// follow.
+template <class T, int KER>
+__device__ __forceinline__ void p2p_fill(DescC<T> &d, double *tab, int nt) {
+    if constexpr (kTabExp<T, KER> || kTabLog<T, KER>) fill_tab<T, KER>(tab, nt);
+    if constexpr (kRes<KER>) {
+        T *rt = reinterpret_cast<T *>(tab);
+        constexpr int kP = (kResIntervals + 1) * kResStride;
+        for (int j = threadIdx.x; j < kP; j += nt) rt[j] = j < kResCoefs ? (T)d.res_tab[j] : T(0);
+        if (threadIdx.x == 0) {
+            rt[kP] = (T)d.res_inv;
+            rt[kP + 1] = (T)d.res_cut2;
+            rt[kP + 2] = (T)sqrt((double)d.coef);   // c (coef = c^2)
+        }
+    }
+}
+template <class T, int KER> constexpr bool kP2pTab = kTabExp<T, KER> || kTabLog<T, KER> || kRes<KER>;
+
+// One task of the near field by the calling wave (lanes = threadIdx.x mod 64), its table filled.
 template <class T, int D, int KER>
-__device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ void p2p_task(DescC<T> &d, T *__restrict__ u, int bid, const double *tab) {
     const int64_t n = d.n;
     const cptr<int> tasks = uconst((const int *)d.ptasks), lb = uconst(d.leaf_begin);
     const cptr<int> sp = uconst(d.src_ptr);
@@ -468,31 +488,15 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
     const int m = t1 - t0;
     const int gl = m <= kWave / 8 ? 3 : m <= kWave / 4 ? 2 : m <= kWave / 2 ? 1 : 0;
     const int TP = kWave >> gl;
-    const int ti = t0 + (int)threadIdx.x % TP;
+    const int lane = (int)threadIdx.x % kWave;
+    const int ti = t0 + lane % TP;
     const bool act = ti < t1;
     // a lane without a target takes the chunk's first one (its sum is not written)
     T y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = d.xs[k * n + (act ? ti : t0)];
     const int r0 = sp[a], r1 = sp[a + 1];
-    // FP64 Gaussian: 2^(j/256); FP64 thin-plate: log tables; banded plans: residual pieces
-    __shared__ __align__(32) double tab[kTabLen<T, KER>];
     T coef = d.coef;
-    if constexpr (kTabExp<T, KER> || kTabLog<T, KER>) {
-        fill_tab<T, KER>(tab, kWave);
-        __syncthreads();
-    }
-    if constexpr (kRes<KER>) {
-        T *rt = reinterpret_cast<T *>(tab);
-        constexpr int kP = (kResIntervals + 1) * kResStride;
-        for (int j = threadIdx.x; j < kP; j += kWave) rt[j] = j < kResCoefs ? (T)d.res_tab[j] : T(0);
-        if (threadIdx.x == 0) {
-            rt[kP] = (T)d.res_inv;
-            rt[kP + 1] = (T)d.res_cut2;
-            rt[kP + 2] = (T)sqrt((double)d.coef);   // c (coef = c^2)
-        }
-        __syncthreads();
-    }
     if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
     const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : kRes<KER> ? (T)d.res_cut2 : T(0);
     T acc;
@@ -502,10 +506,20 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
         case 2: acc = p2p_split<T, D, KER, 4>(d, y, r0, r1, coef, cut2, tab); break;
         default: acc = p2p_split<T, D, KER, 8>(d, y, r0, r1, coef, cut2, tab); break;
     }
-    if (act && (int)threadIdx.x < TP) {
+    if (act && lane < TP) {
         if (d.far) d.u_s[ti] = acc;
         else u[d.off + d.perm[ti]] = acc;   // near-only plan: this is the result
     }
+}
+
+template <class T, int D, int KER>
+__device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid) {
+    __shared__ __align__(32) double tab[kTabLen<T, KER>];
+    if constexpr (kP2pTab<T, KER>) {
+        p2p_fill<T, KER>(d, tab, kWave);
+        __syncthreads();
+    }
+    p2p_task<T, D, KER>(d, u, bid, tab);
 }
 
 // Exact product over all pairs (rows of targets per workgroup, all sources tiled).
@@ -548,16 +562,19 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
 }
 
 // Last-dimension phases, weighted by lambda: dl[i][h] = lam_i e^{-i xi_{H+h} x_{i,d}} for
-// h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).  A block
-// builds the rows of its kThreads points in LDS (rows padded by one entry against bank
-// conflicts) and copies them out as one contiguous span: written straight from the
+// h < H, zero up to HMAX (FP64 rotation recurrence from an FP64 phase, stored in T).  A
+// one-wave block builds the rows of its 64 points in LDS (rows padded by one entry against
+// bank conflicts) and copies them out as one contiguous span: written straight from the
 // recurrence, each store instruction strides by a row and the kernel ran at half the rate.
+// (One wave keeps the block's LDS at 17 KB for FP64 rows of 16, so that it finds room beside
+// the near field's workgroups.)
+constexpr int kPhaseThreads = kWave;
 template <class T, int D, int HMAX>
 __device__ __forceinline__ void phase_dl_body(DescC<T> &d, int bid) {
     using C = typename cplx<T>::type;
     constexpr int ROW = HMAX + 1;
-    __shared__ C st[kThreads * ROW];
-    const int64_t i0 = bid * (int64_t)kThreads, i = i0 + threadIdx.x;
+    __shared__ C st[kPhaseThreads * ROW];
+    const int64_t i0 = bid * (int64_t)kPhaseThreads, i = i0 + threadIdx.x;
     if (i < d.n) {
         const double x = (double)d.xs[(int64_t)(D - 1) * d.n + i], l = (double)d.lam_s[i];
         double sb, cb, ss, cs;
@@ -574,9 +591,9 @@ __device__ __forceinline__ void phase_dl_body(DescC<T> &d, int bid) {
         }
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)kThreads, d.n - i0);
+    const int cnt = (int)min((int64_t)kPhaseThreads, d.n - i0);
     C *out = d.dl + i0 * HMAX;
-    for (int e = threadIdx.x; e < cnt * HMAX; e += kThreads) {
+    for (int e = threadIdx.x; e < cnt * HMAX; e += kPhaseThreads) {
         const int q = e / HMAX;
         out[e] = st[q * ROW + (e - q * HMAX)];
     }
@@ -1166,8 +1183,19 @@ template <class T, int D, int KER> __global__ void __launch_bounds__(kWave) k_p2
 // its own is done.  The grid holds fewer waves than the chip has slots, which leaves the rest
 // to the far-field kernels: a grid of one block per task fills every slot with near-field
 // waves that live long, and the memory-bound kernels beside it wait for them to drain.
-template <class T, int D, int KER> __global__ void __launch_bounds__(kWave) k_p2p_queue(Work<T> w) {
+// Its workgroups are kQueueWaves waves that share one copy of the kernel's LDS table (one copy
+// per one-wave workgroup would hold, at the residual kernel's 6 KB, most of a CU's LDS for the
+// whole run and keep the far-field kernels that need LDS off the CU); after the fill every wave
+// runs its own loop, with no further barrier.
+constexpr int kQueueWaves = 4;
+template <class T, int D, int KER>
+__global__ void __launch_bounds__(kQueueWaves * kWave) k_p2p_queue(Work<T> w) {
     DescC<T> &d = *(cptr<Desc<T>>)&w.one;
+    __shared__ __align__(32) double tab[kTabLen<T, KER>];
+    if constexpr (kP2pTab<T, KER>) {
+        p2p_fill<T, KER>(d, tab, kQueueWaves * kWave);
+        __syncthreads();
+    }
     const int nv = d.nptasks, per = nv / kXcds, rem = nv % kXcds;
     const int x0 = (int)blockIdx.x % kXcds;
     for (int k = 0; k < kXcds; ++k) {
@@ -1175,10 +1203,10 @@ template <class T, int D, int KER> __global__ void __launch_bounds__(kWave) k_p2
         const int lo = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
         for (;;) {
             int v = 0;
-            if (threadIdx.x == 0) v = atomicAdd(d.p2p_ctr + x * kCtrStride, 1);
+            if (threadIdx.x % kWave == 0) v = atomicAdd(d.p2p_ctr + x * kCtrStride, 1);
             v = __builtin_amdgcn_readfirstlane(__shfl(v, 0, kWave));
             if (v >= cnt) break;
-            p2p_body<T, D, KER>(d, w.u, lo + v);
+            p2p_task<T, D, KER>(d, w.u, lo + v, tab);
         }
     }
 }
@@ -1187,7 +1215,7 @@ template <class T, int D, int KER> __global__ void __launch_bounds__(kThreads) k
     DescC<T> &d = *resolve(w, lb);
     direct_body<T, D, KER>(d, w.u, lb);
 }
-template <class T, int D, int HMAX> __global__ void __launch_bounds__(kThreads) k_phase_dl(Work<T> w) {
+template <class T, int D, int HMAX> __global__ void __launch_bounds__(kPhaseThreads) k_phase_dl(Work<T> w) {
     int lb;
     DescC<T> &d = *resolve(w, lb);
     phase_dl_body<T, D, HMAX>(d, lb);
@@ -1256,7 +1284,8 @@ template <class T> int64_t phase_blocks(const Desc<T> &d, int phase) {
     const int64_t nch = (d.P + kThreads - 1) / kThreads;
     if (!d.far && phase != PH_GATHER && phase != PH_P2P && phase != PH_DIRECT) return 0;
     switch (phase) {
-        case PH_GATHER: case PH_PHASE_DL: case PH_DIRECT: return nb_pts;
+        case PH_GATHER: case PH_DIRECT: return nb_pts;
+        case PH_PHASE_DL: return (d.n + kPhaseThreads - 1) / kPhaseThreads;
         case PH_P2P: return d.nptasks;
         case PH_L2P:
             return (int64_t)d.ntasks * (64 / l2p_targets((int)sizeof(typename cplx<T>::type), d.dim, d.HP));
@@ -1303,7 +1332,7 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 default: k_direct<T, D, RBF_R5><<<g, kThreads, 0, s>>>(w); break;
             }
             break;
-        case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kThreads, 0, s>>>(w); break;
+        case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kPhaseThreads, 0, s>>>(w); break;
         case PH_P2M: k_p2m<T, D, HMAX><<<g, (kExpMfma<T> || D > 2) ? kThreads : kWave, shmem, s>>>(w); break;
         case PH_M2M: k_m2m<T><<<g, kThreads, 0, s>>>(w); break;
         case PH_M2L_AXIS: k_m2l_axis<T, D><<<g, kThreads, 0, s>>>(w, axis); break;
@@ -1328,13 +1357,16 @@ template <class T, int D>
 int launch_p2p_queue(const Work<T> &w, hipStream_t s, int kernel) {
     const int64_t ntask = w.one.nptasks;
     if (ntask <= 0) return RBF_OK;
-    const unsigned g = (unsigned)std::min<int64_t>(ntask, (int64_t)256 * 4 * kP2pQueueWaves);   // 256 CUs x 4 SIMDs
+    // 256 CUs x 4 SIMDs x kP2pQueueWaves waves, kQueueWaves to a workgroup
+    const int64_t waves = std::min<int64_t>(ntask, (int64_t)256 * 4 * kP2pQueueWaves);
+    const unsigned g = (unsigned)((waves + kQueueWaves - 1) / kQueueWaves);
+    constexpr int bt = kQueueWaves * kWave;
     switch (kernel) {
-        case RBF_GAUSSIAN: k_p2p_queue<T, D, RBF_GAUSSIAN><<<g, kWave, 0, s>>>(w); break;
-        case RBF_MULTIQUADRIC: k_p2p_queue<T, D, RBF_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
-        case RBF_INVERSE_MULTIQUADRIC: k_p2p_queue<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kWave, 0, s>>>(w); break;
-        case kResTab: k_p2p_queue<T, D, kResTab><<<g, kWave, 0, s>>>(w); break;
-        case kResTabDiv: k_p2p_queue<T, D, kResTabDiv><<<g, kWave, 0, s>>>(w); break;
+        case RBF_GAUSSIAN: k_p2p_queue<T, D, RBF_GAUSSIAN><<<g, bt, 0, s>>>(w); break;
+        case RBF_MULTIQUADRIC: k_p2p_queue<T, D, RBF_MULTIQUADRIC><<<g, bt, 0, s>>>(w); break;
+        case RBF_INVERSE_MULTIQUADRIC: k_p2p_queue<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, bt, 0, s>>>(w); break;
+        case kResTab: k_p2p_queue<T, D, kResTab><<<g, bt, 0, s>>>(w); break;
+        case kResTabDiv: k_p2p_queue<T, D, kResTabDiv><<<g, bt, 0, s>>>(w); break;
         default:
             set_error("near-field work queue: kernel %d has no far field", kernel);
             return RBF_EUNSUPPORTED;
