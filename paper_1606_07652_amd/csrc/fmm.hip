@@ -615,6 +615,9 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
     const int t0 = d.p2m_begin[a], t1 = d.p2m_end[a];   // the unit's sources
     const int row = part * blockDim.x + threadIdx.x;
     const bool act = row < R;
+    // a wave past the last row (the last part of a unit) builds tables and meets the barriers
+    // but skips the sums: 676 rows in 768 threads would otherwise run 12 waves of sums for 11
+    const bool wlive = __builtin_amdgcn_readfirstlane(part * (int)blockDim.x + ((int)threadIdx.x & ~(kWave - 1))) < R;
     const int64_t n = d.n;
     int md[DM];
     {
@@ -657,6 +660,7 @@ __device__ __forceinline__ void p2m_valu_body(DescC<T> &d, int bid, char *smem_r
 #pragma unroll
         for (int v = 0; v < kPre; ++v) sink |= pre[v];
         __syncthreads();
+        if (!wlive) continue;
         if constexpr (sizeof(T) == 4) {
             // prefetch the next point's uniform operands while the current one is used
             C cur[HMAX], nxt[HMAX];
@@ -723,7 +727,7 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
     const int64_t n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, jsel = lane >> 5, csel = (lane >> 4) & 1;
-    const int rbase = part * p2m_rows(D) + wave * 16 * NRT;
+    const int rbase = __builtin_amdgcn_readfirstlane(part * p2m_rows(D) + wave * 16 * NRT);   // wave-uniform
     // row digits of this lane's A rows (fastest digit k = d-2)
     int md[NRT][DM];
 #pragma unroll
@@ -769,6 +773,7 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
             const C *pt = tab + jc * ST;
 #pragma unroll
             for (int t = 0; t < NRT; ++t) {
+                if (rbase + 16 * t >= R) break;   // wave-uniform: the tiles past the last row
                 C kv = pt[md[t][0]];
 #pragma unroll
                 for (int k = 1; k < DM; ++k) kv = cmul(kv, pt[k * mn + md[t][k]]);
