@@ -81,9 +81,12 @@ double kernel_value(int kernel, double r2, double c) {
     return kernel == RBF_MULTIQUADRIC ? std::sqrt(r2 + c * c) : 1.0 / std::sqrt(r2 + c * c);
 }
 
-// window of the top band along one axis: 1 to within 1e-8 on |t| <= ext, below 1e-12 from
-// |t| = ext + 9 tau on (the half period)
-double window(double t, double ext, double tau) { return 0.5 * std::erfc((std::fabs(t) - (ext + 4.0 * tau)) / tau); }
+// window of the top band along one axis: 1 to within erfc(k)/2 on |t| <= ext (7.7e-9 at the
+// k = 4 of tolerances from 1e-6 up; the plan raises k for tighter ones), below 1e-12 from
+// |t| = ext + (k + 5) tau on (the half period)
+double window(double t, double ext, double tau, double k) {
+    return 0.5 * std::erfc((std::fabs(t) - (ext + k * tau)) / tau);
+}
 
 // Root-mean-square of the kernel over all pairs of an evenly spaced sample of the points
 // (at most 2048 of them, in Morton order): the scale against which the tolerance is split.
@@ -157,7 +160,7 @@ std::vector<double> band_table(const rbf_plan *p, const Band &b) {
             double r2 = 0, win = 1.0;
             for (int k = 0; k < d; ++k) {
                 r2 += t[k] * t[k];
-                win *= window(t[k], p->ext, b.s_hi);
+                win *= window(t[k], p->ext, b.s_hi, b.win_k);
             }
             K[s] = top_value(p->kernel, std::sqrt(r2 + c * c), b.s_lo) * win;
             continue;
@@ -387,7 +390,7 @@ void plan_transfers(rbf_plan *p, std::vector<Band> &bands) {
             const Band &b = bands[j];
             if (b.lc != 0 || b.sigma > S.sigma) continue;
             for (int K = 4; K <= std::min(16, S.mn); K += 2)
-                if (transfer_error(S, b, a, K) <= b.tau / (20.0 * d)) {
+                if (transfer_error(S, b, a, K) <= b.tau_x / (20.0 * d)) {
                     ks[j] = K;
                     double big = b.mn / 2;
                     for (int k = 0; k < d - 1; ++k) big *= std::max(S.mn, b.mn);
@@ -563,11 +566,18 @@ int plan_bands(rbf_plan *p) {
     // Tolerance of a piece relative to its largest value: the requested relative error times
     // the kernel's rms over pairs, split over the pieces (bands, top, residual) as independent
     // errors.  The band-limit rule bounds a piece's error by its value at r = 0 and its
-    // narrowest width, which overstates a mixture's error; a factor 4 looser than the even
-    // split measured 2e-7 (FP64, tol 1e-6) and 3e-5 (FP32, tol 1e-4) on the 3-D mixed sets
-    // of 2^13 and 2^20 points, and 16 looser still 2e-7 and 4e-5.
+    // narrowest width, which overstates a mixture's error, most for the narrow bands, whose
+    // error sits within their width of r = 0 and so touches few pairs.  Measured on the 3-D
+    // mixed sets (2^13 to 2^20 points) and the 2-D sets of the tests: with the split below
+    // (a factor 4 looser than the even split) FP64 products at tol 1e-6 came out at 1e-8 to 2e-7
+    // and FP32 at 1e-4 at 1e-6 to 1e-5; FP64 bands 16 times looser still came out at 1.2e-7 to
+    // 5.4e-7 (the 2^20-point products at 1.5e-7, in 60% of the time), so FP64 plans take that.
+    // FP32 plans keep the split: 16 times looser measured 2.6e-4 on the multiquadric.  The
+    // transfers' stencils keep the split's own tolerance.
     const double split = 0.25 * std::sqrt((double)(J + 2));
-    auto tau_for = [&](double mag) { return std::min(1e-2, std::max(1e-3 * tol, tol * p->phi_rms / (mag * split))); };
+    const double loose = p->dtype == RBF_F64 ? 16.0 : 1.0;
+    auto tau_at = [&](double mag, double f) { return std::min(1e-2, std::max(1e-3 * tol, f * tol * p->phi_rms / (mag * split))); };
+    auto tau_for = [&](double mag) { return tau_at(mag, loose); };
     std::vector<Band> bands;
     for (int j = 0; j < J; ++j) {
         Band b;
@@ -576,6 +586,7 @@ int plan_bands(rbf_plan *p) {
         const double mag = std::fabs(band_value(kernel, c, b.s_lo, b.s_hi));
         b.scale = mag;
         b.tau = tau_for(mag);
+        b.tau_x = tau_at(mag, 1.0);
         b.sigma = band_limit_t(b.tau) / b.s_lo;
         b.reach = b.s_hi * std::sqrt(2.0 * std::log(4.0 / b.tau) + 1.0);
         const double margin = b.s_hi * std::sqrt(2.0 * std::log(4.0 / b.tau));
@@ -596,8 +607,15 @@ int plan_bands(rbf_plan *p) {
         const double mag = kernel == RBF_MULTIQUADRIC ? top_value(kernel, bmax, s_top) : top_value(kernel, c, s_top);
         b.scale = mag;
         b.tau = tau_for(mag);
-        b.L = 2.0 * (ext + 9.0 * b.s_hi);
-        const double sig = band_limit_t(b.tau) / (1.2 * s_top);
+        b.tau_x = tau_at(mag, 1.0);
+        // the window's deviation from 1 inside the domain, times the top band's size (a few
+        // times the kernel's rms), stays two orders below the tolerance: at k = 4 it set a floor
+        // of 1.4e-8 under the multiquadric product whatever the tolerance
+        while (0.5 * std::erfc(b.win_k) > 1e-2 * tol && b.win_k < 8.0) b.win_k += 0.1;
+        b.L = 2.0 * (ext + (b.win_k + 5.0) * b.s_hi);
+        // the band limit of the top band's narrowest width, s_top, as for every other band (a
+        // limit at 1.2 s_top, enough at 1e-6, left 2e-7 of the multiquadric product's error)
+        const double sig = band_limit_t(b.tau) / s_top;
         b.mn = round_nodes((int)std::ceil(sig * b.L / M_PI) + 1);
         if (b.mn == 0) {
             set_error("rbf_fmm_plan: the top band needs more than 64 nodes per dimension at tol %g", tol);

@@ -78,6 +78,8 @@ struct Band {
     int top = 0;                 // 1: the windowed top band (widths >= s_lo)
     double s_lo = 0, s_hi = 0;   // widths of the band's Gaussians (top: s_hi = window width)
     double tau = 0;              // tolerance of the band relative to its largest value
+    double tau_x = 0;            // tolerance of the transfer into this band (the unloosened split)
+    double win_k = 4.0;          // top band: its window steps down win_k window widths outside the domain
     double sigma = 0, L = 0, reach = 0, rfar = 0, scale = 0;
     int lc = 0, r = 0, mn = 0, H = 0, HP = 0;
     int64_t R = 0, P = 0, ncells = 0;

@@ -120,6 +120,25 @@ def test_banded_exact_option_keeps_the_direct_sum():
     p.close()
 
 
+@pytest.mark.parametrize("kernel", ["multiquadric", "inverse_multiquadric"])
+def test_banded_tight_tolerances(kernel):
+    """FP64 products at tol 1e-7, 1e-8 and 1e-9 (the solve's products run at 1e-8): the top
+    band's window steps down further outside the domain as the tolerance tightens, and its band
+    limit follows the narrowest width it holds, so every product meets its tolerance against the
+    direct sum (a window 4 widths out, 1 - 7.7e-9 at the domain's faces, and a band limit at
+    1.2 times that width held the multiquadric at 1.4e-8 whatever the tolerance)."""
+    x = mixed_points(8192, 3, 745)
+    lam = normal_weights(8192, 746)
+    ref = direct.direct_sum(x, lam, kernel, 0.02)
+    for tol in (1e-7, 1e-8, 1e-9):
+        p = banded(x, kernel, 0.02, torch.float64, tol)
+        u = p.matvec(dev(lam)).cpu().numpy()
+        err = direct.rel_l2(u, ref)
+        print(f"  tol {tol:g}: rel-L2 vs direct sum = {err:.3e}", flush=True)
+        assert err <= tol
+        p.close()
+
+
 def test_banded_solve_reaches_the_true_residual():
     """GMRES over the banded product (inverse multiquadric, block-Jacobi): the returned
     coefficients meet the requested true residual of the fast operator, and under the exact
