@@ -727,7 +727,7 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
     const int64_t n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, jsel = lane >> 5, csel = (lane >> 4) & 1;
-    const int rbase = __builtin_amdgcn_readfirstlane(part * p2m_rows(D) + wave * 16 * NRT);   // wave-uniform
+    const int rbase = part * p2m_rows(D) + wave * 16 * NRT;
     // row digits of this lane's A rows (fastest digit k = d-2)
     int md[NRT][DM];
 #pragma unroll
@@ -773,7 +773,6 @@ __device__ __forceinline__ void p2m_body(DescC<T> &d, int bid, char *smem_raw) {
             const C *pt = tab + jc * ST;
 #pragma unroll
             for (int t = 0; t < NRT; ++t) {
-                if (rbase + 16 * t >= R) break;   // wave-uniform: the tiles past the last row
                 C kv = pt[md[t][0]];
 #pragma unroll
                 for (int k = 1; k < DM; ++k) kv = cmul(kv, pt[k * mn + md[t][k]]);
