@@ -90,6 +90,7 @@ double window(double t, double ext, double tau, double k) {
 
 // Root-mean-square of the kernel over all pairs of an evenly spaced sample of the points
 // (at most 2048 of them, in Morton order): the scale against which the tolerance is split.
+// The same pairs give the distribution of pair distances (p->pair_cdf, log-spaced bins).
 int kernel_rms(rbf_plan *p, double *rms) {
     const int64_t n = p->n;
     const int d = p->d;
@@ -106,6 +107,9 @@ int kernel_rms(rbf_plan *p, double *rms) {
         }
     }
     double acc = 0;
+    // pair distances in log-spaced bins (kPairBins per factor 2, from ext / 2^40 up)
+    std::vector<double> hist(kPairBinsTotal + 1, 0.0);
+    const double rlo = p->ext * std::ldexp(1.0, -40);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) {
             double r2 = 0;
@@ -115,9 +119,26 @@ int kernel_rms(rbf_plan *p, double *rms) {
             }
             const double v = kernel_value(p->kernel, r2, p->shape);
             acc += v * v;
+            const double r = std::sqrt(r2);
+            const int b = r <= rlo ? 0 : std::min(kPairBinsTotal, 1 + (int)(std::log2(r / rlo) * kPairBins));
+            hist[b] += 1.0;
         }
     *rms = std::sqrt(acc / ((double)m * m));
+    p->pair_cdf.assign(kPairBinsTotal + 1, 0.0);
+    double c = 0;
+    for (int b = 0; b <= kPairBinsTotal; ++b) { c += hist[b]; p->pair_cdf[b] = c / ((double)m * m); }
+    p->pair_rlo = rlo;
+    p->pair_min = 1.0 / m;
     return RBF_OK;
+}
+
+// Fraction of the sampled pairs (self pairs included) closer than R, from the histogram: the
+// upper edge of R's bin, so never below the true fraction.
+double pair_fraction(const rbf_plan *p, double R) {
+    if (p->pair_cdf.empty()) return 1.0;
+    if (R <= p->pair_rlo) return std::max(p->pair_cdf[0], p->pair_min);
+    const int b = std::min(kPairBinsTotal, 1 + (int)(std::log2(R / p->pair_rlo) * kPairBins));
+    return std::max(p->pair_cdf[b], p->pair_min);
 }
 
 // w(xi) C(xi) for the stored nodes of a band: C from the DFT of the band's samples over one
@@ -565,19 +586,19 @@ int plan_bands(rbf_plan *p) {
     const int J = (int)edges.size() - 1;
     // Tolerance of a piece relative to its largest value: the requested relative error times
     // the kernel's rms over pairs, split over the pieces (bands, top, residual) as independent
-    // errors.  The band-limit rule bounds a piece's error by its value at r = 0 and its
-    // narrowest width, which overstates a mixture's error, most for the narrow bands, whose
-    // error sits within their width of r = 0 and so touches few pairs.  Measured on the 3-D
-    // mixed sets (2^13 to 2^20 points) and the 2-D sets of the tests: with the split below
-    // (a factor 4 looser than the even split) FP64 products at tol 1e-6 came out at 1e-8 to 2e-7
-    // and FP32 at 1e-4 at 1e-6 to 1e-5; FP64 bands 16 times looser still came out at 1.2e-7 to
-    // 5.4e-7 (the 2^20-point products at 1.5e-7, in 60% of the time), so FP64 plans take that.
-    // FP32 plans keep the split: 16 times looser measured 2.6e-4 on the multiquadric.  The
-    // transfers' stencils keep the split's own tolerance.
+    // errors.  The band-limit rule bounds a piece's error by its value at r = 0; that error (the
+    // band-limit, aliasing and pruning terms) lives within about 6 widths s_hi of r = 0, so
+    // only the pairs that close carry it: a band's tolerance is divided by the square root of
+    // the fraction of sampled pairs closer than 6 s_hi (1 for the wide bands, much less for the
+    // narrow ones).  On top of that the bound still overstates the error, and FP64 plans take
+    // bands 16 times looser.  Measured over the test sets (3-D and 2-D, 1 to 2^20 points) at tol
+    // 1e-6: at most 5.4e-7 in FP64 (2.8e-7 / 2.0e-7 for the 2^20-point multiquadric / inverse
+    // multiquadric), at most 4.8e-6 in FP32 at 1e-4.  (FP32 bands 16 times looser measured 2.6e-4.)
+    // The transfers' stencils keep the plain split's tolerance.
     const double split = 0.25 * std::sqrt((double)(J + 2));
     const double loose = p->dtype == RBF_F64 ? 16.0 : 1.0;
+    constexpr double kErrWidths = 6.0;
     auto tau_at = [&](double mag, double f) { return std::min(1e-2, std::max(1e-3 * tol, f * tol * p->phi_rms / (mag * split))); };
-    auto tau_for = [&](double mag) { return tau_at(mag, loose); };
     std::vector<Band> bands;
     for (int j = 0; j < J; ++j) {
         Band b;
@@ -585,7 +606,7 @@ int plan_bands(rbf_plan *p) {
         b.s_hi = edges[j + 1];
         const double mag = std::fabs(band_value(kernel, c, b.s_lo, b.s_hi));
         b.scale = mag;
-        b.tau = tau_for(mag);
+        b.tau = tau_at(mag, loose / std::sqrt(pair_fraction(p, kErrWidths * b.s_hi)));
         b.tau_x = tau_at(mag, 1.0);
         b.sigma = band_limit_t(b.tau) / b.s_lo;
         b.reach = b.s_hi * std::sqrt(2.0 * std::log(4.0 / b.tau) + 1.0);
@@ -606,7 +627,7 @@ int plan_bands(rbf_plan *p) {
         const double bmax = std::sqrt((double)d) * ext + c;
         const double mag = kernel == RBF_MULTIQUADRIC ? top_value(kernel, bmax, s_top) : top_value(kernel, c, s_top);
         b.scale = mag;
-        b.tau = tau_for(mag);
+        b.tau = tau_at(mag, loose);   // every pair sees the top band (pair fraction 1)
         b.tau_x = tau_at(mag, 1.0);
         // the window's deviation from 1 inside the domain, times the top band's size (a few
         // times the kernel's rms), stays two orders below the tolerance: at k = 4 it set a floor

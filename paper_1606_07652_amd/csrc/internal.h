@@ -54,6 +54,8 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
 
 // Near-field work queue: one task counter per XCD, each on its own 128-byte line.
 constexpr int kXcds = 8, kCtrStride = 32;
+// pair-distance histogram of the band split: bins per factor 2, and their number
+constexpr int kPairBins = 8, kPairBinsTotal = 8 * 48;
 
 template <class T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
@@ -190,6 +192,8 @@ struct rbf_plan {
     double res_inv = 0;              // residual pieces per unit of b
     double *res_tab = nullptr;       // residual polynomial pieces [kResCoefs]
     double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
+    std::vector<double> pair_cdf;    // sampled pairs closer than each log-spaced distance
+    double pair_rlo = 0, pair_min = 0;
     void *bW = nullptr, *bLx = nullptr, *bWc = nullptr, *bLc = nullptr, *bTmp = nullptr, *bdl = nullptr;
     std::vector<hipEvent_t> band_ev; // profiling: event pairs per band and phase
     // interpolating transfers (the coarsest bands take their expansions from the source band's
