@@ -1354,8 +1354,9 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
 
 // Near-field work queue of a single problem: its grid holds this many waves per SIMD (of the
 // 8 a SIMD can hold at the kernel's register count).  Measured on the 2^20-point 3-D
-// workloads: the multiquadric product 57.6 ms with one block per task, 53.6 with the queue
-// at 8 waves, 53.5 at 4, 56.4 at 2; the Gaussian 9.17 / 9.08 / 8.94 ms at 8 / 4 / 2.
+// workloads (banded multiquadric beside its bands, Gaussian beside its far field): against one
+// workgroup per task, the queue at 8, 4 and 2 waves took the multiquadric product to 93%, 93%
+// and 98% of its time, the Gaussian to 100%, 99% and 98%.
 constexpr int kP2pQueueWaves = 4;
 template <class T, int D>
 int launch_p2p_queue(const Work<T> &w, hipStream_t s, int kernel) {
