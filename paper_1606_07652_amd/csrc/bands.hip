@@ -120,7 +120,8 @@ int kernel_rms(rbf_plan *p, double *rms) {
             const double v = kernel_value(p->kernel, r2, p->shape);
             acc += v * v;
             const double r = std::sqrt(r2);
-            const int b = r <= rlo ? 0 : std::min(kPairBinsTotal, 1 + (int)(std::log2(r / rlo) * kPairBins));
+            const double t = r <= rlo ? -1.0 : std::log2(r / rlo) * kPairBins;
+            const int b = !(t >= 0.0) ? 0 : t >= kPairBinsTotal - 1 ? kPairBinsTotal : 1 + (int)t;   // NaN: bin 0
             hist[b] += 1.0;
         }
     *rms = std::sqrt(acc / ((double)m * m));
@@ -135,9 +136,10 @@ int kernel_rms(rbf_plan *p, double *rms) {
 // Fraction of the sampled pairs (self pairs included) closer than R, from the histogram: the
 // upper edge of R's bin, so never below the true fraction.
 double pair_fraction(const rbf_plan *p, double R) {
-    if (p->pair_cdf.empty()) return 1.0;
+    if (p->pair_cdf.empty() || !(p->pair_rlo > 0.0)) return 1.0;   // no sample, or all points equal
     if (R <= p->pair_rlo) return std::max(p->pair_cdf[0], p->pair_min);
-    const int b = std::min(kPairBinsTotal, 1 + (int)(std::log2(R / p->pair_rlo) * kPairBins));
+    const double t = std::log2(R / p->pair_rlo) * kPairBins;
+    const int b = !(t < kPairBinsTotal - 1) ? kPairBinsTotal : 1 + (int)t;   // NaN: the last bin
     return std::max(p->pair_cdf[b], p->pair_min);
 }
 
