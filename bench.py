@@ -76,13 +76,14 @@ def gauss_pair_flops(d, dtype_bytes):
     return 3 * d + 3 + (12 if dtype_bytes == 8 else 1)
 
 
-def residual_pair_flops(d, dtype_bytes=8):
+def residual_pair_flops(d, dtype_bytes=8, in_q=True):
     """Per near pair of a banded plan (multiquadric kernels), as the kernel executes it (a fused
-    multiply-add counts 2): the distance and the accumulation (3 d + 3); q = r^2 + c^2, its
-    reciprocal square root and b = q / sqrt q (3, and in FP64 one Newton step on the root: 5
-    more); the table index and local variable (3); the degree-5 polynomial (10).  The inverse
-    multiquadric's product with 1 / b is not counted."""
-    return 3 * d + 3 + (8 if dtype_bytes == 8 else 3) + 3 + 10
+    multiply-add counts 2): the distance and the accumulation (3 d + 3); the table index and
+    local variable (3); the degree-5 polynomial (10).  A table in b = sqrt(r^2 + c^2) (plans
+    whose fit in q = r^2 + c^2 misses its bound) adds q, its reciprocal square root and
+    b = q / sqrt q (3, and in FP64 one Newton step on the root: 5 more); the inverse
+    multiquadric's product with 1 / b there is not counted."""
+    return 3 * d + 3 + (0 if in_q else (8 if dtype_bytes == 8 else 3)) + 3 + 10
 
 
 def measured_traffic(phase):
@@ -461,7 +462,7 @@ def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None, lev
         phase_ms = {k: v / calls for k, v in ph.items()}
         fp_peak = FP64_VEC_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
         mfma_peak = FP64_MFMA_TFLOPS if bytes_ == 8 else FP32_VEC_TFLOPS
-        model = {"p2p": ("alu", info["near_pairs"] * residual_pair_flops(info["d"], bytes_)),
+        model = {"p2p": ("alu", info["near_pairs"] * residual_pair_flops(info["d"], bytes_, info["residual_in_q"] == 1)),
                  "p2m": ("alu" if bytes_ == 8 else "mfma", 8.0 * n * sum_p),
                  "l2p": ("mfma", 8.0 * n * sum_p)}
         roofs = {k: roofline_of(*model[k], phase_ms[k], fp_peak, mfma_peak) for k in model if phase_ms.get(k, 0) > 0}
@@ -470,6 +471,7 @@ def banded_leg(torch, FmmPlan, w, kernel, steps, warmup, idx=None, ref=None, lev
         out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "tol": tol, "plan_ms": plan_ms,
                      "bands": len(bands), "transferred_bands": moved, "sum_half_nodes": sum_p, "near_level": info["coarse_level"],
                      "near_pairs": info["near_pairs"], "residual_width": info["residual_width"],
+                     "residual_in_q": info["residual_in_q"],
                      "phase_ms": phase_ms, "roofline": roof,
                      "phase_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4),
                                             "achieved": round(v["achieved"], 3), "unit": v["unit"]}

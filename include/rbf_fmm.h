@@ -216,6 +216,10 @@ typedef struct rbf_plan_info {
     int     nbands;       /* banded plans (multiquadric kernels): scale bands incl. the top */
     double  residual_width; /* banded plans: Gaussian width s0 below which the kernel is summed
                                directly over the near field */
+    int     residual_in_q;  /* banded plans: 1 when the near field's residual table is a piecewise
+                               polynomial in q = r^2 + c^2 (no square root per pair), 0 in
+                               b = sqrt(q) (where the fit in q misses the accuracy bound) */
+    int     reserved_info;
 } rbf_plan_info;
 
 /* Parameters and sizes chosen by the plan (host struct). */

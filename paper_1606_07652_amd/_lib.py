@@ -47,7 +47,8 @@ class RbfPlanInfo(ctypes.Structure):
                 ("band", ctypes.c_double), ("period", ctypes.c_double), ("rcut", ctypes.c_double),
                 ("rfar", ctypes.c_double), ("ext", ctypes.c_double), ("lo", ctypes.c_double * 5),
                 ("device_bytes", ctypes.c_int64), ("far_field", ctypes.c_int), ("nbands", ctypes.c_int),
-                ("residual_width", ctypes.c_double)]
+                ("residual_width", ctypes.c_double), ("residual_in_q", ctypes.c_int),
+                ("reserved_info", ctypes.c_int)]
 
 
 class RbfBandInfo(ctypes.Structure):

@@ -485,6 +485,7 @@ int rbf_fmm_plan_info(const rbf_plan *p, rbf_plan_info *info) {
     info->far_field = (p->far || !p->bands.empty()) ? 1 : 0;
     info->nbands = (int)p->bands.size();
     info->residual_width = p->res_s0;
+    info->residual_in_q = p->res_q;
     return RBF_OK;
 }
 

@@ -304,6 +304,47 @@ double residual_table(int kernel, double c, double bmax, double s0, std::vector<
     return emax;
 }
 
+// Polynomial pieces over q = r^2 + c^2 in [c^2, qmax) of the residual at b = sqrt q (smooth in
+// q there, since b >= c > 0): on each of kResIntervals equal pieces the interpolant of degree
+// kResDegree at Chebyshev points, as monomial coefficients in the piece's local variable v in
+// [0, 1); *inv = pieces per unit of r^2.  Returns the largest deviation of the residual it gives
+// from the closed form on a finer sample of every piece.
+double residual_table_q(int kernel, double c, double qmax, double s0, std::vector<double> &tab, double *inv) {
+    constexpr int n = kResDegree + 1;
+    const double q0 = c * c, dq = (qmax - q0) / kResIntervals;
+    *inv = 1.0 / dq;
+    tab.assign(kResCoefs, 0.0);
+    double emax = 0;
+    for (int k = 0; k < kResIntervals; ++k) {
+        double A[n][n + 1];
+        for (int i = 0; i < n; ++i) {
+            const double v = 0.5 - 0.5 * std::cos(M_PI * (2 * i + 1) / (2.0 * n));
+            double pw = 1.0;
+            for (int j = 0; j < n; ++j) { A[i][j] = pw; pw *= v; }
+            A[i][n] = residual_value(kernel, std::sqrt(q0 + (k + v) * dq), s0);
+        }
+        // Gaussian elimination with partial pivoting on the n x n Vandermonde system
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r) if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+            for (int j = 0; j <= n; ++j) std::swap(A[col][j], A[piv][j]);
+            for (int r = 0; r < n; ++r) {
+                if (r == col) continue;
+                const double f = A[r][col] / A[col][col];
+                for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+            }
+        }
+        for (int j = 0; j < n; ++j) tab[k * n + j] = A[j][n] / A[j][j];
+        for (int t = 0; t <= 16; ++t) {
+            const double v = t / 16.0;
+            double y = tab[k * n + n - 1];
+            for (int j = n - 2; j >= 0; --j) y = y * v + tab[k * n + j];
+            emax = std::max(emax, std::fabs(y - residual_value(kernel, std::sqrt(q0 + (k + v) * dq), s0)));
+        }
+    }
+    return emax;
+}
+
 int upload(Arena &ar, void **dst, const void *src, size_t bytes) {
     RBF_TRY(ar.alloc(dst, bytes));
     RBF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -573,8 +614,12 @@ int plan_bands(rbf_plan *p) {
         // beyond x = xcut, where it is below the tolerance) as polynomial pieces in b
         p->res_qmax = wn * wn;
         std::vector<double> tab;
-        const double err = residual_table(kernel, c, std::sqrt(wn * wn + c * c), p->res_s0, tab, &p->res_inv);
-        if (!(err <= 1e-3 * tol * p->phi_rms)) {
+        // the table in q (no square root per pair) where its fit meets the bound, else in b
+        const double bound = 1e-3 * tol * p->phi_rms;
+        double err = residual_table_q(kernel, c, wn * wn + c * c, p->res_s0, tab, &p->res_inv);
+        p->res_q = err <= bound ? 1 : 0;
+        if (!p->res_q) err = residual_table(kernel, c, std::sqrt(wn * wn + c * c), p->res_s0, tab, &p->res_inv);
+        if (!(err <= bound)) {
             set_error("rbf_fmm_plan: the near-field residual table deviates by %.2e (kernel rms %.2e, tol %g)",
                       err, p->phi_rms, tol);
             return RBF_EUNSUPPORTED;

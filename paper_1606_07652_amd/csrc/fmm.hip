@@ -264,7 +264,7 @@ template <class T, int KER> constexpr bool kTabExp = KER == RBF_GAUSSIAN && size
 // The FP64 thin-plate spline goes through log_tab (tab: its two tables of 256 entries).
 template <class T, int KER> constexpr bool kTabLog = KER == RBF_THIN_PLATE && sizeof(T) == 8;
 // The residual kernel of a banded plan reads its polynomial pieces from tab.
-template <int KER> constexpr bool kRes = KER == kResTab || KER == kResTabDiv;
+template <int KER> constexpr bool kRes = KER == kResTab || KER == kResTabDiv || KER == kResTabQ;
 // residual pieces in LDS: kResStride entries per piece (its coefficients, unpadded), a piece of
 // zeros after the last (b >= bmax, where the residual is negligible, lands on it), then 3
 // parameters; FP32 products hold them as floats.  Unpadded FP64 pieces are 48 bytes apart, so
@@ -289,12 +289,26 @@ template <class T, int KER> __device__ __forceinline__ void fill_tab(double *tab
 }
 
 // Residual of the scale split of the multiquadric kernels (every Gaussian width below s0) at
-// squared distance r2: with b = sqrt(r2 + c^2), piece i = floor((b - c) inv) of the table (the
-// zero piece from b = bmax on, i.e. from r2 = qmax on), a polynomial of degree kResDegree in
-// v = (b - c) inv - i; the inverse multiquadric's table holds b times the residual.
+// squared distance r2.  Tables in b (kResTab, kResTabDiv): with b = sqrt(r2 + c^2), piece
+// i = floor((b - c) inv) (the zero piece from b = bmax on, i.e. from r2 = qmax on), a polynomial
+// of degree kResDegree in v = (b - c) inv - i; the inverse multiquadric's table holds b times the
+// residual.  Table in q = r2 + c^2 (kResTabQ), where the plan's fit meets its accuracy: pieces
+// uniform in q, which are coarse in b near b = c when the near zone is wide.
 template <class T, int KER> __device__ __forceinline__ T kres(T r2, T c2, const double *tab_raw) {
     const T *tab = reinterpret_cast<const T *>(tab_raw);        // entries in the product's precision
     constexpr int kP = (kResIntervals + 1) * kResStride;         // parameters after the pieces
+    if constexpr (KER == kResTabQ) {
+        // pieces uniform in q = r2 + c^2 from c^2: piece floor(r2 inv), no square root and no
+        // division (the table holds the residual of either kernel itself)
+        const T s = min(r2 * tab[kP], (T)kResIntervals);          // r2 >= 0; NaN: the zero piece
+        const int i = (int)s;
+        const T v = s - (T)i;
+        const T *c = tab + i * kResStride;
+        T y = c[kResDegree];
+#pragma unroll
+        for (int k = kResDegree - 1; k >= 0; --k) y = fma(y, v, c[k]);
+        return y;
+    }
     // 1/b from the hardware reciprocal square root (relative error 5e-8 in FP64, measured; one
     // Newton step: 4e-15), b = q / sqrt q; the inverse multiquadric's division is a product
     const T q = r2 + c2;
@@ -1323,6 +1337,7 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_THIN_PLATE: k_p2p<T, D, RBF_THIN_PLATE><<<g, kWave, 0, s>>>(w); break;
                 case kResTab: k_p2p<T, D, kResTab><<<g, kWave, 0, s>>>(w); break;
                 case kResTabDiv: k_p2p<T, D, kResTabDiv><<<g, kWave, 0, s>>>(w); break;
+                case kResTabQ: k_p2p<T, D, kResTabQ><<<g, kWave, 0, s>>>(w); break;
                 default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
             }
             break;
@@ -1372,6 +1387,7 @@ int launch_p2p_queue(const Work<T> &w, hipStream_t s, int kernel) {
         case RBF_INVERSE_MULTIQUADRIC: k_p2p_queue<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, bt, 0, s>>>(w); break;
         case kResTab: k_p2p_queue<T, D, kResTab><<<g, bt, 0, s>>>(w); break;
         case kResTabDiv: k_p2p_queue<T, D, kResTabDiv><<<g, bt, 0, s>>>(w); break;
+        case kResTabQ: k_p2p_queue<T, D, kResTabQ><<<g, bt, 0, s>>>(w); break;
         default:
             set_error("near-field work queue: kernel %d has no far field", kernel);
             return RBF_EUNSUPPORTED;
@@ -1690,7 +1706,7 @@ int banded_matvec_d(rbf_plan *p, const T *lam, T *u) {
         RBF_HIP(hipStreamWaitEvent(pt.side, pt.fork, 0));
         sn = pt.side;
     }
-    const int rk = p->kernel == RBF_INVERSE_MULTIQUADRIC ? kResTabDiv : kResTab;
+    const int rk = p->res_q ? kResTabQ : p->kernel == RBF_INVERSE_MULTIQUADRIC ? kResTabDiv : kResTab;
     RBF_HIP(pt.begin(1, sn));
     if (pt.side)
         RBF_TRY((launch_p2p_queue<T, D>(w, sn, rk)));

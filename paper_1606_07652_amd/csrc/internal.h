@@ -64,8 +64,9 @@ template <> struct cplx<double> { using type = double2; };
 // Near-field kernels of a banded plan: the residual of the scale split (widths below s0) of
 // the multiquadric (kResTab) and of the inverse multiquadric (kResTabDiv: the table holds b
 // times the residual), as a piecewise polynomial in b = sqrt(r^2 + c^2) (kResIntervals pieces
-// of degree kResDegree over [c, bmax); zero from r^2 = qmax on).  Internal codes, not ABI.
-constexpr int kResTab = 16, kResTabDiv = 17;
+// of degree kResDegree over [c, bmax); zero from r^2 = qmax on), or of either kernel in
+// q = r^2 + c^2 (kResTabQ: pieces uniform in q over [c^2, qmax)).  Internal codes, not ABI.
+constexpr int kResTab = 16, kResTabDiv = 17, kResTabQ = 18;
 constexpr int kResIntervals = 128, kResDegree = 5;
 constexpr int kResCoefs = kResIntervals * (kResDegree + 1);
 
@@ -191,6 +192,7 @@ struct rbf_plan {
     double res_qmax = 0;             // r^2 from which the residual is negligible (the cell width^2)
     double res_inv = 0;              // residual pieces per unit of b
     double *res_tab = nullptr;       // residual polynomial pieces [kResCoefs]
+    int res_q = 0;                   // 1: the residual table is in q = r^2 + c^2 (kResTabQ)
     double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
     std::vector<double> pair_cdf;    // sampled pairs closer than each log-spaced distance
     double pair_rlo = 0, pair_min = 0;
