@@ -21,6 +21,12 @@ Closed forms used as pins (not used by the split reference itself):
   with w the Faddeeva function; its largest deviation from the Gaussian, at t = 0, is
   erfc(s sigma / sqrt 2).
 * Poisson summation: phi^Q(t) = sum_n (-1)^{n (Mn-1)} phi_sigma(t - n L), L = 2 pi / h.
+
+The band-limited Gaussian as a basis of its own (section 3, eq. 16 with the box of eq. 28):
+``phi_sigma_gauss`` is Phi_sigma(r) = prod_k phi_sigma(r_k) and ``direct_sum_phi_sigma`` the
+sum of eq. (1) with it, u_i = sum_j lam_j Phi_sigma(y_i - x_j), in chunked numpy.  Pinned by
+a two-dimensional numerical integral over the box, the smallest-eigenvalue bound of section
+3.1, and the Gaussian limit at large s sigma (tests/test_oracle_bandlimit.py).
 """
 from __future__ import annotations
 
@@ -88,4 +94,27 @@ def phi_q_poisson_1d_gauss(t, s: float, sigma: float, mn: int, nimg: int = 8):
     for n in range(-nimg, nimg + 1):
         sgn = -1.0 if (n * (mn - 1)) % 2 else 1.0
         out = out + sgn * phi_sigma_1d_gauss(t - n * L, s, sigma)
+    return out
+
+
+def phi_sigma_gauss(r, s: float, sigma: float):
+    """Phi_sigma(r) = prod_k phi_sigma(r_k): the Gaussian's transform cut off at the box
+    [-sigma, sigma]^d (eq. 28) factorises over the coordinates; r has shape (..., d)."""
+    r = np.asarray(r, dtype=np.float64)
+    out = np.ones(r.shape[:-1])
+    for k in range(r.shape[-1]):
+        out = out * phi_sigma_1d_gauss(r[..., k], s, sigma)
+    return out
+
+
+def direct_sum_phi_sigma(points, lam, s: float, sigma: float, targets=None, chunk: int = 256) -> np.ndarray:
+    """u_i = sum_j lam_j Phi_sigma(y_i - x_j) over all sources j (eq. 1 with the band-limited
+    kernel of eq. 16); y = targets or the sources.  Targets in chunks of ``chunk`` rows."""
+    src = np.asarray(points, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    tgt = src if targets is None else np.asarray(targets, dtype=np.float64)
+    out = np.empty(tgt.shape[0])
+    for a in range(0, tgt.shape[0], chunk):
+        diff = tgt[a:a + chunk, None, :] - src[None, :, :]
+        out[a:a + chunk] = phi_sigma_gauss(diff, s, sigma) @ lam
     return out
