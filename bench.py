@@ -718,6 +718,82 @@ def run_wendland(args):
     print(json.dumps(result), flush=True)
 
 
+def bandlimited_pair_flops(d):
+    """Floating-point operations the band-limited kernel executes per pair: per axis the
+    difference, its scaling to a piece position, the local variable u = 2 (s - i) - 1 and a
+    degree-7 Horner step (7 FMAs); the product over the axes and the weighted accumulation."""
+    return d * (1 + 1 + 2 + 2 * 7) + (d - 1) + 2
+
+
+def run_bandlimited(args):
+    """The band-limited Gaussian as the basis (section 3, eq. 16 with the box of eq. 28):
+    Phi_sigma(x) = prod_k phi_sigma(x_k), s = 0.03, s sigma = 3, on 2^16 points of the default
+    workload's mixed uniform/blob distribution, as the exact sum over all pairs (tiled direct
+    kernel), FP64 at tol 1e-10 and FP32 at 1e-5.  value = points / time of one FP64 product;
+    the roofline is the direct kernel's executed flops per pair over its time; the oracle
+    (closed form through scipy's Faddeeva function) checks 256 seeded targets."""
+    import torch
+
+    from paper_1606_07652_amd import FmmPlan
+    from workloads import c2
+
+    w = c2("gaussian", n=args.n_bl)
+    n, d = w.points.shape
+    s, sigma = 0.03, 3.0 / 0.03
+    rng = np.random.default_rng(321)
+    idx = np.sort(rng.choice(n, min(n, 256), replace=False))
+    ref = None
+    if not args.no_cpu:
+        from oracle import bandlimit
+        xs = w.points.astype(np.float64)
+        t1 = time.perf_counter()
+        ref = bandlimit.direct_sum_phi_sigma(xs, w.lam.astype(np.float64), s, sigma, targets=xs[idx])
+        tcpu = time.perf_counter() - t1
+    out = {}
+    for name, dt, tol, peak in (("f64", torch.float64, 1e-10, FP64_VEC_TFLOPS),
+                                ("f32", torch.float32, 1e-5, FP32_VEC_TFLOPS)):
+        X = torch.as_tensor(w.points, dtype=dt, device="cuda:0")
+        lam = torch.as_tensor(w.lam, dtype=dt, device="cuda:0")
+        t0 = time.perf_counter()
+        plan = FmmPlan(X, kernel="gaussian_bandlimited", shape=s, tol=tol, band=sigma)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        u = torch.empty_like(lam)
+        for _ in range(args.warmup):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.matvec(lam, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        flops = float(n) * n * bandlimited_pair_flops(d)
+        out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "pairs_per_s": float(n) * n / (ms * 1e-3),
+                     "plan_ms": plan_ms, "tol": tol, "roofline": roofline_of("alu", flops, ms, peak)}
+        if ref is not None:
+            out[name]["rel_l2_sampled"] = float(np.linalg.norm(u.double().cpu().numpy()[idx] - ref) /
+                                                np.linalg.norm(ref))
+        log(f"[bench] bandlimited {name}: {ms:.2f} ms per product ({n * n / (ms * 1e-3):.3e} pairs/s), "
+            f"plan {plan_ms:.0f} ms")
+        plan.close()
+        del X, lam, u
+        torch.cuda.empty_cache()
+    f = out["f64"]
+    roof = dict(f["roofline"])
+    roof["traffic"] = None
+    result = {"metric": "RBF matvec points/s, band-limited Gaussian basis (exact sum)", "value": f["points_per_s"],
+              "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+              "config": {"workload": "3d_mixed_uniform_blobs_gaussian_bandlimited_s0.03_ssigma3", "n": n,
+                         "kernel": "gaussian_bandlimited", "shape": s, "band": sigma},
+              "roofline": roof, "paths": out}
+    if ref is not None:
+        result["cpu_baseline"] = {"value": len(idx) / tcpu, "unit": "points/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"{len(idx)} seeded targets x all {n} sources ({tcpu:.1f} s)"}
+    print(json.dumps(result), flush=True)
+
+
 def run_eval(args):
     """Evaluation at separate targets: the default workload's 2^20 mixed sources and weights,
     2^20 targets uniform over the unit cube (seed 7), FP64 at tol 1e-6 and FP32 at 1e-4.
@@ -801,7 +877,9 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq", "eval", "wendland"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "solve", "c4", "c2mq", "eval", "wendland",
+                                                          "bandlimited"])
+    ap.add_argument("--n-bl", type=int, default=1 << 16, help="points of --workload bandlimited")
     ap.add_argument("--n-targets", type=int, default=1 << 20)
     ap.add_argument("--n-c4", type=int, default=1 << 18)
     ap.add_argument("--n-solve", type=int, default=1 << 21)
@@ -846,6 +924,8 @@ def main():
         return run_eval(args)
     if args.workload == "wendland":
         return run_wendland(args)
+    if args.workload == "bandlimited":
+        return run_bandlimited(args)
 
     import torch
 

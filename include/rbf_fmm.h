@@ -61,9 +61,21 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
  *   no far field: every pair inside the support is a near pair, so the product is exact (a
  *   single leaf when no such level below the root exists).  For Wendland, thin-plate and r^5
  *   tol and the tree options are ignored.  Any plan of one leaf without a far field computes
- *   its product with the tiled direct kernel. */
+ *   its product with the tiled direct kernel.
+ *   RBF_GAUSSIAN_BANDLIMITED is the band-limited Gaussian of section 3 (eq. 16, with the
+ *   cut-off box [-sigma, sigma]^d of eq. 28): Phi_sigma(x) = prod_k phi_sigma(x_k),
+ *   phi_sigma(t) = int_{-sigma}^{sigma} s/sqrt(2 pi) exp(-s^2 xi^2 / 2) cos(xi t) dxi, the
+ *   Gaussian of width s (shape) with its transform cut off at the bandwidth sigma, which
+ *   opts->band must give (RBF_EINVAL otherwise).  Its matrix is positive definite for
+ *   distinct points (section 3.1).  The plan tabulates phi_sigma on the host as piecewise
+ *   polynomials over [0, the bounding box's largest side], with a measured error of at most
+ *   tol phi_sigma(0) / (4 d) (floor 1e-14 phi_sigma(0)); products, evaluation and solves are
+ *   exact sums over all pairs through the tiled direct kernel (one leaf): the box's sharp
+ *   cut-off leaves tails decaying like 1/|t|, which a periodic frequency grid would alias.
+ *   RBF_EUNSUPPORTED: a table of more than 4096 pieces (min(sigma, 4 / s) times the box side
+ *   above about 1600), batch plans, the autotuner, block-Jacobi and learned preconditioners. */
 enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3,
-       RBF_THIN_PLATE = 4, RBF_R5 = 5 };
+       RBF_THIN_PLATE = 4, RBF_R5 = 5, RBF_GAUSSIAN_BANDLIMITED = 6 };
 enum { RBF_PC_NONE = 0, RBF_PC_BLOCK_JACOBI = 1, RBF_PC_LEARNED = 2 };
 
 /* Optional planning overrides; zero or negative fields mean "choose automatically".
@@ -75,7 +87,7 @@ typedef struct rbf_opts {
     int    coarse_level; /* level l_c of the coarse far-field stencil (-1 = rule) */
     int    coarse_radius;/* stencil radius r in cells at l_c (-1 = rule) */
     int    nodes;        /* quadrature nodes per dimension Mn, even (0 = rule) */
-    double band;         /* band limit sigma (0 = rule) */
+    double band;         /* band limit sigma (0 = rule); the bandwidth of RBF_GAUSSIAN_BANDLIMITED */
     int    m2l_schedule; /* leaf-translation block order: 0 or 1 = contiguous leaf ranges per
                             XCD (default), 2 = leaf-major over the whole grid */
     int    exact;        /* multiquadric and inverse multiquadric: 1 = exact sum (one leaf, the

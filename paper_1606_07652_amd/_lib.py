@@ -9,7 +9,8 @@ LIB_PATH = os.path.join(HERE, "lib", "librbffmm.so")
 
 RBF_OK, RBF_ENOCONV, RBF_EINVAL, RBF_EUNSUPPORTED, RBF_ENOMEM, RBF_EHIP, RBF_ESTATE = 0, 1, -1, -2, -3, -4, -5
 RBF_F32, RBF_F64 = 0, 1
-RBF_GAUSSIAN, RBF_MULTIQUADRIC, RBF_INVERSE_MULTIQUADRIC, RBF_WENDLAND, RBF_THIN_PLATE, RBF_R5 = 0, 1, 2, 3, 4, 5
+(RBF_GAUSSIAN, RBF_MULTIQUADRIC, RBF_INVERSE_MULTIQUADRIC, RBF_WENDLAND, RBF_THIN_PLATE, RBF_R5,
+ RBF_GAUSSIAN_BANDLIMITED) = 0, 1, 2, 3, 4, 5, 6
 RBF_PC_NONE, RBF_PC_BLOCK_JACOBI, RBF_PC_LEARNED = 0, 1, 2
 RBF_NPHASES = 7
 RBF_PC_BLOCK, RBF_MLP_IN, RBF_MLP_HIDDEN, RBF_MLP_NPARAMS = 64, 64, 256, 164672

@@ -55,8 +55,9 @@ namespace {
 
 // Exact-sum plans: the thin-plate spline and r^5 (no far field: their transforms are singular
 // at the origin), the multiquadric kernels with opts.exact or outside the dimensions of their
-// banded far field, and the base of the Wendland plan below.  Every pair is a near pair of a
-// single leaf: the product is the exact sum, evaluated by the tiled direct kernel.
+// banded far field, the band-limited Gaussian (its box cut-off leaves tails like 1/|t|, which
+// no periodic grid resolves), and the base of the Wendland plan below.  Every pair is a near
+// pair of a single leaf: the product is the exact sum, evaluated by the tiled direct kernel.
 void multiquadric_params(rbf_plan *p) {
     p->sigma = 1.0;
     p->rcut = p->rfar = p->ext;
@@ -117,7 +118,7 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
         return RBF_OK;
     }
     if (p->kernel == RBF_MULTIQUADRIC || p->kernel == RBF_INVERSE_MULTIQUADRIC || p->kernel == RBF_THIN_PLATE ||
-        p->kernel == RBF_R5) {
+        p->kernel == RBF_R5 || p->kernel == RBF_GAUSSIAN_BANDLIMITED) {
         multiquadric_params(p);
         return RBF_OK;
     }
@@ -211,7 +212,11 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     if (d < 1 || d > kMaxDim) { set_error("rbf_fmm_plan: d=%d out of range [1,5]", d); return RBF_EINVAL; }
     if (d != 2 && d != 3 && d != 5) { set_error("rbf_fmm_plan: d=%d is not compiled (2, 3, 5 are)", d); return RBF_EUNSUPPORTED; }
     if (dtype != RBF_F32 && dtype != RBF_F64) { set_error("rbf_fmm_plan: bad dtype %d", dtype); return RBF_EINVAL; }
-    if (kernel < RBF_GAUSSIAN || kernel > RBF_R5) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
+    if (kernel < RBF_GAUSSIAN || kernel > RBF_GAUSSIAN_BANDLIMITED) { set_error("rbf_fmm_plan: bad kernel %d", kernel); return RBF_EINVAL; }
+    if (kernel == RBF_GAUSSIAN_BANDLIMITED && !(opts && opts->band > 0 && std::isfinite(opts->band))) {
+        set_error("rbf_fmm_plan: the band-limited Gaussian needs its bandwidth in opts->band (> 0)");
+        return RBF_EINVAL;
+    }
     if (!(shape > 0) || !std::isfinite(shape)) { set_error("rbf_fmm_plan: shape must be positive"); return RBF_EINVAL; }
     if (!(tol > 0 && tol < 1)) { set_error("rbf_fmm_plan: tol must lie in (0, 1)"); return RBF_EINVAL; }
     rbf_plan *p = new (std::nothrow) rbf_plan();
@@ -242,6 +247,7 @@ int plan_impl(const void *points, int64_t n, int d, int dtype, int kernel, doubl
     }
     p->band_xfer = opts ? opts->band_transfer : 0;
     if (rc == RBF_OK && banded_kernel(kernel, d) && !(opts && opts->exact)) rc = plan_bands(p);
+    if (rc == RBF_OK && kernel == RBF_GAUSSIAN_BANDLIMITED) rc = bandlimited_table(p, opts->band);
     const int64_t fboxes = p->far ? 1 : 0;   // expansions are allocated only with a far field
     if (rc == RBF_OK) {
         double need = (double)fboxes * csz * p->P * (2.0 * p->nleaves + 3.0 * p->ncells) +

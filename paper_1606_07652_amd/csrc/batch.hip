@@ -343,6 +343,10 @@ using namespace rbf;
 
 extern "C" int rbf_fmm_autotune(const void *points, int64_t n, int d, int dtype, int kernel, double shape, double tol,
                                 const rbf_opts *base, int reps, void *stream, rbf_opts *best, double *best_ms) {
+    if (kernel == RBF_GAUSSIAN_BANDLIMITED) {
+        set_error("rbf_fmm_autotune: the band-limited Gaussian has one plan shape (an exact sum); nothing to tune");
+        return RBF_EUNSUPPORTED;
+    }
     if (!points || !best) { set_error("rbf_fmm_autotune: null argument"); return RBF_EINVAL; }
     if (n < 1) { set_error("rbf_fmm_autotune: n must be positive"); return RBF_EINVAL; }
     return autotune_impl(points, n, d, dtype, kernel, shape, tol, base, reps > 0 ? reps : 3, (hipStream_t)stream, false,
@@ -361,6 +365,10 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
             set_error("rbf_fmm_plan_batch: offsets must be strictly increasing from 0 (problem %d)", q);
             return RBF_EINVAL;
         }
+    if (kernel == RBF_GAUSSIAN_BANDLIMITED) {
+        set_error("rbf_fmm_plan_batch: the band-limited Gaussian has single plans only");
+        return RBF_EUNSUPPORTED;
+    }
     auto t0 = std::chrono::steady_clock::now();
     rbf_batch *b = new rbf_batch();
     b->nprob = nprob;

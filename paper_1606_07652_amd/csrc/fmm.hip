@@ -273,7 +273,8 @@ template <int KER> constexpr bool kRes = KER == kResTab || KER == kResTabDiv || 
 constexpr int kResStride = kResDegree + 1;
 constexpr int kResLds = (kResIntervals + 1) * kResStride + 4;
 template <class T, int KER>
-constexpr int kTabLen = kTabLog<T, KER> ? 2 * kLogTab
+constexpr int kTabLen = KER == RBF_GAUSSIAN_BANDLIMITED ? 1   // its table stays in global memory
+                        : kTabLog<T, KER> ? 2 * kLogTab
                         : kRes<KER>     ? (sizeof(T) == 8 ? kResLds : (kResLds + 1) / 2)
                                         : kExpTab;
 // fills the LDS table of the kernel (stride: the workgroup size); a barrier must follow
@@ -344,6 +345,31 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
     else return KFun<T>::r5(r2);
 }
 
+// Band-limited Gaussian (section 3, eq. 16 with the box of eq. 28): Phi_sigma(x) = prod_k
+// phi(x_k), phi from the plan's table in global memory (kBlHead, then kBlStride monomial
+// coefficients in u = 2 v - 1 per piece, v the position in the piece); inv = pieces per unit t,
+// last = the last piece, which also takes |t| rounded past the box side.  A NaN difference
+// reads piece 0 and yields NaN.
+template <class T>
+__device__ __forceinline__ T bl_axis(T t, T inv, int last, const double *__restrict__ tab) {
+    const T s = fabs(t) * inv;
+    const int i = min((int)s, last);
+    const T u = T(2) * (s - (T)i) - T(1);
+    const double *c = tab + kBlHead + i * kBlStride;
+    T y = (T)c[kBlDegree];
+#pragma unroll
+    for (int k = kBlDegree - 1; k >= 0; --k) y = fma(y, u, (T)c[k]);
+    return y;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T bl_pair(const T (&y)[D], const T (&x)[D], T inv, int last, const double *tab) {
+    T f = bl_axis<T>(y[0] - x[0], inv, last, tab);
+#pragma unroll
+    for (int k = 1; k < D; ++k) f *= bl_axis<T>(y[k] - x[k], inv, last, tab);
+    return f;
+}
+
 template <class T, int D, int KER>
 __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, const double *tab) {
     T r2 = 0;
@@ -395,6 +421,10 @@ __device__ __forceinline__ T p2p_step(const T (&y)[D], const T (&x)[S][D], const
 #pragma unroll
             for (int v = 0; v < S; ++v) acc = fma(w[v], KFun<T>::wendland(r2[v], coef), acc);
         }
+    } else if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
+        // coef: pieces per unit t; cut2: the last piece; tab: the table in global memory
+#pragma unroll
+        for (int v = 0; v < S; ++v) acc = fma(w[v], bl_pair<T, D>(y, x[v], coef, (int)cut2, tab), acc);
     } else {
 #pragma unroll
         for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
@@ -512,7 +542,8 @@ __device__ __forceinline__ void p2p_task(DescC<T> &d, T *__restrict__ u, int bid
     const int r0 = sp[a], r1 = sp[a + 1];
     T coef = d.coef;
     if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
-    const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : kRes<KER> ? (T)d.res_cut2 : T(0);
+    const T cut2 = KER == RBF_WENDLAND ? T(1) / (coef * coef) : (kRes<KER> || KER == RBF_GAUSSIAN_BANDLIMITED) ? (T)d.res_cut2 : T(0);
+    if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) tab = d.res_tab;
     T acc;
     switch (gl) {
         case 0: acc = p2p_whole<T, D, KER>(d, y, r0, r1, coef, cut2, tab); break;
@@ -562,14 +593,26 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
             sdat[threadIdx.x * DP + D] = d.lam_s[base + threadIdx.x];
         }
         __syncthreads();
-        for (int e = 0; e < cnt; ++e) {
-            T r2 = 0;
+        if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
+            // coef: pieces per unit t; the table and its last piece from the descriptor
+            const int last = (int)d.res_cut2;
+            const double *bt = d.res_tab;
+            for (int e = 0; e < cnt; ++e) {
+                T x[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                T t = y[k] - sdat[e * DP + k];
-                r2 += t * t;
+                for (int k = 0; k < D; ++k) x[k] = sdat[e * DP + k];
+                acc += sdat[e * DP + D] * bl_pair<T, D>(y, x, coef, last, bt);
             }
-            acc += sdat[e * DP + D] * kphi<T, KER>(r2, coef, tab);
+        } else {
+            for (int e = 0; e < cnt; ++e) {
+                T r2 = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    T t = y[k] - sdat[e * DP + k];
+                    r2 += t * t;
+                }
+                acc += sdat[e * DP + D] * kphi<T, KER>(r2, coef, tab);
+            }
         }
     }
     if (act) u[d.off + d.perm[ti]] = acc;
@@ -1338,7 +1381,11 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case kResTab: k_p2p<T, D, kResTab><<<g, kWave, 0, s>>>(w); break;
                 case kResTabDiv: k_p2p<T, D, kResTabDiv><<<g, kWave, 0, s>>>(w); break;
                 case kResTabQ: k_p2p<T, D, kResTabQ><<<g, kWave, 0, s>>>(w); break;
-                default: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
+                case RBF_GAUSSIAN_BANDLIMITED: k_p2p<T, D, RBF_GAUSSIAN_BANDLIMITED><<<g, kWave, 0, s>>>(w); break;
+                case RBF_R5: k_p2p<T, D, RBF_R5><<<g, kWave, 0, s>>>(w); break;
+                default:
+                    set_error("near-field kernel: unknown kernel %d", kernel);
+                    return RBF_EUNSUPPORTED;
             }
             break;
         case PH_DIRECT:
@@ -1348,7 +1395,11 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_INVERSE_MULTIQUADRIC: k_direct<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_WENDLAND: k_direct<T, D, RBF_WENDLAND><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_THIN_PLATE: k_direct<T, D, RBF_THIN_PLATE><<<g, kThreads, 0, s>>>(w); break;
-                default: k_direct<T, D, RBF_R5><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_GAUSSIAN_BANDLIMITED: k_direct<T, D, RBF_GAUSSIAN_BANDLIMITED><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_R5: k_direct<T, D, RBF_R5><<<g, kThreads, 0, s>>>(w); break;
+                default:
+                    set_error("direct kernel: unknown kernel %d", kernel);
+                    return RBF_EUNSUPPORTED;
             }
             break;
         case PH_PHASE_DL: k_phase_dl<T, D, HMAX><<<g, kPhaseThreads, 0, s>>>(w); break;
@@ -1858,6 +1909,12 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->p2p_ctr = p->p2p_ctr;
     d->res_tab = nullptr;
     d->res_inv = d->res_cut2 = 0.0;
+    if (p->kernel == RBF_GAUSSIAN_BANDLIMITED) {
+        // the per-axis table: pieces per unit t as coef, the last piece in res_cut2
+        d->coef = (T)p->bl_inv;
+        d->res_tab = p->bl_tab;
+        d->res_cut2 = p->bl_pieces - 1;
+    }
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);
 template void fill_desc<double>(const rbf_plan *, Desc<double> *);

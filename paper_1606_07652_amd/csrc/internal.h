@@ -69,6 +69,10 @@ template <> struct cplx<double> { using type = double2; };
 constexpr int kResTab = 16, kResTabDiv = 17, kResTabQ = 18;
 constexpr int kResIntervals = 128, kResDegree = 5;
 constexpr int kResCoefs = kResIntervals * (kResDegree + 1);
+// Band-limited Gaussian (RBF_GAUSSIAN_BANDLIMITED): phi_sigma per axis as pieces of degree
+// kBlDegree in u in [-1, 1] over [0, tmax]; the table holds the piece count, then kBlStride
+// monomial coefficients per piece (u^0 first).
+constexpr int kBlDegree = 7, kBlStride = kBlDegree + 1, kBlHead = 2, kBlMaxPieces = 4096;
 
 // One scale band of a banded far field (multiquadric kernels).  A band is a smooth part of
 // the kernel with its own quadrature grid (band limit sigma, nodes mn, period L), its own
@@ -193,6 +197,11 @@ struct rbf_plan {
     double res_inv = 0;              // residual pieces per unit of b
     double *res_tab = nullptr;       // residual polynomial pieces [kResCoefs]
     int res_q = 0;                   // 1: the residual table is in q = r^2 + c^2 (kResTabQ)
+    // band-limited Gaussian: per-axis table in the layout of kBlHead / kBlStride (device),
+    // pieces per unit t, piece count, measured largest fit error
+    double *bl_tab = nullptr;
+    double bl_inv = 0, bl_err = 0;
+    int bl_pieces = 0;
     double phi_rms = 0;              // rms of the kernel over sampled pairs (tolerance split)
     std::vector<double> pair_cdf;    // sampled pairs closer than each log-spaced distance
     double pair_rlo = 0, pair_min = 0;
@@ -258,6 +267,7 @@ int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u);
 int reject_eval_plan(const rbf_plan *p, const char *fn);
 int launch_direct(rbf_plan *p, const void *lambda, void *u);
 int plan_bands(rbf_plan *p);                                         // bands.hip
+int bandlimited_table(rbf_plan *p, double sigma);                    // bandlimited.hip
 template <class T>
 int xfer_band(const rbf_plan *p, const Xfer &x, const Band &S, const Band &Tb, const void *wc_keep, void *lx_s,
               hipStream_t s);                                          // xfer.hip

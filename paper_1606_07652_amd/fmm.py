@@ -15,7 +15,7 @@ from . import _lib as L
 
 _KERNELS = {"gaussian": L.RBF_GAUSSIAN, "multiquadric": L.RBF_MULTIQUADRIC,
             "inverse_multiquadric": L.RBF_INVERSE_MULTIQUADRIC, "wendland": L.RBF_WENDLAND,
-            "thin_plate": L.RBF_THIN_PLATE, "r5": L.RBF_R5}
+            "thin_plate": L.RBF_THIN_PLATE, "r5": L.RBF_R5, "gaussian_bandlimited": L.RBF_GAUSSIAN_BANDLIMITED}
 _PCS = {"none": L.RBF_PC_NONE, "block_jacobi": L.RBF_PC_BLOCK_JACOBI, "learned": L.RBF_PC_LEARNED}
 
 
