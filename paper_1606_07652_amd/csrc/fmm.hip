@@ -350,25 +350,33 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
 // coefficients in u = 2 v - 1 per piece, v the position in the piece); inv = pieces per unit t,
 // last = the last piece, which also takes |t| rounded past the box side.  A NaN difference
 // reads piece 0 and yields NaN.
-template <class T>
-__device__ __forceinline__ T bl_axis(T t, T inv, int last, const double *__restrict__ tab) {
+// pieces: the first piece's coefficients, ST apart (the table in global memory past its head,
+// as doubles, or the direct kernel's LDS copy in T)
+template <class T, class P, int ST = kBlStride>
+__device__ __forceinline__ T bl_axis(T t, T inv, int last, const P *__restrict__ pieces) {
     const T s = fabs(t) * inv;
     const int i = min((int)s, last);
     const T u = T(2) * (s - (T)i) - T(1);
-    const double *c = tab + kBlHead + i * kBlStride;
+    const P *c = pieces + i * ST;
     T y = (T)c[kBlDegree];
 #pragma unroll
     for (int k = kBlDegree - 1; k >= 0; --k) y = fma(y, u, (T)c[k]);
     return y;
 }
 
-template <class T, int D>
-__device__ __forceinline__ T bl_pair(const T (&y)[D], const T (&x)[D], T inv, int last, const double *tab) {
-    T f = bl_axis<T>(y[0] - x[0], inv, last, tab);
+template <class T, int D, class P, int ST = kBlStride>
+__device__ __forceinline__ T bl_pair(const T (&y)[D], const T (&x)[D], T inv, int last, const P *pieces) {
+    T f = bl_axis<T, P, ST>(y[0] - x[0], inv, last, pieces);
 #pragma unroll
-    for (int k = 1; k < D; ++k) f *= bl_axis<T>(y[k] - x[k], inv, last, tab);
+    for (int k = 1; k < D; ++k) f *= bl_axis<T, P, ST>(y[k] - x[k], inv, last, pieces);
     return f;
 }
+// Tables up to this size are staged in the direct kernel's LDS (in T), the pieces kBlLds<T>
+// entries apart: unpadded pieces (a power of two bytes) start on only a few bank groups, so
+// that the lanes' different pieces collide; one entry of padding spreads them (FP64, 2^16
+// points: 77 ms unpadded, 25 ms padded, 54 ms reading the table from global memory).
+constexpr int kBlLdsBytes = 48 * 1024;
+template <class T> constexpr int kBlLds = kBlStride + 1;
 
 template <class T, int D, int KER>
 __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, const double *tab) {
@@ -424,7 +432,7 @@ __device__ __forceinline__ T p2p_step(const T (&y)[D], const T (&x)[S][D], const
     } else if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
         // coef: pieces per unit t; cut2: the last piece; tab: the table in global memory
 #pragma unroll
-        for (int v = 0; v < S; ++v) acc = fma(w[v], bl_pair<T, D>(y, x[v], coef, (int)cut2, tab), acc);
+        for (int v = 0; v < S; ++v) acc = fma(w[v], bl_pair<T, D>(y, x[v], coef, (int)cut2, tab + kBlHead), acc);
     } else {
 #pragma unroll
         for (int v = 0; v < S; ++v) acc = fma(w[v], p2p_pair<T, D, KER>(y, x[v], coef, tab), acc);
@@ -569,7 +577,7 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
 
 // Exact product over all pairs (rows of targets per workgroup, all sources tiled).
 template <class T, int D, int KER>
-__device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int bid) {
+__device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int bid, char *smem_raw) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     const T *__restrict__ xs = d.xs;
@@ -583,6 +591,13 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
     T coef = d.coef;
     fill_tab<T, KER>(tab, kThreads);
     if constexpr (kTabExp<T, KER>) coef *= kExpTab;   // exact
+    T *const bt = reinterpret_cast<T *>(smem_raw);     // band-limited table in LDS (bl_lds)
+    if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
+        // ordered before its first use by the barriers of the first tile
+        if (d.bl_lds)
+            for (int j = threadIdx.x; j < ((int)d.res_cut2 + 1) * kBlStride; j += kThreads)
+                bt[(j / kBlStride) * kBlLds<T> + j % kBlStride] = (T)d.res_tab[kBlHead + j];
+    }
     T acc = 0;
     for (int64_t base = 0; base < n; base += kTile) {
         const int cnt = (int)min((int64_t)kTile, n - base);
@@ -594,14 +609,24 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
         }
         __syncthreads();
         if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
-            // coef: pieces per unit t; the table and its last piece from the descriptor
+            // coef: pieces per unit t; the last piece from the descriptor; the pieces from LDS
+            // when the launch staged them there, else from global memory
             const int last = (int)d.res_cut2;
-            const double *bt = d.res_tab;
-            for (int e = 0; e < cnt; ++e) {
-                T x[D];
+            if (d.bl_lds) {
+                for (int e = 0; e < cnt; ++e) {
+                    T x[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k) x[k] = sdat[e * DP + k];
-                acc += sdat[e * DP + D] * bl_pair<T, D>(y, x, coef, last, bt);
+                    for (int k = 0; k < D; ++k) x[k] = sdat[e * DP + k];
+                    acc += sdat[e * DP + D] * bl_pair<T, D, T, kBlLds<T>>(y, x, coef, last, (const T *)bt);
+                }
+            } else {
+                const double *gt = d.res_tab + kBlHead;
+                for (int e = 0; e < cnt; ++e) {
+                    T x[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) x[k] = sdat[e * DP + k];
+                    acc += sdat[e * DP + D] * bl_pair<T, D>(y, x, coef, last, gt);
+                }
             }
         } else {
             for (int e = 0; e < cnt; ++e) {
@@ -1272,9 +1297,10 @@ __global__ void __launch_bounds__(kQueueWaves * kWave) k_p2p_queue(Work<T> w) {
     }
 }
 template <class T, int D, int KER> __global__ void __launch_bounds__(kThreads) k_direct(Work<T> w) {
+    extern __shared__ char smem_raw[];
     int lb;
     DescC<T> &d = *resolve(w, lb);
-    direct_body<T, D, KER>(d, w.u, lb);
+    direct_body<T, D, KER>(d, w.u, lb, smem_raw);
 }
 template <class T, int D, int HMAX> __global__ void __launch_bounds__(kPhaseThreads) k_phase_dl(Work<T> w) {
     int lb;
@@ -1395,7 +1421,9 @@ int launch_phase(const Work<T> &w, int phase, int64_t nblocks, hipStream_t s, in
                 case RBF_INVERSE_MULTIQUADRIC: k_direct<T, D, RBF_INVERSE_MULTIQUADRIC><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_WENDLAND: k_direct<T, D, RBF_WENDLAND><<<g, kThreads, 0, s>>>(w); break;
                 case RBF_THIN_PLATE: k_direct<T, D, RBF_THIN_PLATE><<<g, kThreads, 0, s>>>(w); break;
-                case RBF_GAUSSIAN_BANDLIMITED: k_direct<T, D, RBF_GAUSSIAN_BANDLIMITED><<<g, kThreads, 0, s>>>(w); break;
+                case RBF_GAUSSIAN_BANDLIMITED:
+                    k_direct<T, D, RBF_GAUSSIAN_BANDLIMITED><<<g, kThreads, shmem, s>>>(w);
+                    break;
                 case RBF_R5: k_direct<T, D, RBF_R5><<<g, kThreads, 0, s>>>(w); break;
                 default:
                     set_error("direct kernel: unknown kernel %d", kernel);
@@ -1599,8 +1627,11 @@ int direct_d(rbf_plan *p, const T *lam, T *u) {
     w.lam = lam;
     w.u = u;
     const int64_t nb = phase_blocks<T>(w.one, PH_DIRECT);
+    // the band-limited Gaussian's table in the direct kernel's LDS (fill_desc sets bl_lds when
+    // it fits in kBlLdsBytes)
+    const size_t sh = w.one.bl_lds ? sizeof(T) * (size_t)p->bl_pieces * kBlLds<T> : 0;
     RBF_TRY((launch_phase<T, D, 4>(w, PH_GATHER, nb, p->stream, 0, 0, p->kernel)));
-    RBF_TRY((launch_phase<T, D, 4>(w, PH_DIRECT, nb, p->stream, 0, 0, p->kernel)));
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_DIRECT, nb, p->stream, 0, sh, p->kernel)));
     return RBF_OK;
 }
 
@@ -1909,11 +1940,13 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->p2p_ctr = p->p2p_ctr;
     d->res_tab = nullptr;
     d->res_inv = d->res_cut2 = 0.0;
+    d->bl_lds = 0;
     if (p->kernel == RBF_GAUSSIAN_BANDLIMITED) {
         // the per-axis table: pieces per unit t as coef, the last piece in res_cut2
         d->coef = (T)p->bl_inv;
         d->res_tab = p->bl_tab;
         d->res_cut2 = p->bl_pieces - 1;
+        d->bl_lds = sizeof(T) * (size_t)p->bl_pieces * kBlLds<T> <= (size_t)kBlLdsBytes ? 1 : 0;
     }
 }
 template void fill_desc<float>(const rbf_plan *, Desc<float> *);

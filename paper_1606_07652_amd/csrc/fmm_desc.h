@@ -55,6 +55,8 @@ template <class T> struct Desc {
     double res_inv;         // pieces per unit of b
     double res_cut2;        // r^2 from which the residual is zero (qmax)
     int *p2p_ctr;           // near-field work queue: per-XCD task counters, kCtrStride ints apart
+    int bl_lds;             // band-limited Gaussian: 1 = the direct kernel copies the table (pieces
+                            // only, in T) into its dynamic LDS, which the launch sizes for it
 };
 
 template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d);

@@ -51,7 +51,9 @@ def points(kind, n, d, seed):
     return mixed_points(n, d, seed) if kind == "mixed" else uniform_points(n, d, seed)
 
 
-@pytest.mark.parametrize("d,n,s,ssig,kind", CASES)
+# s = 0.003 with s sigma = 1.2 (sigma = 400) needs about 1000 pieces: 64 KB in FP64, past the
+# direct kernel's LDS staging limit, so the pieces are read from global memory
+@pytest.mark.parametrize("d,n,s,ssig,kind", CASES + [(3, 600, 0.003, 1.2, "uniform")])
 def test_product_fp64_matches_oracle(d, n, s, ssig, kind):
     tol = 1e-10
     x = points(kind, n, d, 700 + n)
