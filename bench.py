@@ -718,18 +718,20 @@ def run_wendland(args):
     print(json.dumps(result), flush=True)
 
 
-def bandlimited_pair_flops(d):
+def bandlimited_pair_flops(d, deg):
     """Floating-point operations the band-limited kernel executes per pair: per axis the
     difference, its scaling to a piece position, the local variable u = 2 (s - i) - 1 and a
-    degree-7 Horner step (7 FMAs); the product over the axes and the weighted accumulation."""
-    return d * (1 + 1 + 2 + 2 * 7) + (d - 1) + 2
+    Horner step of the table's degree (7 in FP64, 3 in FP32: that many FMAs); the product over
+    the axes and the weighted accumulation.  3-D: 58 (FP64), 34 (FP32)."""
+    return d * (1 + 1 + 2 + 2 * deg) + (d - 1) + 2
 
 
 def run_bandlimited(args):
     """The band-limited Gaussian as the basis (section 3, eq. 16 with the box of eq. 28):
     Phi_sigma(x) = prod_k phi_sigma(x_k), s = 0.03, s sigma = 3, on 2^16 points of the default
     workload's mixed uniform/blob distribution, as the exact sum over all pairs (tiled direct
-    kernel), FP64 at tol 1e-10 and FP32 at 1e-5.  value = points / time of one FP64 product;
+    kernel; per-axis tables of degree 7 in FP64, 3 in FP32), FP64 at tol 1e-10 and FP32 at 1e-5.
+    value = points / time of one FP64 product;
     the roofline is the direct kernel's executed flops per pair over its time; the oracle
     (closed form through scipy's Faddeeva function) checks 256 seeded targets."""
     import torch
@@ -767,7 +769,7 @@ def run_bandlimited(args):
             plan.matvec(lam, u)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        flops = float(n) * n * bandlimited_pair_flops(d)
+        flops = float(n) * n * bandlimited_pair_flops(d, 7 if dt == torch.float64 else 3)
         out[name] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "pairs_per_s": float(n) * n / (ms * 1e-3),
                      "plan_ms": plan_ms, "tol": tol, "roofline": roofline_of("alu", flops, ms, peak)}
         if ref is not None:

@@ -7,7 +7,8 @@
 // phi is even, band-limited with bandwidth sigma (so its k-th derivative is at most
 // sigma^k phi(0)) and, with the sharp cut-off, decays only like 1/|t|.  The plan tabulates it
 // over [0, tmax], tmax the largest side of the points' bounding box (every coordinate
-// difference lies in [-tmax, tmax]), as pieces of degree kBlDegree: each piece interpolates
+// difference lies in [-tmax, tmax]), as pieces of degree kBlDegree64 (FP64 plans) or
+// kBlDegree32 (FP32 plans): each piece interpolates
 // phi at the Chebyshev points of the first kind of its interval, converted to monomials in
 // the piece's variable u in [-1, 1].  phi itself comes from composite Gauss-Legendre
 // quadrature of its defining integral, with panels short enough (at most one radian of the
@@ -70,33 +71,37 @@ double phi_axis(double t, double s, double sigma, const GaussLegendre &g) {
     return 2.0 * a * sum;
 }
 
-// Monomial coefficients (u^0 first) of the Chebyshev polynomials T_0..T_kBlDegree.
+// Monomial coefficients (u^0 first) of the Chebyshev polynomials T_0..T_kMaxK-1.
+constexpr int kMaxK = kBlDegree64 + 1;
 struct ChebMonomials {
-    double c[kBlStride][kBlStride] = {};
+    double c[kMaxK][kMaxK] = {};
     ChebMonomials() {
         c[0][0] = 1.0;
         c[1][1] = 1.0;
-        for (int k = 2; k < kBlStride; ++k)
-            for (int j = 0; j < kBlStride; ++j)
+        for (int k = 2; k < kMaxK; ++k)
+            for (int j = 0; j < kMaxK; ++j)
                 c[k][j] = (j > 0 ? 2.0 * c[k - 1][j - 1] : 0.0) - c[k - 2][j];
     }
 };
 
-// Tabulate with np pieces; returns the largest error found at the check points.
-double fit_pieces(double s, double sigma, double tmax, int np, const GaussLegendre &g, std::vector<double> &tab) {
+// Tabulate with np pieces of degree deg (at most kBlDegree64); returns the largest error found
+// at the check points.
+double fit_pieces(double s, double sigma, double tmax, int np, int deg, const GaussLegendre &g,
+                  std::vector<double> &tab) {
     static const ChebMonomials cm;
-    constexpr int K = kBlStride;
-    tab.assign(kBlHead + (size_t)np * kBlStride, 0.0);
+    const int K = deg + 1;
+    tab.assign(kBlHead + (size_t)np * K, 0.0);
     tab[0] = np;
+    tab[1] = deg;
     const double h = tmax / np;
-    double un[K];
+    double un[kMaxK];
     for (int j = 0; j < K; ++j) un[j] = std::cos(M_PI * (j + 0.5) / K);
     // check points: the piece's ends and two points between nodes
     const double uc[4] = {-1.0, -0.37, 0.61, 1.0};
     double emax = 0.0;
     for (int i = 0; i < np; ++i) {
         const double a0 = i * h;
-        double f[K], a[K];
+        double f[kMaxK], a[kMaxK];
         for (int j = 0; j < K; ++j) f[j] = phi_axis(a0 + 0.5 * h * (un[j] + 1.0), s, sigma, g);
         // Chebyshev coefficients a_k = (2 / K) sum_j f_j T_k(u_j), a_0 halved
         for (int k = 0; k < K; ++k) {
@@ -104,12 +109,12 @@ double fit_pieces(double s, double sigma, double tmax, int np, const GaussLegend
             for (int j = 0; j < K; ++j) v += f[j] * std::cos(k * M_PI * (j + 0.5) / K);
             a[k] = (k == 0 ? 1.0 : 2.0) * v / K;
         }
-        double *b = tab.data() + kBlHead + (size_t)i * kBlStride;
+        double *b = tab.data() + kBlHead + (size_t)i * K;
         for (int k = 0; k < K; ++k)
             for (int j = 0; j < K; ++j) b[j] += a[k] * cm.c[k][j];
         for (double u : uc) {
-            double y = b[kBlDegree];
-            for (int k = kBlDegree - 1; k >= 0; --k) y = y * u + b[k];
+            double y = b[deg];
+            for (int k = deg - 1; k >= 0; --k) y = y * u + b[k];
             emax = std::max(emax, std::fabs(y - phi_axis(a0 + 0.5 * h * (u + 1.0), s, sigma, g)));
         }
     }
@@ -124,11 +129,15 @@ int bandlimited_table(rbf_plan *p, double sigma) {
     const double s = p->shape;
     const double tmax = p->ext * (1.0 + 1e-9);
     const double phi0 = std::erf(s * sigma / std::sqrt(2.0));   // phi(0)
-    const double bound = std::max(p->tol / (4.0 * p->d), 1e-14) * phi0;
-    // start from pieces of 0.4 rad of the bandwidth (or of 0.1 s where the Gaussian's own
-    // scale is the finer one); the fit costs pieces x panels, so a first estimate above the
-    // cap is refused before any fitting
-    const double want = std::ceil(tmax * std::min(sigma, 4.0 / s) / 0.4);
+    const bool f64 = p->dtype == RBF_F64;
+    const int deg = f64 ? kBlDegree64 : kBlDegree32;
+    // floors: what the product's own arithmetic resolves
+    const double bound = std::max(p->tol / (4.0 * p->d), f64 ? 1e-14 : 3e-8) * phi0;
+    // start from pieces of 0.4 rad of the bandwidth for degree 7 (fit error about 5e-15 of
+    // phi(0)), 0.3 rad for degree 3 (about 1e-7), or of 0.1 s, 0.075 s where the Gaussian's own
+    // scale is the finer one; the fit costs pieces x panels, so a first estimate above the cap
+    // is refused before any fitting
+    const double want = std::ceil(tmax * std::min(sigma, 4.0 / s) / (f64 ? 0.4 : 0.3));
     if (!(want <= kBlMaxPieces)) {
         set_error("band-limited Gaussian: sigma %g over the box side %g needs about %.0f table pieces, more than %d",
                   sigma, tmax, want, kBlMaxPieces);
@@ -138,7 +147,7 @@ int bandlimited_table(rbf_plan *p, double sigma) {
     std::vector<double> tab;
     double err = INFINITY;
     for (;;) {
-        err = fit_pieces(s, sigma, tmax, np, g, tab);
+        err = fit_pieces(s, sigma, tmax, np, deg, g, tab);
         if (err <= bound || np >= kBlMaxPieces) break;
         np = std::min(kBlMaxPieces, (int)std::ceil(np * 1.5));
     }

@@ -346,25 +346,26 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
 }
 
 // Band-limited Gaussian (section 3, eq. 16 with the box of eq. 28): Phi_sigma(x) = prod_k
-// phi(x_k), phi from the plan's table in global memory (kBlHead, then kBlStride monomial
+// phi(x_k), phi from the plan's table in global memory (kBlHead, then kBlDeg<T> + 1 monomial
 // coefficients in u = 2 v - 1 per piece, v the position in the piece); inv = pieces per unit t,
 // last = the last piece, which also takes |t| rounded past the box side.  A NaN difference
 // reads piece 0 and yields NaN.
 // pieces: the first piece's coefficients, ST apart (the table in global memory past its head,
 // as doubles, or the direct kernel's LDS copy in T)
-template <class T, class P, int ST = kBlStride>
+template <class T, class P, int ST = kBlDeg<T> + 1>
 __device__ __forceinline__ T bl_axis(T t, T inv, int last, const P *__restrict__ pieces) {
+    constexpr int DEG = kBlDeg<T>;
     const T s = fabs(t) * inv;
     const int i = min((int)s, last);
     const T u = T(2) * (s - (T)i) - T(1);
     const P *c = pieces + i * ST;
-    T y = (T)c[kBlDegree];
+    T y = (T)c[DEG];
 #pragma unroll
-    for (int k = kBlDegree - 1; k >= 0; --k) y = fma(y, u, (T)c[k]);
+    for (int k = DEG - 1; k >= 0; --k) y = fma(y, u, (T)c[k]);
     return y;
 }
 
-template <class T, int D, class P, int ST = kBlStride>
+template <class T, int D, class P, int ST = kBlDeg<T> + 1>
 __device__ __forceinline__ T bl_pair(const T (&y)[D], const T (&x)[D], T inv, int last, const P *pieces) {
     T f = bl_axis<T, P, ST>(y[0] - x[0], inv, last, pieces);
 #pragma unroll
@@ -376,7 +377,7 @@ __device__ __forceinline__ T bl_pair(const T (&y)[D], const T (&x)[D], T inv, in
 // that the lanes' different pieces collide; one entry of padding spreads them (FP64, 2^16
 // points: 77 ms unpadded, 25 ms padded, 54 ms reading the table from global memory).
 constexpr int kBlLdsBytes = 48 * 1024;
-template <class T> constexpr int kBlLds = kBlStride + 1;
+template <class T> constexpr int kBlLds = kBlDeg<T> + 2;
 
 template <class T, int D, int KER>
 __device__ __forceinline__ T p2p_pair(const T (&y)[D], const T (&x)[D], T coef, const double *tab) {
@@ -595,8 +596,8 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
     if constexpr (KER == RBF_GAUSSIAN_BANDLIMITED) {
         // ordered before its first use by the barriers of the first tile
         if (d.bl_lds)
-            for (int j = threadIdx.x; j < ((int)d.res_cut2 + 1) * kBlStride; j += kThreads)
-                bt[(j / kBlStride) * kBlLds<T> + j % kBlStride] = (T)d.res_tab[kBlHead + j];
+            for (int j = threadIdx.x; j < ((int)d.res_cut2 + 1) * (kBlDeg<T> + 1); j += kThreads)
+                bt[(j / (kBlDeg<T> + 1)) * kBlLds<T> + j % (kBlDeg<T> + 1)] = (T)d.res_tab[kBlHead + j];
     }
     T acc = 0;
     for (int64_t base = 0; base < n; base += kTile) {

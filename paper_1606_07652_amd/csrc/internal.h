@@ -69,10 +69,12 @@ template <> struct cplx<double> { using type = double2; };
 constexpr int kResTab = 16, kResTabDiv = 17, kResTabQ = 18;
 constexpr int kResIntervals = 128, kResDegree = 5;
 constexpr int kResCoefs = kResIntervals * (kResDegree + 1);
-// Band-limited Gaussian (RBF_GAUSSIAN_BANDLIMITED): phi_sigma per axis as pieces of degree
-// kBlDegree in u in [-1, 1] over [0, tmax]; the table holds the piece count, then kBlStride
-// monomial coefficients per piece (u^0 first).
-constexpr int kBlDegree = 7, kBlStride = kBlDegree + 1, kBlHead = 2, kBlMaxPieces = 4096;
+// Band-limited Gaussian (RBF_GAUSSIAN_BANDLIMITED): phi_sigma per axis as pieces in u in
+// [-1, 1] over [0, tmax], of degree 7 for FP64 products and 3 for FP32 ones (whose arithmetic
+// ends near 1e-7 anyway, and whose LDS reads halve); the table holds the piece count and the
+// degree, then degree + 1 monomial coefficients per piece (u^0 first).
+constexpr int kBlDegree64 = 7, kBlDegree32 = 3, kBlHead = 2, kBlMaxPieces = 4096;
+template <class T> constexpr int kBlDeg = sizeof(T) == 8 ? kBlDegree64 : kBlDegree32;
 
 // One scale band of a banded far field (multiquadric kernels).  A band is a smooth part of
 // the kernel with its own quadrature grid (band limit sigma, nodes mn, period L), its own
@@ -197,7 +199,7 @@ struct rbf_plan {
     double res_inv = 0;              // residual pieces per unit of b
     double *res_tab = nullptr;       // residual polynomial pieces [kResCoefs]
     int res_q = 0;                   // 1: the residual table is in q = r^2 + c^2 (kResTabQ)
-    // band-limited Gaussian: per-axis table in the layout of kBlHead / kBlStride (device),
+    // band-limited Gaussian: per-axis table in the layout of kBlHead / kBlDeg (device),
     // pieces per unit t, piece count, measured largest fit error
     double *bl_tab = nullptr;
     double bl_inv = 0, bl_err = 0;
