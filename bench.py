@@ -778,7 +778,24 @@ def run_bandlimited(args):
         log(f"[bench] bandlimited {name}: {ms:.2f} ms per product ({n * n / (ms * 1e-3):.3e} pairs/s), "
             f"plan {plan_ms:.0f} ms")
         plan.close()
-        del X, lam, u
+        # evaluation at n separate targets uniform over the unit cube (the near-field kernel over
+        # the joint set, the table read from global memory)
+        from paper_1606_07652_amd import EvalPlan
+        from workloads import uniform_points
+        Y = torch.as_tensor(uniform_points(n, d, 17), dtype=dt, device="cuda:0")
+        ep = EvalPlan(X, Y, kernel="gaussian_bandlimited", shape=s, tol=tol, band=sigma)
+        ue = ep.eval(lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ep.eval(lam, ue)
+        torch.cuda.synchronize()
+        ems = (time.perf_counter() - t0) * 1e3 / args.steps
+        out[name]["eval_ms"] = ems
+        out[name]["eval_pairs_per_s"] = float(n) * n / (ems * 1e-3)
+        log(f"[bench] bandlimited {name} evaluation at {n} targets: {ems:.2f} ms")
+        ep.close()
+        del X, lam, u, Y, ue
         torch.cuda.empty_cache()
     f = out["f64"]
     roof = dict(f["roofline"])

@@ -52,8 +52,8 @@ def points(kind, n, d, seed):
 
 
 # s = 0.003 with s sigma = 1.2 (sigma = 400) needs about 1000 pieces: 64 KB in FP64, past the
-# direct kernel's LDS staging limit, so the pieces are read from global memory
-@pytest.mark.parametrize("d,n,s,ssig,kind", CASES + [(3, 600, 0.003, 1.2, "uniform")])
+# direct kernel's LDS staging limit, so the pieces are read from global memory; and one 5-D set
+@pytest.mark.parametrize("d,n,s,ssig,kind", CASES + [(3, 600, 0.003, 1.2, "uniform"), (5, 700, 0.2, 2.0, "uniform")])
 def test_product_fp64_matches_oracle(d, n, s, ssig, kind):
     tol = 1e-10
     x = points(kind, n, d, 700 + n)
