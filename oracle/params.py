@@ -3,16 +3,16 @@
 The paper leaves the choice of sigma and M open (low-rank section: "in practice one
 chooses ...", with sigma = pi for unit-spaced samples).  The library uses the rule
 below for the Gaussian exp(-r^2/(2 s^2)); it is written out here independently so that a
-test can compare the plan's choice with it.  Each line is an error budget of tol/4 on a
-relative scale:
+test can compare the plan's choice with it.  Each line is an error budget on a relative
+scale (tol/4, tol/4 and tol/2, so that together they make up tol):
 
 * band limit: s sigma = t_b with erfc(t_b / sqrt 2) = tol / 4 (the largest deviation of the
   band-limited Gaussian from the Gaussian, at r = 0; see ``bandlimit``);
 * pruning radius: box pairs whose gap is at least R_cut = s sqrt(2 ln(4/tol) + 1) are
   dropped (their kernel values are below 0.61 tol / 4);
 * aliasing margin: the period L must exceed the largest coordinate distance R_far of a
-  kept far pair by s sqrt(2 ln(4/tol)), so that the periodic images of the band-limited
-  kernel are below tol / 4;
+  kept far pair by s sqrt(2 ln(2/tol)), so that the periodic images of the band-limited
+  kernel are below tol / 2 (the part of the tolerance the two budgets above leave);
 * coarse level: level l (cell width w = ext / 2^l) with stencil radius r = 1 + floor(R_cut/w)
   keeps every pair closer than R_cut and gives R_far = (r + 1) w.  The rule picks the level
   with the smallest R_far among l = 1 .. min(floor(log_{2^d}(n / n_max)), floor(18 / d)),
@@ -59,10 +59,15 @@ def band_t(tol: float) -> float:
     return hi
 
 
+def aliasing_margin(s: float, tol: float) -> float:
+    """s sqrt(2 ln(2/tol)): the Gaussian exp(-t^2 / (2 s^2)) is below tol / 2 from there on."""
+    return s * math.sqrt(2.0 * math.log(2.0 / tol))
+
+
 def gauss_params(s: float, tol: float, d: int, n: int, ext: float, n_max: int) -> Params:
     sigma = band_t(tol) / s
     rcut = s * math.sqrt(2.0 * math.log(4.0 / tol) + 1.0)
-    margin = s * math.sqrt(2.0 * math.log(4.0 / tol))
+    margin = aliasing_margin(s, tol)
     lmax = 0
     if n > n_max:
         lmax = int(math.floor(math.log(n / n_max) / math.log(2.0 ** d)))

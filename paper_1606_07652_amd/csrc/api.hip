@@ -130,7 +130,9 @@ int choose_params(rbf_plan *p, const rbf_opts *o) {
     const int d = p->d;
     p->sigma = (o && o->band > 0) ? o->band : band_limit_t(tol) / s;
     p->rcut = s * std::sqrt(2.0 * std::log(4.0 / tol) + 1.0);
-    const double margin = s * std::sqrt(2.0 * std::log(4.0 / tol));
+    // error budget: tol/4 for the band limit, tol/4 for the pruned pairs, tol/2 (the rest of the
+    // tolerance) for the periodic images of the kept pairs
+    const double margin = s * std::sqrt(2.0 * std::log(2.0 / tol));
     int lmax = 0;
     if (p->n > p->n_max) lmax = (int)std::floor(std::log((double)p->n / p->n_max) / std::log(std::pow(2.0, d)));
     lmax = std::max(0, std::min(lmax, 18 / d));

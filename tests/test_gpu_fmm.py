@@ -93,7 +93,7 @@ def test_plan_parameters_meet_the_error_budget(s, tol, n, d, nmax):
     inf = p.info()
     lo, ext = T.root_cube(x)
     pr = params.gauss_params(s, tol, d, n, ext, nmax)
-    margin = s * np.sqrt(2.0 * np.log(4.0 / tol))
+    margin = params.aliasing_margin(s, tol)
     if inf["far_field"] == 0:
         w = ext / 2 ** inf["coarse_level"]
         assert inf["coarse_level"] == params.near_only_level(s, tol, d, ext) and inf["coarse_radius"] == 1
