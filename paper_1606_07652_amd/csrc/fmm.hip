@@ -348,15 +348,16 @@ template <class T, int KER> __device__ __forceinline__ T kphi(T r2, T coef, cons
 // Band-limited Gaussian (section 3, eq. 16 with the box of eq. 28): Phi_sigma(x) = prod_k
 // phi(x_k), phi from the plan's table in global memory (kBlHead, then kBlDeg<T> + 1 monomial
 // coefficients in u = 2 v - 1 per piece, v the position in the piece); inv = pieces per unit t,
-// last = the last piece, which also takes |t| rounded past the box side.  A NaN difference
-// reads piece 0 and yields NaN.
+// last = the last piece, which also takes |t| rounded past the box side.  The piece position is
+// clamped before its conversion to an integer, so the index stays in the table for any input;
+// a NaN difference takes the last piece and yields NaN through u.
 // pieces: the first piece's coefficients, ST apart (the table in global memory past its head,
 // as doubles, or the direct kernel's LDS copy in T)
 template <class T, class P, int ST = kBlDeg<T> + 1>
 __device__ __forceinline__ T bl_axis(T t, T inv, int last, const P *__restrict__ pieces) {
     constexpr int DEG = kBlDeg<T>;
     const T s = fabs(t) * inv;
-    const int i = min((int)s, last);
+    const int i = min((int)min(s, (T)last), last);
     const T u = T(2) * (s - (T)i) - T(1);
     const P *c = pieces + i * ST;
     T y = (T)c[DEG];
