@@ -577,14 +577,15 @@ __device__ __forceinline__ void p2p_body(DescC<T> &d, T *__restrict__ u, int bid
     p2p_task<T, D, KER>(d, u, bid, tab);
 }
 
-// Exact product over all pairs (rows of targets per workgroup, all sources tiled).
+// Exact product over all pairs (rows of targets per workgroup, all sources tiled): targets
+// [dir_t0, n), sources [0, dir_ns) of the sorted points.
 template <class T, int D, int KER>
 __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int bid, char *smem_raw) {
     constexpr int DP = Pad<D>::v;
     __shared__ T sdat[kTile * DP];
     const T *__restrict__ xs = d.xs;
-    const int64_t n = d.n;
-    const int64_t ti = bid * (int64_t)kThreads + threadIdx.x;
+    const int64_t n = d.n, ns = d.dir_ns;
+    const int64_t ti = d.dir_t0 + bid * (int64_t)kThreads + threadIdx.x;
     const bool act = ti < n;
     T y[D];
 #pragma unroll
@@ -601,8 +602,8 @@ __device__ __forceinline__ void direct_body(DescC<T> &d, T *__restrict__ u, int 
                 bt[(j / (kBlDeg<T> + 1)) * kBlLds<T> + j % (kBlDeg<T> + 1)] = (T)d.res_tab[kBlHead + j];
     }
     T acc = 0;
-    for (int64_t base = 0; base < n; base += kTile) {
-        const int cnt = (int)min((int64_t)kTile, n - base);
+    for (int64_t base = 0; base < ns; base += kTile) {
+        const int cnt = (int)min((int64_t)kTile, ns - base);
         __syncthreads();
         if (threadIdx.x < cnt) {
 #pragma unroll
@@ -1628,12 +1629,21 @@ int direct_d(rbf_plan *p, const T *lam, T *u) {
     fill_desc<T>(p, &w.one);
     w.lam = lam;
     w.u = u;
-    const int64_t nb = phase_blocks<T>(w.one, PH_DIRECT);
+    const int64_t nb = phase_blocks<T>(w.one, PH_DIRECT);   // every point (the gather)
+    // A plan of one leaf for separate targets holds its sources first: the direct kernel then
+    // pairs the targets [n_src, n) with the sources [0, n_src) only.  Otherwise every point is a
+    // target and a source (an evaluation plan of several leaves interleaves them; its packed
+    // weights are zero at the targets).
+    if (p->n_src > 0 && p->nleaves == 1) {
+        w.one.dir_t0 = p->n_src;
+        w.one.dir_ns = p->n_src;
+    }
+    const int64_t nbd = (p->n - w.one.dir_t0 + kThreads - 1) / kThreads;
     // the band-limited Gaussian's table in the direct kernel's LDS (fill_desc sets bl_lds when
     // it fits in kBlLdsBytes)
     const size_t sh = w.one.bl_lds ? sizeof(T) * (size_t)p->bl_pieces * kBlLds<T> : 0;
     RBF_TRY((launch_phase<T, D, 4>(w, PH_GATHER, nb, p->stream, 0, 0, p->kernel)));
-    RBF_TRY((launch_phase<T, D, 4>(w, PH_DIRECT, nb, p->stream, 0, sh, p->kernel)));
+    RBF_TRY((launch_phase<T, D, 4>(w, PH_DIRECT, nbd, p->stream, 0, sh, p->kernel)));
     return RBF_OK;
 }
 
@@ -1942,6 +1952,8 @@ template <class T> void fill_desc(const rbf_plan *p, Desc<T> *d) {
     d->p2p_ctr = p->p2p_ctr;
     d->res_tab = nullptr;
     d->res_inv = d->res_cut2 = 0.0;
+    d->dir_t0 = 0;
+    d->dir_ns = p->n;
     d->bl_lds = 0;
     if (p->kernel == RBF_GAUSSIAN_BANDLIMITED) {
         // the per-axis table: pieces per unit t as coef, the last piece in res_cut2
@@ -1979,8 +1991,8 @@ template int launch_batch_group<double>(int, int, int, const Desc<double> *, int
 // A plan of one leaf without a far field (the autotuner's direct choice, the multiquadric) is the
 // exact sum over all pairs; the tiled direct kernel computes it faster than the near-field
 // kernel, whose waves would each stream the whole point set through scalar loads.  With
-// profiling the whole sum counts as the near field.  Plans for separate targets keep the
-// near-field kernel, which pairs targets with sources only.
+// profiling the whole sum counts as the near field.  A one-leaf plan for separate targets
+// takes it too, pairing its targets with its sources only (direct_d).
 int direct_product(rbf_plan *p, const void *lambda, void *u) {
     hipStream_t s = p->stream;
     if (p->profiling)
@@ -2000,7 +2012,7 @@ int launch_matvec_phases(rbf_plan *p, const void *lambda, void *u) {
 int launch_matvec(rbf_plan *p, const void *lambda, void *u) {
     if (!p->bands.empty())
         return p->dtype == RBF_F32 ? banded_matvec_t<float>(p, lambda, u) : banded_matvec_t<double>(p, lambda, u);
-    if (p->nleaves == 1 && !p->far && p->n_src == 0) return direct_product(p, lambda, u);
+    if (p->nleaves == 1 && !p->far) return direct_product(p, lambda, u);
     return launch_matvec_phases(p, lambda, u);
 }
 

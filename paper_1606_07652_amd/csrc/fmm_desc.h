@@ -55,6 +55,8 @@ template <class T> struct Desc {
     double res_inv;         // pieces per unit of b
     double res_cut2;        // r^2 from which the residual is zero (qmax)
     int *p2p_ctr;           // near-field work queue: per-XCD task counters, kCtrStride ints apart
+    int64_t dir_t0, dir_ns; // direct kernel: targets [dir_t0, n), sources [0, dir_ns) of the sorted
+                            // points (0 and n, or a one-leaf plan's separate targets and sources)
     int bl_lds;             // band-limited Gaussian: 1 = the direct kernel copies the table (pieces
                             // only, in T) into its dynamic LDS, which the launch sizes for it
 };
