@@ -72,8 +72,10 @@ enum { RBF_F32 = 0, RBF_F64 = 1 };
  *   tol phi_sigma(0) / (4 d) (floor 1e-14 phi_sigma(0)); products, evaluation and solves are
  *   exact sums over all pairs through the tiled direct kernel (one leaf): the box's sharp
  *   cut-off leaves tails decaying like 1/|t|, which a periodic frequency grid would alias.
+ *   Batch plans run each problem's exact sum through the near-field kernel (opts->band is the
+ *   bandwidth of every problem; autotune is ignored for them).
  *   RBF_EUNSUPPORTED: a table of more than 4096 pieces (min(sigma, 4 / s) times the box side
- *   above about 1600), batch plans, the autotuner, block-Jacobi and learned preconditioners.
+ *   above about 1600), the autotuner, block-Jacobi and learned preconditioners.
  *   The table costs host time growing with the square of that product: about 30 ms at 250
  *   pieces, about 15 s at the cap. */
 enum { RBF_GAUSSIAN = 0, RBF_MULTIQUADRIC = 1, RBF_INVERSE_MULTIQUADRIC = 2, RBF_WENDLAND = 3,

@@ -365,10 +365,6 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
             set_error("rbf_fmm_plan_batch: offsets must be strictly increasing from 0 (problem %d)", q);
             return RBF_EINVAL;
         }
-    if (kernel == RBF_GAUSSIAN_BANDLIMITED) {
-        set_error("rbf_fmm_plan_batch: the band-limited Gaussian has single plans only");
-        return RBF_EUNSUPPORTED;
-    }
     auto t0 = std::chrono::steady_clock::now();
     rbf_batch *b = new rbf_batch();
     b->nprob = nprob;
@@ -403,7 +399,8 @@ extern "C" int rbf_fmm_plan_batch(const void *points, const int64_t *offsets, in
         // a batch runs the per-phase kernels of one frequency grid per problem: the banded far
         // field of the multiquadric kernels is not batched, they take the exact sum
         if (banded_kernel(kernel, d)) o.exact = 1;
-        if (autotune) {
+        // the band-limited Gaussian has one plan shape (an exact sum over one leaf)
+        if (autotune && kernel != RBF_GAUSSIAN_BANDLIMITED) {
             double ms = 0;
             rc = autotune_impl(pq, nq, d, dtype, kernel, shapes[q], tol, &o, 2, b->stream, true, &o, &ms);
             if (rc != RBF_OK) break;
